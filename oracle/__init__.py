@@ -1,0 +1,179 @@
+"""Plain CPU oracle of the Genome-on-Diet sparsified-seeding hot path (arXiv 2211.08157).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the GPU library never does, and the two share no
+code (they meet only in the seeded inputs of ``datagen``).
+
+The arithmetic lives in ``godiet_oracle.c`` (plain C, one sequence at a time, every
+k-mer code and window minimum recomputed from its definition).  This module only builds
+that file with gcc, loads it with ctypes and marshals numpy arrays.
+
+Sequences are given as one base code per byte (A=0, C=1, G=2, T=3) with n_seq+1 offsets.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "godiet_oracle.c")
+_LIB = os.path.join(_HERE, "libgodiet_oracle.so")
+
+ECAP = -2
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, no intrinsics)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+        L.gdo_mix64.argtypes = [u64]
+        L.gdo_mix64.restype = u64
+        L.gdo_kept_count.argtypes = [u64, ctypes.c_char_p, u32]
+        L.gdo_kept_count.restype = u64
+        L.gdo_sparsify.argtypes = [P, P, u32, ctypes.c_char_p, P, P, P, P]
+        L.gdo_sparsify.restype = i64
+        L.gdo_sketch.argtypes = [P, P, u32, ctypes.c_char_p, P, i32, i32, P, P, P, u64]
+        L.gdo_sketch.restype = i64
+        L.gdo_index_build.argtypes = [P, P, u32, ctypes.c_char_p, i32, i32, i32, P, P, u64]
+        L.gdo_index_build.restype = i64
+        L.gdo_lookup.argtypes = [P, u64, P, u64, P, P]
+        L.gdo_lookup.restype = None
+        L.gdo_seed.argtypes = [P, P, u64, P, P, u32, ctypes.c_char_p, i32, i32, i32, u32, u32,
+                               P, u64, P, P]
+        L.gdo_seed.restype = i64
+        L.gdo_contain.argtypes = [P, P, u64, P, P, u32, ctypes.c_char_p, i32, i32, i32, u32, u32,
+                                  u32, P, P]
+        L.gdo_contain.restype = i64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _codes(codes, offsets):
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if codes.size and codes.max() > 3:
+        raise ValueError("base codes must be 0..3")
+    return codes, offsets
+
+
+def _check(r, what):
+    if r < 0:
+        raise RuntimeError("oracle %s failed with code %d" % (what, r))
+    return r
+
+
+def mix64(z):
+    return int(lib().gdo_mix64(int(z) & (2**64 - 1)))
+
+
+def kept_count(length, pattern, shift=0):
+    return int(lib().gdo_kept_count(int(length), pattern.encode(), int(shift)))
+
+
+def sparsify(codes, offsets, pattern, shifts=None):
+    """Returns (patterned codes, patterned offsets, original coordinate of each kept base)."""
+    codes, offsets = _codes(codes, offsets)
+    n_seq = offsets.size - 1
+    sh = None if shifts is None else np.ascontiguousarray(shifts, dtype=np.uint32)
+    out = np.zeros(max(codes.size, 1), np.uint8)
+    oofs = np.zeros(n_seq + 1, np.uint64)
+    orig = np.zeros(max(codes.size, 1), np.uint64)
+    n = _check(lib().gdo_sparsify(_ptr(codes), _ptr(offsets), n_seq, pattern.encode(), _ptr(sh),
+                                  _ptr(out), _ptr(oofs), _ptr(orig)), "sparsify")
+    return out[:n].copy(), oofs, orig[:n].copy()
+
+
+def sketch(codes, offsets, pattern, k, w, shifts=None):
+    """Minimizers of every sequence: (keys u64, vals u64 = pos<<1|strand, offsets[n_seq+1])."""
+    codes, offsets = _codes(codes, offsets)
+    n_seq = offsets.size - 1
+    sh = None if shifts is None else np.ascontiguousarray(shifts, dtype=np.uint32)
+    cap = max(codes.size, 1)
+    keys = np.zeros(cap, np.uint64)
+    vals = np.zeros(cap, np.uint64)
+    mz = np.zeros(n_seq + 1, np.uint64)
+    n = _check(lib().gdo_sketch(_ptr(codes), _ptr(offsets), n_seq, pattern.encode(), _ptr(sh),
+                                k, w, _ptr(keys), _ptr(vals), _ptr(mz), cap), "sketch")
+    return keys[:n].copy(), vals[:n].copy(), mz
+
+
+def index_build(codes, offsets, pattern, k, w, val_bits=32):
+    """Sorted seed index: (keys u64, vals u64) sorted by (key, val)."""
+    codes, offsets = _codes(codes, offsets)
+    n_seq = offsets.size - 1
+    cap = max(codes.size, 1)
+    keys = np.zeros(cap, np.uint64)
+    vals = np.zeros(cap, np.uint64)
+    n = _check(lib().gdo_index_build(_ptr(codes), _ptr(offsets), n_seq, pattern.encode(), k, w,
+                                     val_bits, _ptr(keys), _ptr(vals), cap), "index_build")
+    return keys[:n].copy(), vals[:n].copy()
+
+
+def lookup(keys, queries):
+    """(lb, occ) of every query in the sorted key array."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    q = np.ascontiguousarray(queries, dtype=np.uint64)
+    lb = np.zeros(q.size, np.uint64)
+    occ = np.zeros(q.size, np.uint64)
+    lib().gdo_lookup(_ptr(keys), keys.size, _ptr(q), q.size, _ptr(lb), _ptr(occ))
+    return lb, occ
+
+
+def seed(ikeys, ivals, codes, offsets, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0,
+         capacity=None):
+    """Pattern alignment + compressed seeding.  Returns (anchors (n,4) uint32 rows of
+    read_id, qpos, rpos, strand; read_off[n_reads+1]; shift[n_reads])."""
+    ikeys = np.ascontiguousarray(ikeys, dtype=np.uint64)
+    ivals = np.ascontiguousarray(ivals, dtype=np.uint64)
+    codes, offsets = _codes(codes, offsets)
+    n_reads = offsets.size - 1
+    cap = capacity if capacity is not None else max(1024, 4 * codes.size)
+    while True:
+        anchors = np.zeros((cap, 4), np.uint32)
+        roff = np.zeros(n_reads + 1, np.uint64)
+        shift = np.zeros(max(n_reads, 1), np.uint32)
+        n = lib().gdo_seed(_ptr(ikeys), _ptr(ivals), ikeys.size, _ptr(codes), _ptr(offsets),
+                           n_reads, pattern.encode(), k, w, shift_mode, align_t, max_occ,
+                           _ptr(anchors), cap, _ptr(roff), _ptr(shift))
+        if n == ECAP and capacity is None:
+            cap *= 4
+            continue
+        _check(n, "seed")
+        return anchors[:n].copy(), roff, shift[:n_reads].copy()
+
+
+def contain(ikeys, ivals, codes, offsets, pattern, k, w, n_genomes, shift_mode=-1, align_t=0,
+            max_occ=0):
+    """Per-genome shared distinct minimizer counts: (counts[n_genomes], sizes[n_genomes])."""
+    ikeys = np.ascontiguousarray(ikeys, dtype=np.uint64)
+    ivals = np.ascontiguousarray(ivals, dtype=np.uint64)
+    codes, offsets = _codes(codes, offsets)
+    counts = np.zeros(n_genomes, np.uint32)
+    sizes = np.zeros(n_genomes, np.uint32)
+    _check(lib().gdo_contain(_ptr(ikeys), _ptr(ivals), ikeys.size, _ptr(codes), _ptr(offsets),
+                             offsets.size - 1, pattern.encode(), k, w, shift_mode, align_t,
+                             max_occ, n_genomes, _ptr(counts), _ptr(sizes)), "contain")
+    return counts, sizes

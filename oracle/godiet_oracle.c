@@ -1,0 +1,424 @@
+/*
+ * godiet_oracle.c -- plain, slow CPU oracle of the sparsified-seeding hot path of
+ * Genome-on-Diet (Alser, Eudine, Mutlu: "Genome-on-Diet: Taming Large-Scale Genomic
+ * Analyses via Sparsified Genomics", arXiv 2211.08157).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no source, header, table or
+ * helper with the GPU library; the two meet only in the seeded synthetic inputs.
+ *
+ * Every routine follows the definition in the paper as directly as possible, with no
+ * blocking, fusion or reordering: sequences are handled one at a time, k-mer codes are
+ * recomputed from their k bases, window minima are recomputed from their w members.
+ *
+ * Inputs are bases as one code per byte (A=0, C=1, G=2, T=3) plus n_seq+1 offsets.
+ * Positions stored in minimizer records are coordinates of the ORIGINAL (unpatterned)
+ * sequence (Section 3.1, step 3).
+ *
+ * Readings of points the paper leaves open (each one is listed with its reason in the
+ * design notes of the repository):
+ *   - pattern phase for reads: base j is kept iff P[(j - a) mod p] == 1 (cyclic form of
+ *     the set {Q[i+a] * P[i mod p]} of Section 3);
+ *   - hash: splitmix64 finalizer of the canonical 2k-bit code (the paper uses Thomas
+ *     Wang's hash, Section 3.6.1; the workloads fix splitmix64);
+ *   - window ties: every k-mer attaining a window minimum is a minimizer;
+ *   - only full windows of w k-mers count; palindromic k-mers (fwd == rc) are never
+ *     minimizers and never lower a window minimum;
+ *   - pattern alignment scores the first n* = min_s |M_s| minimizers of every shift
+ *     (capped by t when t > 0), skips occurrences >= max_occ when max_occ > 0, and picks
+ *     the smallest shift of maximal score (0 when p == 1).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define GDO_OK 0
+#define GDO_EINVAL (-1)
+#define GDO_ECAP (-2)
+#define GDO_ENOMEM (-3)
+
+typedef struct {
+    int p;                    /* pattern length */
+    int x;                    /* weight = number of ones */
+    unsigned char bit[64];
+} gdo_pattern;
+
+static int parse_pattern(const char *s, gdo_pattern *P)
+{
+    if (!s) return GDO_EINVAL;
+    size_t n = strlen(s);
+    if (n < 1 || n > 64) return GDO_EINVAL;
+    P->p = (int)n;
+    P->x = 0;
+    for (size_t i = 0; i < n; i++) {
+        if (s[i] == '1') { P->bit[i] = 1; P->x++; }
+        else if (s[i] == '0') P->bit[i] = 0;
+        else return GDO_EINVAL;
+    }
+    return P->x >= 1 ? GDO_OK : GDO_EINVAL;
+}
+
+/* Section 3 and Section 3.1 steps (1)-(2): the user pattern is repeated along the
+ * sequence; with the pattern shifted right by a, base j is kept iff P[(j - a) mod p]. */
+static int is_kept(const gdo_pattern *P, uint64_t j, uint32_t a)
+{
+    uint64_t p = (uint64_t)P->p;
+    uint64_t t = (j % p + p - (a % p)) % p;
+    return P->bit[t];
+}
+
+/* splitmix64 finalizer (Steele, Lea, Flood 2014: the output function of SplitMix64). */
+uint64_t gdo_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Number of kept bases of a sequence of length L under shift a, counted by definition. */
+uint64_t gdo_kept_count(uint64_t L, const char *pattern, uint32_t a)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK) return UINT64_MAX;
+    uint64_t n = 0;
+    for (uint64_t j = 0; j < L; j++) n += is_kept(&P, j, a);
+    return n;
+}
+
+/* Sparsify every sequence of a batch (Section 3.1 (1)-(2)).  out_codes receives the kept
+ * bases of all sequences back to back, out_offsets[n_seq+1] their boundaries and, when
+ * non-NULL, out_orig the original in-sequence coordinate of every kept base.
+ * shifts may be NULL (all zero).  Returns the total number of kept bases. */
+int64_t gdo_sparsify(const uint8_t *codes, const uint64_t *offsets, uint32_t n_seq,
+                     const char *pattern, const uint32_t *shifts,
+                     uint8_t *out_codes, uint64_t *out_offsets, uint64_t *out_orig)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK) return GDO_EINVAL;
+    uint64_t n = 0;
+    out_offsets[0] = 0;
+    for (uint32_t s = 0; s < n_seq; s++) {
+        uint32_t a = shifts ? shifts[s] : 0;
+        if (a >= (uint32_t)P.p) return GDO_EINVAL;
+        for (uint64_t j = offsets[s]; j < offsets[s + 1]; j++) {
+            if (is_kept(&P, j - offsets[s], a)) {
+                out_codes[n] = codes[j];
+                if (out_orig) out_orig[n] = j - offsets[s];
+                n++;
+            }
+        }
+        out_offsets[s + 1] = n;
+    }
+    return (int64_t)n;
+}
+
+/* Minimizers of one sequence (Section 3.1 step (3) and its minimizer definition):
+ *   1. sparsify with shift a, remembering the original coordinate of each kept base;
+ *   2. for every k-mer of the patterned sequence: forward code (first base most
+ *      significant), reverse-complement code, canonical = smaller, strand = rc < fwd,
+ *      hash = mix64(canonical);
+ *   3. a k-mer is a minimizer iff its hash equals the minimum of some full window of w
+ *      consecutive k-mers containing it.
+ * Records are (key = hash, val = orig << 1 | strand) in ascending k-mer order.
+ * Returns the number of records, or GDO_ECAP if more than cap would be written. */
+static int64_t sketch_one(const uint8_t *S, uint64_t L, const gdo_pattern *P, uint32_t a,
+                          int k, int w, uint64_t *keys, uint64_t *vals, uint64_t cap)
+{
+    uint8_t *PS = (uint8_t *)malloc(L ? L : 1);
+    uint64_t *orig = (uint64_t *)malloc((L ? L : 1) * sizeof(uint64_t));
+    if (!PS || !orig) { free(PS); free(orig); return GDO_ENOMEM; }
+    uint64_t n = 0;
+    for (uint64_t j = 0; j < L; j++)
+        if (is_kept(P, j, a)) { PS[n] = S[j]; orig[n] = j; n++; }
+
+    int64_t out = 0;
+    if (n >= (uint64_t)k && n - (uint64_t)k + 1 >= (uint64_t)w) {
+        uint64_t nk = n - (uint64_t)k + 1;
+        uint64_t *h = (uint64_t *)malloc(nk * sizeof(uint64_t));
+        uint8_t *ok = (uint8_t *)malloc(nk);
+        uint8_t *strand = (uint8_t *)malloc(nk);
+        uint64_t nwin = nk - (uint64_t)w + 1;
+        uint64_t *wmin = (uint64_t *)malloc(nwin * sizeof(uint64_t));
+        uint8_t *wany = (uint8_t *)malloc(nwin);
+        if (!h || !ok || !strand || !wmin || !wany) {
+            free(h); free(ok); free(strand); free(wmin); free(wany); free(PS); free(orig);
+            return GDO_ENOMEM;
+        }
+        for (uint64_t i = 0; i < nk; i++) {
+            uint64_t fwd = 0, rc = 0;
+            for (int t = 0; t < k; t++) fwd = fwd * 4 + PS[i + t];
+            for (int t = 0; t < k; t++) rc = rc * 4 + (uint64_t)(3 - PS[i + (uint64_t)k - 1 - t]);
+            if (fwd == rc) { ok[i] = 0; h[i] = 0; strand[i] = 0; continue; }
+            ok[i] = 1;
+            strand[i] = rc < fwd ? 1 : 0;
+            h[i] = gdo_mix64(rc < fwd ? rc : fwd);
+        }
+        for (uint64_t s = 0; s < nwin; s++) {
+            wany[s] = 0;
+            wmin[s] = 0;
+            for (uint64_t t = s; t < s + (uint64_t)w; t++) {
+                if (!ok[t]) continue;
+                if (!wany[s] || h[t] < wmin[s]) wmin[s] = h[t];
+                wany[s] = 1;
+            }
+        }
+        for (uint64_t i = 0; i < nk; i++) {
+            if (!ok[i]) continue;
+            uint64_t s_lo = i + 1 >= (uint64_t)w ? i + 1 - (uint64_t)w : 0;
+            uint64_t s_hi = i < nwin - 1 ? i : nwin - 1;
+            int sel = 0;
+            for (uint64_t s = s_lo; s <= s_hi; s++)
+                if (wany[s] && h[i] == wmin[s]) { sel = 1; break; }
+            if (!sel) continue;
+            if ((uint64_t)out >= cap) { out = GDO_ECAP; break; }
+            keys[out] = h[i];
+            vals[out] = (orig[i] << 1) | strand[i];
+            out++;
+        }
+        free(h); free(ok); free(strand); free(wmin); free(wany);
+    }
+    free(PS);
+    free(orig);
+    return out;
+}
+
+/* Minimizers of every sequence of a batch.  vals hold orig << 1 | strand in the
+ * sequence's own coordinates; mz_offsets[n_seq+1] delimit each sequence's records.
+ * Returns the total, GDO_ECAP when cap is too small, GDO_EINVAL on bad arguments. */
+int64_t gdo_sketch(const uint8_t *codes, const uint64_t *offsets, uint32_t n_seq,
+                   const char *pattern, const uint32_t *shifts, int k, int w,
+                   uint64_t *keys, uint64_t *vals, uint64_t *mz_offsets, uint64_t cap)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK || k < 1 || k > 32 || w < 1) return GDO_EINVAL;
+    uint64_t n = 0;
+    mz_offsets[0] = 0;
+    for (uint32_t s = 0; s < n_seq; s++) {
+        uint32_t a = shifts ? shifts[s] : 0;
+        if (a >= (uint32_t)P.p) return GDO_EINVAL;
+        int64_t r = sketch_one(codes + offsets[s], offsets[s + 1] - offsets[s], &P, a, k, w,
+                               keys + n, vals + n, cap - n);
+        if (r < 0) return r;
+        n += (uint64_t)r;
+        mz_offsets[s + 1] = n;
+    }
+    return (int64_t)n;
+}
+
+typedef struct { uint64_t key, val; } gdo_rec;
+
+static int rec_cmp(const void *pa, const void *pb)
+{
+    const gdo_rec *a = (const gdo_rec *)pa, *b = (const gdo_rec *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->val != b->val) return a->val < b->val ? -1 : 1;
+    return 0;
+}
+
+/* Seed index (Section 3.1 step (3)): all minimizer records of the reference, appended to
+ * one array and sorted by (hash, location).  val_bits == 32: val = global position in the
+ * concatenated batch << 1 | strand; val_bits == 64: val = sequence id << 32 |
+ * position << 1 | strand.  Returns the number of records. */
+int64_t gdo_index_build(const uint8_t *codes, const uint64_t *offsets, uint32_t n_seq,
+                        const char *pattern, int k, int w, int val_bits,
+                        uint64_t *keys, uint64_t *vals, uint64_t cap)
+{
+    if (val_bits != 32 && val_bits != 64) return GDO_EINVAL;
+    uint64_t *mz = (uint64_t *)malloc(((uint64_t)n_seq + 1) * sizeof(uint64_t));
+    if (!mz) return GDO_ENOMEM;
+    int64_t n = gdo_sketch(codes, offsets, n_seq, pattern, NULL, k, w, keys, vals, mz, cap);
+    if (n < 0) { free(mz); return n; }
+    gdo_rec *r = (gdo_rec *)malloc(((uint64_t)n + 1) * sizeof(gdo_rec));
+    if (!r) { free(mz); return GDO_ENOMEM; }
+    for (uint32_t s = 0; s < n_seq; s++) {
+        for (uint64_t i = mz[s]; i < mz[s + 1]; i++) {
+            uint64_t pos = vals[i] >> 1, strand = vals[i] & 1;
+            r[i].key = keys[i];
+            if (val_bits == 32) r[i].val = ((offsets[s] + pos) << 1) | strand;
+            else r[i].val = ((uint64_t)s << 32) | (pos << 1) | strand;
+        }
+    }
+    qsort(r, (size_t)n, sizeof(gdo_rec), rec_cmp);
+    for (int64_t i = 0; i < n; i++) { keys[i] = r[i].key; vals[i] = r[i].val; }
+    free(r);
+    free(mz);
+    return n;
+}
+
+/* Exact-match lookup: lb = first i with keys[i] >= q, ub = first i with keys[i] > q. */
+static uint64_t lower_bound(const uint64_t *keys, uint64_t n, uint64_t q)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < q) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static uint64_t upper_bound(const uint64_t *keys, uint64_t n, uint64_t q)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] <= q) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+void gdo_lookup(const uint64_t *keys, uint64_t n, const uint64_t *q, uint64_t m,
+                uint64_t *lb, uint64_t *occ)
+{
+    for (uint64_t i = 0; i < m; i++) {
+        uint64_t l = lower_bound(keys, n, q[i]);
+        lb[i] = l;
+        occ[i] = upper_bound(keys, n, q[i]) - l;
+    }
+}
+
+/* Pattern alignment (Section 3.2) for one read: returns the alignment index a. */
+static int64_t align_read(const uint8_t *S, uint64_t L, const gdo_pattern *P, int k, int w,
+                          const uint64_t *ikeys, uint64_t in, uint32_t t, uint32_t max_occ)
+{
+    if (P->p == 1) return 0;
+    uint64_t **mk = (uint64_t **)calloc((size_t)P->p, sizeof(uint64_t *));
+    uint64_t **mv = (uint64_t **)calloc((size_t)P->p, sizeof(uint64_t *));
+    int64_t *cnt = (int64_t *)calloc((size_t)P->p, sizeof(int64_t));
+    if (!mk || !mv || !cnt) { free(mk); free(mv); free(cnt); return GDO_ENOMEM; }
+    int64_t status = 0;
+    uint64_t cap = L + 1;
+    for (int s = 0; s < P->p && status == 0; s++) {
+        mk[s] = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        mv[s] = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        if (!mk[s] || !mv[s]) { status = GDO_ENOMEM; break; }
+        cnt[s] = sketch_one(S, L, P, (uint32_t)s, k, w, mk[s], mv[s], cap);
+        if (cnt[s] < 0) status = cnt[s];
+    }
+    int64_t best = 0;
+    if (status == 0) {
+        uint64_t nstar = (uint64_t)cnt[0];
+        for (int s = 1; s < P->p; s++) if ((uint64_t)cnt[s] < nstar) nstar = (uint64_t)cnt[s];
+        if (t > 0 && (uint64_t)t < nstar) nstar = t;
+        uint64_t best_score = 0;
+        for (int s = 0; s < P->p; s++) {
+            uint64_t score = 0;
+            for (uint64_t j = 0; j < nstar; j++) {
+                uint64_t occ = upper_bound(ikeys, in, mk[s][j]) - lower_bound(ikeys, in, mk[s][j]);
+                if (max_occ == 0 || occ < max_occ) score += occ;
+            }
+            if (score > best_score) { best_score = score; best = s; }
+        }
+    }
+    for (int s = 0; s < P->p; s++) { free(mk[s]); free(mv[s]); }
+    free(mk); free(mv); free(cnt);
+    return status ? status : best;
+}
+
+/* Pattern alignment + compressed seeding (Sections 3.2, 3.3) over a batch of reads.
+ * Index: sorted keys[in], vals[in] with val = global reference position << 1 | strand.
+ * shift_mode < 0 runs pattern alignment; shift_mode >= 0 forces that shift.
+ * For every read r (in order), every minimizer of the read at its shift a (ascending
+ * k-mer order), unless max_occ > 0 and its occurrence count >= max_occ, and every index
+ * entry e with the same hash (ascending), one anchor
+ *     (read_id = r, qpos = read position, rpos = vals[e] >> 1, strand = (qval ^ vals[e]) & 1)
+ * is written as four uint32.  read_off[n_reads+1] delimits each read's anchors and
+ * shift_out[n_reads] receives a.  Returns the number of anchors or GDO_ECAP. */
+int64_t gdo_seed(const uint64_t *ikeys, const uint64_t *ivals, uint64_t in,
+                 const uint8_t *codes, const uint64_t *offsets, uint32_t n_reads,
+                 const char *pattern, int k, int w, int shift_mode, uint32_t t, uint32_t max_occ,
+                 uint32_t *anchors, uint64_t cap, uint64_t *read_off, uint32_t *shift_out)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK || k < 1 || k > 32 || w < 1) return GDO_EINVAL;
+    if (shift_mode >= P.p) return GDO_EINVAL;
+    uint64_t n = 0;
+    read_off[0] = 0;
+    int64_t status = 0;
+    for (uint32_t r = 0; r < n_reads && status == 0; r++) {
+        const uint8_t *S = codes + offsets[r];
+        uint64_t L = offsets[r + 1] - offsets[r];
+        int64_t a = shift_mode >= 0 ? shift_mode
+                                    : align_read(S, L, &P, k, w, ikeys, in, t, max_occ);
+        if (a < 0) { status = a; break; }
+        if (shift_out) shift_out[r] = (uint32_t)a;
+        uint64_t *mk = (uint64_t *)malloc((L + 1) * sizeof(uint64_t));
+        uint64_t *mv = (uint64_t *)malloc((L + 1) * sizeof(uint64_t));
+        if (!mk || !mv) { free(mk); free(mv); status = GDO_ENOMEM; break; }
+        int64_t m = sketch_one(S, L, &P, (uint32_t)a, k, w, mk, mv, L + 1);
+        if (m < 0) status = m;
+        for (int64_t j = 0; j < m && status == 0; j++) {
+            uint64_t lb = lower_bound(ikeys, in, mk[j]);
+            uint64_t ub = upper_bound(ikeys, in, mk[j]);
+            if (max_occ > 0 && ub - lb >= max_occ) continue;
+            for (uint64_t e = lb; e < ub; e++) {
+                if (n >= cap) { status = GDO_ECAP; break; }
+                anchors[4 * n + 0] = r;
+                anchors[4 * n + 1] = (uint32_t)(mv[j] >> 1);
+                anchors[4 * n + 2] = (uint32_t)(ivals[e] >> 1);
+                anchors[4 * n + 3] = (uint32_t)((mv[j] ^ ivals[e]) & 1);
+                n++;
+            }
+        }
+        free(mk);
+        free(mv);
+        read_off[r + 1] = n;
+    }
+    return status ? status : (int64_t)n;
+}
+
+static int u64_cmp(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Containment-style counts (the k-mer-set intersection of Section 2.2): H_sample is the
+ * set of hashes of all reads' minimizers at their aligned shift; for genome g, H_g is the
+ * set of hashes among index records whose val >> 32 == g (val_bits 64);
+ * counts[g] = |H_sample intersect H_g| and sizes[g] = |H_g|. */
+int64_t gdo_contain(const uint64_t *ikeys, const uint64_t *ivals, uint64_t in,
+                    const uint8_t *codes, const uint64_t *offsets, uint32_t n_reads,
+                    const char *pattern, int k, int w, int shift_mode, uint32_t t,
+                    uint32_t max_occ, uint32_t n_genomes, uint32_t *counts, uint32_t *sizes)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK || k < 1 || k > 32 || w < 1) return GDO_EINVAL;
+    if (shift_mode >= P.p) return GDO_EINVAL;
+    uint64_t cap = offsets[n_reads] + 1;
+    uint64_t *sample = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    uint64_t *tmpv = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    if (!sample || !tmpv) { free(sample); free(tmpv); return GDO_ENOMEM; }
+    uint64_t ns = 0;
+    for (uint32_t r = 0; r < n_reads; r++) {
+        const uint8_t *S = codes + offsets[r];
+        uint64_t L = offsets[r + 1] - offsets[r];
+        int64_t a = shift_mode >= 0 ? shift_mode
+                                    : align_read(S, L, &P, k, w, ikeys, in, t, max_occ);
+        if (a < 0) { free(sample); free(tmpv); return a; }
+        int64_t m = sketch_one(S, L, &P, (uint32_t)a, k, w, sample + ns, tmpv, cap - ns);
+        if (m < 0) { free(sample); free(tmpv); return m; }
+        ns += (uint64_t)m;
+    }
+    free(tmpv);
+    qsort(sample, (size_t)ns, sizeof(uint64_t), u64_cmp);
+    uint64_t nu = 0;
+    for (uint64_t i = 0; i < ns; i++)
+        if (nu == 0 || sample[nu - 1] != sample[i]) sample[nu++] = sample[i];
+
+    for (uint32_t g = 0; g < n_genomes; g++) { counts[g] = 0; sizes[g] = 0; }
+    /* pairs (genome, hash), sorted, then distinct pairs counted */
+    gdo_rec *gh = (gdo_rec *)malloc((in + 1) * sizeof(gdo_rec));
+    if (!gh) { free(sample); return GDO_ENOMEM; }
+    for (uint64_t i = 0; i < in; i++) { gh[i].key = ivals[i] >> 32; gh[i].val = ikeys[i]; }
+    qsort(gh, (size_t)in, sizeof(gdo_rec), rec_cmp);
+    for (uint64_t i = 0; i < in; i++) {
+        if (i > 0 && gh[i].key == gh[i - 1].key && gh[i].val == gh[i - 1].val) continue;
+        uint64_t g = gh[i].key;
+        if (g >= n_genomes) { free(gh); free(sample); return GDO_EINVAL; }
+        sizes[g]++;
+        if (bsearch(&gh[i].val, sample, (size_t)nu, sizeof(uint64_t), u64_cmp)) counts[g]++;
+    }
+    free(gh);
+    free(sample);
+    return (int64_t)nu;
+}

@@ -1,0 +1,366 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+published generator outputs, hand-worked examples, closed forms, brute-force
+enumeration (tests/brute.py), library routines (numpy sort/searchsorted, Python sets)
+and invariants of the definitions (window coverage, the opening identity, strand
+symmetry, the expected minimizer density, recovery of the true pattern phase)."""
+import os
+
+import numpy as np
+import pytest
+
+import brute
+import datagen
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+GAMMA = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+BASES = {"A": 0, "C": 1, "G": 2, "T": 3}
+
+
+def codes_of(text):
+    return np.array([BASES[c] for c in text], np.uint8)
+
+
+def one(seq):
+    return np.array([0, len(seq)], np.uint64)
+
+
+# ---------------------------------------------------------------- hash (splitmix64)
+
+def published_vectors():
+    out = []
+    with open(os.path.join(GOLD, "splitmix64_published.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            seed = int(parts[0], 0)
+            out.append((seed, [int(v, 0) for v in parts[1:]]))
+    return out
+
+
+def test_mix64_matches_published_splitmix64():
+    for seed, outs in published_vectors():
+        state = seed
+        for expected in outs:
+            state = (state + GAMMA) & M64
+            assert oracle.mix64(state) == expected
+            assert brute.mix64(state) == expected
+
+
+def test_mix64_zero_is_fixed_point():
+    # every shift-xor and multiply maps 0 to 0: poly-A k-mers always hash to 0
+    assert oracle.mix64(0) == 0
+
+
+# ---------------------------------------------------------------- sparsification
+
+def closed_form_kept(L, pattern, a):
+    p, x = len(pattern), pattern.count("1")
+    rem = sum(1 for t in range(L % p) if pattern[(t - a) % p] == "1")
+    return (L // p) * x + rem
+
+
+@pytest.mark.parametrize("pattern", ["1", "10", "110", "101", "100", "1110", "11100",
+                                     "101001", "1001010011", "0001"])
+def test_kept_count_closed_form(pattern):
+    for L in list(range(0, 40)) + [1000, 1001, 123457]:
+        for a in range(len(pattern)):
+            assert oracle.kept_count(L, pattern, a) == closed_form_kept(L, pattern, a)
+
+
+def test_ceil_form_on_leading_ones_patterns():
+    # sparsified length = ceil(L * x / p) holds at shift 0 when the pattern's ones
+    # come first; it fails in general ('101' at L = 2 keeps 1 base, ceil gives 2)
+    for pattern in ["10", "110", "100", "1110", "1"]:
+        p, x = len(pattern), pattern.count("1")
+        for L in range(0, 200):
+            assert oracle.kept_count(L, pattern, 0) == -(-L * x // p)
+    assert oracle.kept_count(2, "101", 0) == 1
+
+
+def test_sparsify_10_is_every_other_base():
+    rng = np.random.default_rng(7)
+    s = rng.integers(0, 4, 1001, dtype=np.uint8)
+    pc, po, orig = oracle.sparsify(s, one(s), "10")
+    assert np.array_equal(pc, s[0::2])
+    assert np.array_equal(orig, np.arange(0, 1001, 2))
+    pc1, _, orig1 = oracle.sparsify(s, one(s), "10", shifts=[1])
+    assert np.array_equal(pc1, s[1::2])
+    assert np.array_equal(orig1, np.arange(1, 1001, 2))
+
+
+def test_sparsify_batch_restarts_phase_per_sequence():
+    rng = np.random.default_rng(8)
+    lens = [5, 0, 7, 3, 12]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    s = rng.integers(0, 4, offs[-1], dtype=np.uint8)
+    shifts = [0, 1, 2, 1, 0]
+    pc, po, orig = oracle.sparsify(s, offs, "110", shifts=shifts)
+    expect = []
+    for i, L in enumerate(lens):
+        kp = brute.kept_positions(L, "110", shifts[i])
+        expect += [int(s[offs[i] + j]) for j in kp]
+        assert po[i + 1] - po[i] == len(kp)
+    assert pc.tolist() == expect
+
+
+# ---------------------------------------------------------------- minimizers
+
+def load_hand_cases():
+    cases = []
+    with open(os.path.join(GOLD, "hand_minimizers.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            lhs, rhs = line.split("|")
+            seq, pat, shift, k, w = lhs.split()
+            recs = []
+            for tok in rhs.split():
+                hc, val = tok.split(":")
+                c = int(hc[2:-1])
+                recs.append((brute.mix64(c), int(val)))
+            cases.append((seq, pat, int(shift), int(k), int(w), recs))
+    return cases
+
+
+@pytest.mark.parametrize("case", load_hand_cases(), ids=lambda c: "%s-%s-%d" % c[:3])
+def test_hand_worked_examples(case):
+    seq, pat, shift, k, w, recs = case
+    s = codes_of(seq)
+    keys, vals, mz = oracle.sketch(s, one(s), pat, k, w, shifts=[shift])
+    assert list(zip(keys.tolist(), vals.tolist())) == recs
+    assert mz.tolist() == [0, len(recs)]
+
+
+SWEEP = [("1", 1, 1), ("10", 3, 2), ("110", 4, 3), ("101", 5, 4), ("100", 2, 5), ("1110", 8, 10),
+         ("11100", 15, 11), ("101001", 21, 5), ("1001010011", 28, 2), ("1", 32, 40), ("10", 1, 2),
+         ("110", 2, 1), ("1", 4, 7), ("10", 6, 3), ("1101", 11, 11)]
+
+
+@pytest.mark.parametrize("pattern,k,w", SWEEP)
+def test_sketch_matches_brute_force(pattern, k, w):
+    rng = np.random.default_rng(hash((pattern, k, w)) & 0xFFFF)
+    for trial in range(6):
+        L = int(rng.integers(0, 260))
+        if trial == 0:
+            s = np.zeros(L, np.uint8)                  # poly-A: hash-0 ties everywhere
+        elif trial == 1:
+            s = np.tile(np.array([0, 3], np.uint8), L // 2 + 1)[:L]   # ATAT...: palindromes
+        elif trial == 2:
+            s = np.tile(rng.integers(0, 4, 3, dtype=np.uint8), L // 3 + 1)[:L]
+        else:
+            s = rng.integers(0, 4, L, dtype=np.uint8)
+        for a in range(len(pattern)):
+            keys, vals, mz = oracle.sketch(s, one(s), pattern, k, w, shifts=[a])
+            got = list(zip(keys.tolist(), vals.tolist()))
+            assert got == brute.sketch(s.tolist(), pattern, a, k, w), (pattern, k, w, a, L)
+
+
+def test_sketch_batch_equals_per_sequence():
+    rng = np.random.default_rng(11)
+    lens = [0, 1, 30, 31, 200, 5, 64]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    s = rng.integers(0, 4, offs[-1], dtype=np.uint8)
+    shifts = [i % 3 for i in range(len(lens))]
+    keys, vals, mz = oracle.sketch(s, offs, "110", 5, 4, shifts=shifts)
+    for i in range(len(lens)):
+        seg = s[offs[i]:offs[i + 1]]
+        exp = brute.sketch(seg.tolist(), "110", shifts[i], 5, 4)
+        got = list(zip(keys[mz[i]:mz[i + 1]].tolist(), vals[mz[i]:mz[i + 1]].tolist()))
+        assert got == exp
+
+
+def _patterned_hashes(s, pattern, a, k):
+    """Hashes of all patterned k-mers computed by brute force (None for palindromes)."""
+    kept = brute.kept_positions(len(s), pattern, a)
+    ps = [int(s[j]) for j in kept]
+    hs = []
+    for i in range(len(ps) - k + 1):
+        f = brute.numeral(ps[i:i + k])
+        r = brute.numeral([3 - b for b in reversed(ps[i:i + k])])
+        hs.append(None if f == r else brute.mix64(min(f, r)))
+    return kept, hs
+
+
+@pytest.mark.parametrize("pattern,k,w", [("10", 15, 10), ("110", 7, 5), ("1", 5, 11)])
+def test_window_coverage_and_opening_identity(pattern, k, w):
+    rng = np.random.default_rng(12)
+    s = rng.integers(0, 4, 3000, dtype=np.uint8)
+    keys, vals, _ = oracle.sketch(s, one(s), pattern, k, w)
+    kept, hs = _patterned_hashes(s, pattern, 0, k)
+    pos_to_i = {o: i for i, o in enumerate(kept)}
+    sel = {pos_to_i[int(v) >> 1] for v in vals}
+    n = len(hs)
+    # coverage: every full window's minimum is attained by a selected k-mer
+    for st in range(n - w + 1):
+        m = min(h for h in hs[st:st + w] if h is not None)
+        assert any(hs[i] == m and i in sel for i in range(st, st + w))
+    # opening: selected  <=>  hash equals the max over containing windows of their minima
+    for i in range(n):
+        if hs[i] is None:
+            assert i not in sel
+            continue
+        wins = range(max(0, i - w + 1), min(i, n - w) + 1)
+        opened = max(min(h for h in hs[st:st + w] if h is not None) for st in wins)
+        assert (hs[i] == opened) == (i in sel)
+
+
+@pytest.mark.parametrize("pattern,L", [("1", 2000), ("10", 2001)])
+def test_strand_symmetry(pattern, L):
+    # with '1' (or '10' on odd L) the kept set maps onto itself under reversal, so the
+    # sketch of the reverse complement is the mirror image with flipped strands
+    rng = np.random.default_rng(13)
+    s = rng.integers(0, 4, L, dtype=np.uint8)
+    k, w = 15, 10
+    rcs = datagen.revcomp(s)
+    k1, v1, _ = oracle.sketch(s, one(s), pattern, k, w)
+    k2, v2, _ = oracle.sketch(rcs, one(rcs), pattern, k, w)
+    span = (k - 1) * len(pattern) + 1
+    mirrored = sorted(((int(kk), ((L - span - (int(v) >> 1)) << 1) | (1 - (int(v) & 1)))
+                       for kk, v in zip(k1, v1)), key=lambda t: t[1])
+    assert mirrored == list(zip(k2.tolist(), v2.tolist()))
+
+
+def test_density_and_sparsified_index_size():
+    s = datagen.random_genome(1_000_000, 1)
+    k, w = 15, 10
+    keys, _, _ = oracle.sketch(s, one(s), "10", k, w)
+    nk = 500_000 - k + 1
+    assert abs(keys.size / (nk * 2.0 / (w + 1)) - 1.0) < 0.02
+    full, _, _ = oracle.sketch(s, one(s), "1", k, w)
+    # the index shrinks by about the pattern's weight ratio x/p
+    assert abs(keys.size / full.size - 0.5) < 0.02
+
+
+# ---------------------------------------------------------------- index and lookup
+
+@pytest.mark.parametrize("val_bits", [32, 64])
+def test_index_is_sorted_sketch(val_bits):
+    rng = np.random.default_rng(14)
+    lens = [5000, 0, 17, 3000, 1]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    s = rng.integers(0, 4, offs[-1], dtype=np.uint8)
+    s[100:400] = s[2000:2300]          # a repeat, so equal keys occur
+    ik, iv = oracle.index_build(s, offs, "10", 9, 5, val_bits=val_bits)
+    keys, vals, mz = oracle.sketch(s, offs, "10", 9, 5)
+    seq = np.repeat(np.arange(len(lens)), np.diff(mz.astype(np.int64)))
+    pos, strand = vals >> np.uint64(1), vals & np.uint64(1)
+    if val_bits == 32:
+        gv = ((offs[seq] + pos) << np.uint64(1)) | strand
+    else:
+        gv = (seq.astype(np.uint64) << np.uint64(32)) | vals
+    order = np.lexsort((gv, keys))
+    assert np.array_equal(ik, keys[order]) and np.array_equal(iv, gv[order])
+    assert len(np.unique(ik)) < len(ik)
+
+
+def test_lookup_matches_searchsorted():
+    rng = np.random.default_rng(15)
+    keys = np.sort(rng.integers(0, 1000, 5000).astype(np.uint64))
+    q = np.concatenate([rng.integers(0, 1100, 3000).astype(np.uint64),
+                        np.array([0, 999, 1000, 2**64 - 1], np.uint64)])
+    lb, occ = oracle.lookup(keys, q)
+    assert np.array_equal(lb, np.searchsorted(keys, q, "left"))
+    assert np.array_equal(occ, np.searchsorted(keys, q, "right") - np.searchsorted(keys, q, "left"))
+    e_lb, e_occ = oracle.lookup(np.zeros(0, np.uint64), q[:3])
+    assert e_lb.tolist() == [0, 0, 0] and e_occ.tolist() == [0, 0, 0]
+
+
+# ---------------------------------------------------------------- pattern alignment, seeding
+
+@pytest.mark.parametrize("pattern,k,w,t,max_occ", [("10", 7, 4, 0, 0), ("110", 5, 3, 0, 0),
+                                                     ("101", 6, 2, 3, 0), ("1", 5, 3, 0, 0),
+                                                     ("100", 4, 2, 0, 3), ("10", 4, 3, 2, 2)])
+def test_seed_matches_brute_force(pattern, k, w, t, max_occ):
+    rng = np.random.default_rng(16)
+    ref = rng.integers(0, 4, 600, dtype=np.uint8)
+    ref[300:360] = ref[50:110]
+    ik, iv = oracle.index_build(ref, one(ref), pattern, k, w)
+    index = list(zip(ik.tolist(), iv.tolist()))
+    reads, lens = [], [40, 0, 3, 77, 25, 60]
+    for L in lens:
+        st = int(rng.integers(0, 600 - L))
+        r = ref[st:st + L].copy()
+        if L > 10:
+            r[5] = (r[5] + 1) % 4
+        if rng.integers(0, 2):
+            r = datagen.revcomp(r)
+        reads.append(r)
+    reads.append(rng.integers(0, 4, 50, dtype=np.uint8))
+    offs = np.concatenate([[0], np.cumsum([len(r) for r in reads])]).astype(np.uint64)
+    codes = np.concatenate(reads)
+    for mode in (-1, 0, len(pattern) - 1):
+        a, roff, sh = oracle.seed(ik, iv, codes, offs, pattern, k, w, shift_mode=mode,
+                                  align_t=t, max_occ=max_occ)
+        exp, exp_sh = brute.seed(index, [r.tolist() for r in reads], pattern, k, w,
+                                 shift_mode=mode, t=t, max_occ=max_occ)
+        assert [tuple(x) for x in a.tolist()] == exp
+        assert sh.tolist() == exp_sh
+        assert roff[-1] == len(exp)
+        # anchors are in lexicographic (read, qpos, rpos, strand) order by construction
+        assert [tuple(x) for x in a.tolist()] == sorted(exp)
+
+
+def test_pattern_alignment_recovers_true_phase_and_anchor():
+    # error-free reads of an i.i.d. reference: the chosen shift is the read's true phase
+    # and every read minimizer hits its true location (forward: rpos = g + qpos;
+    # reverse: rpos = g + L - qpos - span, strand 1)
+    ref = datagen.random_genome(200_000, 21)
+    k, w, L = 15, 10, 150
+    for pattern in ["10", "110", "100"]:
+        p = len(pattern)
+        # reflection centre c of the pattern: P[t] == P[(c - t) mod p] for every t; a
+        # reverse-strand read from g then carries the phase a = g + L - 1 - c (mod p)
+        c = [c for c in range(p) if all(pattern[t] == pattern[(c - t) % p] for t in range(p))][0]
+        ik, iv = oracle.index_build(ref, one(ref), pattern, k, w)
+        codes, offs, st, sd = datagen.fixed_reads(ref, 60, L, 22, sub=0.0)
+        anchors, roff, sh = oracle.seed(ik, iv, codes, offs, pattern, k, w)
+        for r in range(60):
+            g, strand = int(st[r]), int(sd[r])
+            true_a = (-g) % p if strand == 0 else (g + L - 1 - c) % p
+            assert sh[r] == true_a, (pattern, r)
+            read = codes[offs[r]:offs[r + 1]]
+            mk, mv, _ = oracle.sketch(read, one(read), pattern, k, w, shifts=[true_a])
+            kept = brute.kept_positions(L, pattern, true_a)
+            rows = anchors[roff[r]:roff[r + 1]]
+            hits = {(int(q), int(rp), int(s)) for _, q, rp, s in rows}
+            assert mv.size > 0
+            for v in mv.tolist():
+                q = v >> 1
+                i = kept.index(q)
+                span = kept[i + k - 1] - q + 1
+                rp = g + q if strand == 0 else g + L - q - span
+                assert (q, rp, strand) in hits
+
+
+def test_pattern_alignment_tie_and_no_hit_rules():
+    # no read minimizer in the index: all scores 0, shift 0
+    ref = datagen.random_genome(5000, 31)
+    ik, iv = oracle.index_build(ref, one(ref), "110", 11, 5)
+    other = datagen.random_genome(300, 32)
+    _, _, sh = oracle.seed(ik, iv, other, one(other), "110", 11, 5)
+    assert sh.tolist() == [0]
+
+
+# ---------------------------------------------------------------- containment
+
+def test_contain_matches_python_sets():
+    rng = np.random.default_rng(17)
+    lens = [3000, 2000, 4000]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    db = rng.integers(0, 4, offs[-1], dtype=np.uint8)
+    db[offs[1] + 100:offs[1] + 700] = db[200:800]     # genome 1 shares a block with 0
+    k, w, pat = 9, 5, "10"
+    ik, iv = oracle.index_build(db, offs, pat, k, w, val_bits=64)
+    reads, ro, _ = datagen.sample_from_genomes(db, offs.astype(np.int64), 40, 2, 100, 33, sub=0.0)
+    counts, sizes = oracle.contain(ik, iv, reads, ro, pat, k, w, 3)
+    _, _, sh = oracle.seed(ik, iv & np.uint64(0xFFFFFFFF), reads, ro, pat, k, w)
+    sample = set()
+    for r in range(ro.size - 1):
+        sample |= {kv[0] for kv in brute.sketch(reads[ro[r]:ro[r + 1]].tolist(), pat, int(sh[r]), k, w)}
+    for g in range(3):
+        hg = {int(kk) for kk, vv in zip(ik, iv) if int(vv) >> 32 == g}
+        assert sizes[g] == len(hg)
+        assert counts[g] == len(hg & sample)
