@@ -272,7 +272,8 @@ def test_lookup_matches_searchsorted():
 
 @pytest.mark.parametrize("pattern,k,w,t,max_occ", [("10", 7, 4, 0, 0), ("110", 5, 3, 0, 0),
                                                      ("101", 6, 2, 3, 0), ("1", 5, 3, 0, 0),
-                                                     ("100", 4, 2, 0, 3), ("10", 4, 3, 2, 2)])
+                                                     ("100", 4, 2, 0, 3), ("10", 4, 3, 2, 2),
+                                                     ("110", 3, 2, 1, 0)])
 def test_seed_matches_brute_force(pattern, k, w, t, max_occ):
     rng = np.random.default_rng(16)
     ref = rng.integers(0, 4, 600, dtype=np.uint8)
