@@ -1,0 +1,194 @@
+/*
+ * godiet.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path of
+ * Genome-on-Diet's sparsified genomics (Alser, Eudine, Mutlu, arXiv 2211.08157):
+ * sparsify sequences with a repeating keep/skip pattern, sketch the patterned sequences
+ * into canonical (w,k)-minimizers, build the sorted minimizer index of a reference, and
+ * seed reads against it (pattern alignment + compressed seeding) to emit anchors.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers unless marked [host].  Every buffer is owned by the
+ *    caller; the library never allocates, frees, copies to the host or synchronises
+ *    inside a call.  All work is enqueued on the caller's stream, so a call may be
+ *    captured into a HIP graph.
+ *  - Scratch memory is the caller's `ws` of at least godiet_workspace_size() bytes for
+ *    the same operation and sizes.
+ *  - Argument errors (bad pattern, k or w out of range, NULL pointers, workspace too
+ *    small, sizes that cannot fit the value encoding) are detected on the host before
+ *    anything is enqueued and returned synchronously; nothing is written then.
+ *  - Data-dependent problems (an output larger than the caller's capacity, a position
+ *    that does not fit 31 bits, a per-sequence shift >= p) are reported through the
+ *    device status word `status` (bits GODIET_ST_*), which each call clears first.  The
+ *    call still writes the REQUIRED count, so the caller can synchronise, read the status,
+ *    resize and call again.  Outputs other than the counts are unspecified then.
+ *  - A failed kernel launch returns GODIET_E_HIP.
+ *  - Calls that share a workspace must not overlap; otherwise the library keeps no
+ *    state and calls on different streams with different workspaces are independent.
+ *
+ * Sequence layout (the paper's 2-bit encoding of A, C, G, T; Section 3.6.1)
+ * -----------------------------------------------------------------------
+ *  A batch of n_seq sequences is one 2-bit packed byte array: base i of the batch is
+ *  bits [2*(i%4), 2*(i%4)+1] of byte i/4, with A=0, C=1, G=2, T=3 (N cannot be encoded;
+ *  the host packer rejects it).  offsets[n_seq+1] (uint64, non-decreasing, offsets[0] = 0,
+ *  offsets[n_seq] = n_bases) delimit the sequences; they need not be multiples of 4.
+ *  The byte array must hold at least ceil(n_bases / 4) bytes.
+ *
+ * The method (Section 3; Sections 3.1-3.3)
+ * -----------------------------------------
+ *  pattern P = p characters '0'/'1' (1 <= p <= 64, weight x >= 1 ones).  With shift a,
+ *  base j of a sequence is kept iff P[(j - a) mod p] == '1' (the cyclic form of the
+ *  paper's {Q[i+a] * P[i mod p]}).  The reference uses a = 0.
+ *  k-mer code: 2k bits, first base most significant; canonical code = min(forward,
+ *  reverse complement), strand = 1 iff the reverse complement is smaller; a k-mer equal
+ *  to its own reverse complement is never a minimizer.  hash = splitmix64 finalizer of
+ *  the canonical code.  A k-mer of the patterned sequence is a minimizer iff its hash
+ *  equals the minimum over some full window of w consecutive k-mers (all ties kept).
+ *  Locations are coordinates in the ORIGINAL sequence of the k-mer's first kept base.
+ */
+#ifndef GODIET_H
+#define GODIET_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t godiet_status;
+#define GODIET_OK            0
+#define GODIET_E_INVAL      (-1)  /* bad argument */
+#define GODIET_E_RANGE      (-2)  /* sizes do not fit the value encoding */
+#define GODIET_E_WORKSPACE  (-3)  /* ws NULL or smaller than godiet_workspace_size() */
+#define GODIET_E_HIP        (-4)  /* a HIP launch failed */
+#define GODIET_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+
+/* bits of the device status word */
+#define GODIET_ST_CAPACITY 1u  /* output larger than capacity; required count written */
+#define GODIET_ST_RANGE    2u  /* a position needs more than 31 bits */
+#define GODIET_ST_SHIFT    4u  /* a per-sequence shift is >= p */
+
+/* operations for godiet_workspace_size */
+#define GODIET_OP_SPARSIFY    1
+#define GODIET_OP_SKETCH      2
+#define GODIET_OP_INDEX_BUILD 3
+#define GODIET_OP_SEED        4
+#define GODIET_OP_RMI_TRAIN   5
+#define GODIET_OP_CONTAIN     6
+
+typedef struct {
+    const uint8_t *bases;     /* 2-bit packed bases (layout above) */
+    const uint64_t *offsets;  /* n_seq + 1 base offsets */
+    uint32_t n_seq;           /* [host] */
+    uint64_t n_bases;         /* [host] must equal offsets[n_seq] */
+} godiet_seqs;
+
+typedef struct {
+    const char *pattern;      /* [host] NUL-terminated '0'/'1' string, 1..64 chars, >= one '1' */
+    int32_t k;                /* 1..32 */
+    int32_t w;                /* 1..256 */
+} godiet_sketch_params;
+
+/* A sorted seed index as produced by godiet_index_build.  val_bits 32: vals is uint32
+ * global position << 1 | strand; val_bits 64: vals is uint64 sequence id << 32 |
+ * position << 1 | strand.  rmi: NULL for binary-search lookups, else a learned index
+ * trained on exactly these keys by godiet_rmi_train (rmi_bytes its size). */
+typedef struct {
+    const uint64_t *keys;
+    const void *vals;
+    uint64_t n;               /* [host] number of records (< 2^32) */
+    int32_t val_bits;
+    const void *rmi;
+    size_t rmi_bytes;         /* [host] */
+} godiet_index;
+
+typedef struct {
+    int32_t shift_mode;       /* -1: pattern alignment (Section 3.2); 0..p-1: fixed shift */
+    uint32_t align_t;         /* 0: no limit; else at most t minimizers scored per shift */
+    uint32_t max_occ;         /* 0: off; else minimizers with >= max_occ index hits are
+                                 skipped in alignment scores and in seeding */
+} godiet_seed_opts;
+
+typedef struct {
+    uint32_t read_id, qpos, rpos, strand;   /* 16 bytes */
+} godiet_anchor;
+
+/* Human-readable text of a status code. */
+const char *godiet_status_string(godiet_status s);
+
+/* [host] Bytes of scratch an operation needs for these sizes.  `seqs` is the batch the
+ * operation sketches (reference for INDEX_BUILD, reads for SEED/CONTAIN); only its host
+ * fields are read.  n_index is the index size for SEED/CONTAIN/RMI_TRAIN, the output
+ * capacity for SKETCH/INDEX_BUILD.  Returns 0 on invalid arguments. */
+size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs,
+                             const godiet_sketch_params *prm, uint64_t n_index);
+
+/* [host] Upper bound on the number of kept bases of the batch under any shift
+ * (floor(n_bases / p) * x + n_seq * x, capped at n_bases).  Returns UINT64_MAX on a bad
+ * pattern. */
+uint64_t godiet_kept_bound(const godiet_seqs *seqs, const char *pattern);
+
+/* [host] Bytes godiet_sparsify writes to out_bases (a multiple of 4, including zero
+ * padding), or 0 on a bad pattern. */
+size_t godiet_sparsify_bytes(const godiet_seqs *seqs, const char *pattern);
+
+/* Sparsification (Section 3.1 steps 1-2; Section 3, definition of PR and PQ):
+ * keep base j of sequence s iff P[(j - a_s) mod p] == '1', a_s = shift[s] (shift NULL:
+ * all 0).  out_bases receives the kept bases of all sequences back to back in the same
+ * 2-bit layout, zero-padded to godiet_sparsify_bytes(); out_offsets[n_seq+1] their
+ * boundaries. */
+godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const uint32_t *shift,
+                              uint8_t *out_bases, uint64_t *out_offsets,
+                              void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
+/* Minimizer sketch (Section 3.1 step 3, "double-strand (w,k)-minimizer"; Section 3.6.1):
+ * the minimizers of every sequence, sparsified with its shift (NULL: 0), as records
+ * keys[i] = hash, vals[i] = position << 1 | strand (position in that sequence's own
+ * original coordinates), in ascending sequence then position order.
+ * mz_offsets[n_seq+1] delimit each sequence's records.  At most `capacity` records are
+ * written; mz_offsets[n_seq] is the required count either way. */
+godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *prm,
+                            const uint32_t *shift, uint64_t *keys, uint32_t *vals,
+                            uint64_t *mz_offsets, uint64_t capacity,
+                            void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
+/* Compressed indexing (Section 3.1): minimizers of the sparsified reference (shift 0),
+ * appended and sorted ascending by (hash, val) into keys[] / vals[].  val_bits 32: vals is
+ * uint32 (global position in the batch) << 1 | strand, needs n_bases < 2^31; val_bits
+ * 64: vals is uint64 sequence id << 32 | position << 1 | strand.  *n_out (device)
+ * receives the number of records; at most `capacity` are written. */
+godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_params *prm,
+                                 uint64_t *keys, void *vals, int32_t val_bits,
+                                 uint64_t capacity, uint64_t *n_out,
+                                 void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
+/* Pattern alignment (Section 3.2) and compressed seeding (Section 3.3) of a read batch
+ * against a 32-bit-val index.  For each read r: with shift_mode -1, every shift s in
+ * [0, p) is sketched; the first n* = min_s |M_s| minimizers of each shift (n* capped at
+ * align_t when align_t > 0) are scored by their summed index occurrences (skipping those
+ * with >= max_occ when max_occ > 0); a_r = the smallest shift of maximal score (0 when
+ * every score is 0 or p == 1).  Then, for every minimizer of shift a_r in ascending read
+ * position (skipping >= max_occ when set) and every index entry e with the same hash in
+ * index order, one anchor {r, qpos, vals[e] >> 1, (qval ^ vals[e]) & 1} is written.
+ * Anchors are therefore sorted by (read_id, qpos, rpos).  read_anchor_off[n_reads+1]
+ * delimits each read's anchors (its last entry is the required count); shift_out
+ * (nullable) receives a_r.  At most `capacity` anchors are written. */
+godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
+                          const godiet_sketch_params *prm, const godiet_seed_opts *opts,
+                          godiet_anchor *anchors, uint64_t capacity, uint64_t *read_anchor_off,
+                          uint8_t *shift_out, void *ws, size_t ws_bytes, uint32_t *status,
+                          hipStream_t stream);
+
+/* Kernel tracing, a profiling aid outside the method.  While enabled, every kernel launch
+ * of the library is bracketed by HIP events recorded on the launch's stream.  After the
+ * caller has synchronised, godiet_trace_dump writes one line "kernel launches total_ms"
+ * per kernel into buf (truncated to len bytes, NUL-terminated), forgets the records and
+ * returns the number of bytes the full text needs including the NUL. */
+void godiet_trace_enable(int on);
+size_t godiet_trace_dump(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GODIET_H */

@@ -1,0 +1,289 @@
+"""ctypes declarations of libgodiet.so and torch-based argument marshalling."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libgodiet.so")
+
+OK, E_INVAL, E_RANGE, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_CAPACITY, STATUS_RANGE, STATUS_SHIFT = 1, 2, 4
+OP_SPARSIFY, OP_SKETCH, OP_INDEX_BUILD, OP_SEED, OP_RMI_TRAIN, OP_CONTAIN = 1, 2, 3, 4, 5, 6
+
+
+class GodietError(RuntimeError):
+    def __init__(self, code, what):
+        msg = lib().godiet_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__("%s: %s (%d)" % (what, msg, code))
+        self.code = code
+
+
+class Seqs(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n_seq", ctypes.c_uint32), ("n_bases", ctypes.c_uint64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("pattern", ctypes.c_char_p), ("k", ctypes.c_int32), ("w", ctypes.c_int32)]
+
+
+class Index(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("val_bits", ctypes.c_int32), ("rmi", ctypes.c_void_p),
+                ("rmi_bytes", ctypes.c_size_t)]
+
+
+class SeedOpts(ctypes.Structure):
+    _fields_ = [("shift_mode", ctypes.c_int32), ("align_t", ctypes.c_uint32),
+                ("max_occ", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise ImportError("libgodiet.so not built: run __graft_entry__.build() or "
+                              "python paper_2211_08157_amd/build.py")
+        L = ctypes.CDLL(lib_path)
+        P, S = ctypes.c_void_p, ctypes.POINTER
+        u32, u64, i32, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
+        L.godiet_status_string.argtypes = [i32]
+        L.godiet_status_string.restype = ctypes.c_char_p
+        L.godiet_workspace_size.argtypes = [i32, S(Seqs), S(Params), u64]
+        L.godiet_workspace_size.restype = sz
+        L.godiet_kept_bound.argtypes = [S(Seqs), ctypes.c_char_p]
+        L.godiet_kept_bound.restype = u64
+        L.godiet_sparsify_bytes.argtypes = [S(Seqs), ctypes.c_char_p]
+        L.godiet_sparsify_bytes.restype = sz
+        L.godiet_sparsify.argtypes = [S(Seqs), ctypes.c_char_p, P, P, P, P, sz, P, P]
+        L.godiet_sparsify.restype = i32
+        L.godiet_sketch.argtypes = [S(Seqs), S(Params), P, P, P, P, u64, P, sz, P, P]
+        L.godiet_sketch.restype = i32
+        L.godiet_index_build.argtypes = [S(Seqs), S(Params), P, P, i32, u64, P, P, sz, P, P]
+        L.godiet_index_build.restype = i32
+        L.godiet_seed.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), P, u64, P, P, P, sz,
+                                  P, P]
+        L.godiet_seed.restype = i32
+        L.godiet_trace_enable.argtypes = [ctypes.c_int]
+        L.godiet_trace_enable.restype = None
+        L.godiet_trace_dump.argtypes = [ctypes.c_char_p, sz]
+        L.godiet_trace_dump.restype = sz
+        _lib = L
+    return _lib
+
+
+def trace_enable(on=True):
+    lib().godiet_trace_enable(1 if on else 0)
+
+
+def trace_dump():
+    """{kernel name: (launches, total ms)} of the launches traced since the last dump.
+    The caller must have synchronised the streams the kernels ran on."""
+    L = lib()
+    need = L.godiet_trace_dump(None, 0)
+    buf = ctypes.create_string_buffer(max(need, 1) + 4096)
+    L.godiet_trace_dump(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.rsplit(" ", 2)
+        out[name] = (int(n), float(ms))
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(code, what):
+    if code != OK:
+        raise GodietError(code, what)
+
+
+def pack(codes):
+    """2-bit pack base codes (A=0, C=1, G=2, T=3): base i -> bits 2*(i%4) of byte i//4.
+    The result is padded with zero bytes to a multiple of 16."""
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    if c.size and c.max() > 3:
+        raise ValueError("only A, C, G, T (codes 0..3) can be packed")
+    n = c.size
+    padded = np.zeros((n + 63) // 64 * 64, np.uint8)
+    padded[:n] = c
+    q = padded.reshape(-1, 4)
+    return (q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)).astype(np.uint8)
+
+
+class DeviceSeqs:
+    """A 2-bit packed batch of sequences resident in device memory."""
+
+    def __init__(self, bases, offsets, n_seq, n_bases):
+        self.bases, self.offsets = bases, offsets
+        self.n_seq, self.n_bases = int(n_seq), int(n_bases)
+
+    def c(self):
+        return Seqs(self.bases.data_ptr(), self.offsets.data_ptr(), self.n_seq, self.n_bases)
+
+
+def to_device(codes, offsets, device="cuda"):
+    torch = _torch()
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    if offs.size < 1 or offs[0] != 0 or np.any(np.diff(offs) < 0):
+        raise ValueError("offsets must start at 0 and be non-decreasing")
+    packed = pack(codes)
+    if offs[-1] > np.asarray(codes).size:
+        raise ValueError("offsets exceed the number of bases")
+    b = torch.from_numpy(packed).to(device)
+    o = torch.from_numpy(offs).to(device)
+    return DeviceSeqs(b, o, offs.size - 1, int(offs[-1]))
+
+
+def _params(pattern, k, w):
+    return Params(pattern.encode(), int(k), int(w))
+
+
+def workspace_size(op, seqs, pattern, k, w, n_index=0):
+    s = seqs.c()
+    return lib().godiet_workspace_size(op, ctypes.byref(s), ctypes.byref(_params(pattern, k, w)),
+                                       int(n_index))
+
+
+def kept_bound(seqs, pattern):
+    s = seqs.c()
+    return lib().godiet_kept_bound(ctypes.byref(s), pattern.encode())
+
+
+def _empty(n, dtype):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=dtype, device="cuda")
+
+
+def _status_value(st):
+    return int(st.item())
+
+
+def sparsify(seqs, pattern, shift=None):
+    """Returns (packed patterned bases as uint8 tensor, patterned offsets int64 tensor)."""
+    torch = _torch()
+    s = seqs.c()
+    L = lib()
+    nbytes = L.godiet_sparsify_bytes(ctypes.byref(s), pattern.encode())
+    ws = _empty(workspace_size(OP_SPARSIFY, seqs, pattern, 1, 1), torch.uint8)
+    out = _empty(nbytes, torch.uint8)
+    offs = _empty(seqs.n_seq + 1, torch.int64)
+    st = _empty(1, torch.int32)
+    sh = None if shift is None else torch.as_tensor(np.asarray(shift, np.uint32).view(np.int32),
+                                                     device="cuda")
+    _check(L.godiet_sparsify(ctypes.byref(s), pattern.encode(), _ptr(sh), _ptr(out), _ptr(offs),
+                             _ptr(ws), ws.numel(), _ptr(st), _stream()), "godiet_sparsify")
+    if _status_value(st) & STATUS_SHIFT:
+        raise ValueError("a shift is >= the pattern length")
+    return out, offs
+
+
+def sketch(seqs, pattern, k, w, shift=None, capacity=None):
+    """Minimizers of every sequence.  Returns (keys int64 tensor holding uint64 bits,
+    vals int32 tensor holding uint32 pos<<1|strand, mz_offsets int64 tensor)."""
+    torch = _torch()
+    s = seqs.c()
+    L = lib()
+    prm = _params(pattern, k, w)
+    if capacity is None:
+        capacity = max(1024, int(kept_bound(seqs, pattern) * 2.2 / (w + 1)) + 4096)
+    sh = None if shift is None else torch.as_tensor(np.asarray(shift, np.uint32).view(np.int32),
+                                                     device="cuda")
+    ws = _empty(workspace_size(OP_SKETCH, seqs, pattern, k, w), torch.uint8)
+    mz = _empty(seqs.n_seq + 1, torch.int64)
+    st = _empty(1, torch.int32)
+    while True:
+        keys = _empty(capacity, torch.int64)
+        vals = _empty(capacity, torch.int32)
+        _check(L.godiet_sketch(ctypes.byref(s), ctypes.byref(prm), _ptr(sh), _ptr(keys), _ptr(vals),
+                               _ptr(mz), capacity, _ptr(ws), ws.numel(), _ptr(st), _stream()),
+               "godiet_sketch")
+        status = _status_value(st)
+        n = int(mz[-1].item())
+        if status & STATUS_CAPACITY:
+            capacity = n
+            continue
+        if status & STATUS_SHIFT:
+            raise ValueError("a shift is >= the pattern length")
+        if status & STATUS_RANGE:
+            raise ValueError("a sequence is too long for 31-bit positions")
+        return keys[:n], vals[:n], mz
+
+
+class DeviceIndex:
+    """A sorted seed index in device memory (keys as int64 bit patterns of uint64)."""
+
+    def __init__(self, keys, vals, n, val_bits):
+        self.keys, self.vals, self.n, self.val_bits = keys, vals, int(n), int(val_bits)
+
+    def c(self):
+        return Index(self.keys.data_ptr(), self.vals.data_ptr(), self.n, self.val_bits, None, 0)
+
+
+def index_build(ref, pattern, k, w, val_bits=32, capacity=None):
+    torch = _torch()
+    s = ref.c()
+    L = lib()
+    prm = _params(pattern, k, w)
+    if capacity is None:
+        capacity = max(1024, int(kept_bound(ref, pattern) * 2.2 / (w + 1)) + 4096)
+    st = _empty(1, torch.int32)
+    n_out = _empty(1, torch.int64)
+    while True:
+        ws = _empty(workspace_size(OP_INDEX_BUILD, ref, pattern, k, w, capacity), torch.uint8)
+        keys = _empty(capacity, torch.int64)
+        vals = _empty(capacity, torch.int32 if val_bits == 32 else torch.int64)
+        _check(L.godiet_index_build(ctypes.byref(s), ctypes.byref(prm), _ptr(keys), _ptr(vals),
+                                    val_bits, capacity, _ptr(n_out), _ptr(ws), ws.numel(), _ptr(st),
+                                    _stream()), "godiet_index_build")
+        status = _status_value(st)
+        n = int(n_out.item())
+        if status & STATUS_CAPACITY:
+            capacity = n
+            continue
+        if status & STATUS_RANGE:
+            raise ValueError("a position does not fit the value encoding")
+        return DeviceIndex(keys[:n], vals[:n], n, val_bits)
+
+
+def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capacity=None):
+    """Pattern alignment + compressed seeding.  Returns (anchors int32 tensor (n, 4) of
+    read_id, qpos, rpos, strand; read_anchor_off int64 tensor; shift uint8 tensor)."""
+    torch = _torch()
+    s = reads.c()
+    L = lib()
+    prm = _params(pattern, k, w)
+    ix = index.c()
+    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ))
+    ws = _empty(workspace_size(OP_SEED, reads, pattern, k, w, index.n), torch.uint8)
+    off = _empty(reads.n_seq + 1, torch.int64)
+    shift = _empty(reads.n_seq, torch.uint8)
+    st = _empty(1, torch.int32)
+    if capacity is None:
+        capacity = max(4096, reads.n_bases // 4)
+    while True:
+        anchors = _empty(capacity * 4, torch.int32)
+        _check(L.godiet_seed(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(prm),
+                             ctypes.byref(opts), _ptr(anchors), capacity, _ptr(off), _ptr(shift),
+                             _ptr(ws), ws.numel(), _ptr(st), _stream()), "godiet_seed")
+        status = _status_value(st)
+        n = int(off[-1].item())
+        if status & STATUS_CAPACITY:
+            capacity = n
+            continue
+        return anchors[:4 * n].view(n, 4), off, shift[:reads.n_seq]

@@ -1,0 +1,327 @@
+// C ABI entry points: host-side validation, workspace layout and kernel sequencing.
+#include <string.h>
+
+#include "../../include/godiet.h"
+#include "gd_internal.h"
+
+using namespace gd;
+
+namespace {
+
+bool parse_pattern(const char *s, Pattern *P)
+{
+    if (!s) return false;
+    const size_t n = strnlen(s, 65);
+    if (n < 1 || n > 64) return false;
+    memset(P, 0, sizeof(*P));
+    P->p = (uint32_t)n;
+    for (size_t i = 0; i < n; i++) {
+        if (s[i] == '1') {
+            P->mask |= 1ull << i;
+            P->ones[P->x++] = (uint8_t)i;
+        } else if (s[i] != '0') {
+            return false;
+        }
+    }
+    return P->x >= 1;
+}
+
+bool valid_seqs(const godiet_seqs *q)
+{
+    if (!q || !q->offsets) return false;
+    if (q->n_bases > 0 && !q->bases) return false;
+    return q->n_bases < (1ull << 48);
+}
+
+bool valid_params(const godiet_sketch_params *prm, Pattern *P)
+{
+    if (!prm || !parse_pattern(prm->pattern, P)) return false;
+    return prm->k >= 1 && prm->k <= 32 && prm->w >= 1 && prm->w <= 256;
+}
+
+uint64_t kept_bound(const godiet_seqs *q, const Pattern &P)
+{
+    const uint64_t b = (q->n_bases / P.p) * P.x + (uint64_t)q->n_seq * P.x;
+    return b < q->n_bases ? b : q->n_bases;
+}
+
+Batch batch_of(const godiet_seqs *q) { return Batch{q->bases, q->offsets, q->n_seq, q->n_bases}; }
+
+#define GD_TRY(expr)                                   \
+    do {                                               \
+        if ((expr) != hipSuccess) return GODIET_E_HIP; \
+    } while (0)
+
+// ---- workspace plans: the same code measures (ws == nullptr) and carves ----
+
+struct SketchWs {
+    uint64_t *kept, *scan, *pofs;
+    uint32_t *psw;
+    uint64_t *tiles;
+    uint32_t *counter;
+};
+
+void plan_sketch_ws(Bump &b, uint32_t n_seq, uint64_t npb, int w, SketchWs *o)
+{
+    o->kept = b.take<uint64_t>((size_t)n_seq + 1);
+    o->scan = b.take<uint64_t>(scan_scratch((size_t)n_seq + 1));
+    o->pofs = b.take<uint64_t>((size_t)n_seq + 1);
+    o->psw = b.take<uint32_t>(psw_words(npb));
+    o->tiles = b.take<uint64_t>(sketch_tiles_bound(npb, w));
+    o->counter = b.take<uint32_t>(1);
+}
+
+// kept counts -> pofs -> patterned stream, for a per-sequence or uniform shift
+hipError_t sparsify_to_stream(const godiet_seqs *in, const Pattern &P, const uint32_t *shift,
+                              uint32_t uniform, const SketchWs &W, uint64_t npb, uint32_t *status,
+                              hipStream_t s)
+{
+    const Batch bt = batch_of(in);
+    hipError_t e = launch_kept(bt, P, shift, uniform, W.kept, status, s);
+    if (e != hipSuccess) return e;
+    e = exclusive_scan_u64(W.kept, W.pofs, in->n_seq, W.scan, s);
+    if (e != hipSuccess) return e;
+    return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, psw_words(npb), s);
+}
+
+struct IndexWs {
+    SketchWs sk;
+    SortWs so;
+    SortPlan sp;
+};
+
+void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uint64_t capacity,
+                   int val_bytes, IndexWs *o)
+{
+    const uint64_t npb = kept_bound(ref, P);
+    plan_sketch_ws(b, ref->n_seq, npb, w, &o->sk);
+    uint64_t expected = npb * 2 / (uint64_t)(w + 1) + 1;
+    if (expected > capacity) expected = capacity;
+    o->sp = sort_plan(expected);
+    o->so.hist = b.take<uint32_t>(o->sp.nbuckets);
+    o->so.bofs = b.take<uint64_t>(o->sp.nbuckets + 1);
+    o->so.cursor = b.take<uint32_t>(o->sp.nbuckets);
+    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nbuckets));
+    o->so.tkeys = b.take<uint64_t>(capacity);
+    o->so.tvals = b.take<uint8_t>(capacity * (uint64_t)val_bytes);
+    o->so.overflow = b.take<uint32_t>(o->sp.nbuckets);
+    o->so.overflow_n = b.take<uint32_t>(1);
+}
+
+struct SeedWs {
+    SketchWs sk;
+    uint64_t *mzofs;      // n_shift * (n_reads + 1)
+    uint64_t *qkeys;      // n_shift * stride
+    uint32_t *qvals, *lb, *occ;
+    uint32_t *slot, *cnt;
+    uint64_t *scan;
+    size_t stride;
+};
+
+void plan_seed_ws(Bump &b, const godiet_seqs *reads, const Pattern &P, int w, uint32_t n_shift,
+                  SeedWs *o)
+{
+    const uint64_t npb = kept_bound(reads, P);
+    plan_sketch_ws(b, reads->n_seq, npb, w, &o->sk);
+    o->stride = (size_t)npb + 1;
+    const size_t nr = (size_t)reads->n_seq;
+    o->mzofs = b.take<uint64_t>((nr + 1) * n_shift);
+    o->qkeys = b.take<uint64_t>(o->stride * n_shift);
+    o->qvals = b.take<uint32_t>(o->stride * n_shift);
+    o->lb = b.take<uint32_t>(o->stride * n_shift);
+    o->occ = b.take<uint32_t>(o->stride * n_shift);
+    o->slot = b.take<uint32_t>(nr + 1);
+    o->cnt = b.take<uint32_t>(nr + 1);
+    o->scan = b.take<uint64_t>(scan_scratch(nr + 1));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *godiet_status_string(godiet_status s)
+{
+    switch (s) {
+    case GODIET_OK: return "ok";
+    case GODIET_E_INVAL: return "invalid argument";
+    case GODIET_E_RANGE: return "sizes do not fit the value encoding";
+    case GODIET_E_WORKSPACE: return "workspace missing or too small";
+    case GODIET_E_HIP: return "HIP launch failed";
+    case GODIET_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+uint64_t godiet_kept_bound(const godiet_seqs *seqs, const char *pattern)
+{
+    Pattern P;
+    if (!seqs || !parse_pattern(pattern, &P)) return UINT64_MAX;
+    return kept_bound(seqs, P);
+}
+
+size_t godiet_sparsify_bytes(const godiet_seqs *seqs, const char *pattern)
+{
+    Pattern P;
+    if (!seqs || !parse_pattern(pattern, &P)) return 0;
+    return psw_words(kept_bound(seqs, P)) * 4;
+}
+
+size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_sketch_params *prm,
+                             uint64_t n_index)
+{
+    Pattern P;
+    if (!seqs) return 0;
+    Bump b(nullptr);
+    switch (op) {
+    case GODIET_OP_SPARSIFY: {
+        if (!prm || !parse_pattern(prm->pattern, &P)) return 0;
+        b.take<uint64_t>((size_t)seqs->n_seq + 1);
+        b.take<uint64_t>(scan_scratch((size_t)seqs->n_seq + 1));
+        return b.off;
+    }
+    case GODIET_OP_SKETCH: {
+        if (!valid_params(prm, &P)) return 0;
+        SketchWs o;
+        plan_sketch_ws(b, seqs->n_seq, kept_bound(seqs, P), prm->w, &o);
+        return b.off;
+    }
+    case GODIET_OP_INDEX_BUILD: {
+        if (!valid_params(prm, &P)) return 0;
+        IndexWs o;
+        plan_index_ws(b, seqs, P, prm->w, n_index, 8, &o);
+        return b.off;
+    }
+    case GODIET_OP_SEED: {
+        if (!valid_params(prm, &P)) return 0;
+        SeedWs o;
+        plan_seed_ws(b, seqs, P, prm->w, P.p, &o);
+        return b.off;
+    }
+    default: return 0;
+    }
+}
+
+godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const uint32_t *shift,
+                              uint8_t *out_bases, uint64_t *out_offsets, void *ws, size_t ws_bytes,
+                              uint32_t *status, hipStream_t stream)
+{
+    Pattern P;
+    if (!valid_seqs(in) || !parse_pattern(pattern, &P) || !out_bases || !out_offsets || !status)
+        return GODIET_E_INVAL;
+    if (((uintptr_t)out_bases & 3) != 0) return GODIET_E_INVAL;
+    Bump b(ws);
+    uint64_t *kept = b.take<uint64_t>((size_t)in->n_seq + 1);
+    uint64_t *scan = b.take<uint64_t>(scan_scratch((size_t)in->n_seq + 1));
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    const Batch bt = batch_of(in);
+    const uint64_t npb = kept_bound(in, P);
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(launch_kept(bt, P, shift, 0, kept, status, stream));
+    GD_TRY(exclusive_scan_u64(kept, out_offsets, in->n_seq, scan, stream));
+    GD_TRY(launch_sparsify(bt, P, shift, 0, out_offsets, (uint32_t *)out_bases, psw_words(npb),
+                           stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *prm,
+                            const uint32_t *shift, uint64_t *keys, uint32_t *vals,
+                            uint64_t *mz_offsets, uint64_t capacity, void *ws, size_t ws_bytes,
+                            uint32_t *status, hipStream_t stream)
+{
+    Pattern P;
+    if (!valid_seqs(in) || !valid_params(prm, &P) || !mz_offsets || !status) return GODIET_E_INVAL;
+    if (capacity > 0 && (!keys || !vals)) return GODIET_E_INVAL;
+    const uint64_t npb = kept_bound(in, P);
+    Bump b(ws);
+    SketchWs W;
+    plan_sketch_ws(b, in->n_seq, npb, prm->w, &W);
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, status, stream));
+    SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
+    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, npb, prm->k, prm->w, o, W.tiles,
+                         W.counter, status, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_params *prm,
+                                 uint64_t *keys, void *vals, int32_t val_bits, uint64_t capacity,
+                                 uint64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status,
+                                 hipStream_t stream)
+{
+    Pattern P;
+    if (!valid_seqs(ref) || !valid_params(prm, &P) || !n_out || !status) return GODIET_E_INVAL;
+    if (val_bits != 32 && val_bits != 64) return GODIET_E_INVAL;
+    if (capacity > 0 && (!keys || !vals)) return GODIET_E_INVAL;
+    if (capacity >= (1ull << 32)) return GODIET_E_RANGE;
+    if (val_bits == 32 && ref->n_bases >= (1ull << 31)) return GODIET_E_RANGE;
+    const uint64_t npb = kept_bound(ref, P);
+    const int vb = val_bits / 8;
+    Bump b(ws);
+    IndexWs W;
+    plan_index_ws(b, ref, P, prm->w, capacity, 8, &W);
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));
+    SketchOut o{keys, vals, val_bits == 32 ? VAL_GLOBAL32 : VAL_SEQ64, nullptr, capacity, n_out};
+    GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, npb, prm->k, prm->w, o,
+                         W.sk.tiles, W.sk.counter, status, stream));
+    if (capacity > 0) GD_TRY(launch_sort(W.sp, W.so, keys, vals, vb, n_out, capacity, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
+                          const godiet_sketch_params *prm, const godiet_seed_opts *opts,
+                          godiet_anchor *anchors, uint64_t capacity, uint64_t *read_anchor_off,
+                          uint8_t *shift_out, void *ws, size_t ws_bytes, uint32_t *status,
+                          hipStream_t stream)
+{
+    Pattern P;
+    if (!index || !valid_seqs(reads) || !valid_params(prm, &P) || !opts || !read_anchor_off ||
+        !status)
+        return GODIET_E_INVAL;
+    if (index->val_bits != 32) return GODIET_E_UNSUPPORTED;
+    if (index->n > 0 && (!index->keys || !index->vals)) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (index->rmi) return GODIET_E_UNSUPPORTED;
+    if (opts->shift_mode < -1 || opts->shift_mode >= (int32_t)P.p) return GODIET_E_INVAL;
+    if (capacity > 0 && !anchors) return GODIET_E_INVAL;
+    const uint64_t npb = kept_bound(reads, P);
+    const uint32_t n_shift = opts->shift_mode >= 0 ? 1u : P.p;
+    Bump b(ws);
+    SeedWs W;
+    plan_seed_ws(b, reads, P, prm->w, n_shift, &W);
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    const size_t nr = reads->n_seq;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    for (uint32_t si = 0; si < n_shift; si++) {
+        const uint32_t a = opts->shift_mode >= 0 ? (uint32_t)opts->shift_mode : si;
+        GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, status, stream));
+        uint64_t *mz = W.mzofs + si * (nr + 1);
+        uint64_t *qk = W.qkeys + si * W.stride;
+        uint32_t *qv = W.qvals + si * W.stride;
+        SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
+        GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
+                             prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
+        GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
+                             W.occ + si * W.stride, stream));
+    }
+    AlignArgs A;
+    A.mzofs = W.mzofs;
+    A.occ = W.occ;
+    A.lb = W.lb;
+    A.qval = W.qvals;
+    A.stride = W.stride;
+    A.n_reads = reads->n_seq;
+    A.n_shift = n_shift;
+    A.fixed_shift = opts->shift_mode;
+    A.align_t = opts->align_t;
+    A.max_occ = opts->max_occ;
+    GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, stream));
+    GD_TRY(exclusive_scan_u32(W.cnt, read_anchor_off, nr, W.scan, stream));
+    GD_TRY(launch_expand(A, W.slot, read_anchor_off, index->vals, (uint32_t *)anchors, capacity,
+                         status, stream));
+    return GODIET_OK;
+}
+
+}  // extern "C"

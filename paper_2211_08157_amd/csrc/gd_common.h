@@ -1,0 +1,137 @@
+// Device-side building blocks shared by the gfx950 kernels of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gd {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+constexpr uint64_t kMax64 = ~0ull;
+
+// A keep/skip pattern (Section 3: P[0..p-1], weight x).  Passed by value to kernels.
+struct Pattern {
+    uint64_t mask;     // bit t set iff P[t] == '1'
+    uint32_t p, x;
+    uint8_t ones[64];  // positions of the ones in ascending order
+};
+
+// splitmix64 output function (the k-mer hash; Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Pattern rotated right by a: bit t set iff P[(t - a) mod p] == '1'.
+__host__ __device__ __forceinline__ uint64_t rotated_mask(const Pattern &P, uint32_t a)
+{
+    const uint64_t full = P.p == 64 ? kMax64 : ((1ull << P.p) - 1);
+    if (a == 0) return P.mask;
+    return ((P.mask << a) | (P.mask >> (P.p - a))) & full;
+}
+
+// Kept bases of a length-L sequence under shift a: floor(L/p)*x + ones of the rotated
+// pattern among the first L mod p phases.
+__device__ __forceinline__ uint64_t kept_count(const Pattern &P, uint64_t L, uint32_t a)
+{
+    const uint64_t q = L / P.p;
+    const uint32_t rem = (uint32_t)(L - q * P.p);
+    const uint64_t m = rotated_mask(P, a);
+    const uint64_t low = rem == 64 ? m : (m & ((1ull << rem) - 1));
+    return q * P.x + (uint64_t)__popcll(low);
+}
+
+// Offset within a period of the r-th kept phase under shift a (0 <= r < x).  The ones
+// u_i of P move to (u_i + a) mod p; those with u_i >= p - a wrap to the front.
+__device__ __forceinline__ uint32_t kept_phase(const Pattern &P, uint32_t a, uint32_t r)
+{
+    const uint32_t front = a == 0 ? P.x
+        : (uint32_t)__popcll(P.mask & ((1ull << (P.p - a)) - 1));   // ones with u < p - a
+    uint32_t idx = r + front;
+    if (idx >= P.x) idx -= P.x;
+    uint32_t v = P.ones[idx] + a;
+    if (v >= P.p) v -= P.p;
+    return v;
+}
+
+// Original coordinate of the li-th kept base of a sequence under shift a.
+__device__ __forceinline__ uint64_t orig_of(const Pattern &P, uint64_t li, uint32_t a)
+{
+    const uint64_t q = li / P.x;
+    const uint32_t r = (uint32_t)(li - q * P.x);
+    return q * P.p + kept_phase(P, a, r);
+}
+
+// Last s in [0, n] with a[s] <= v (a non-decreasing, a[0] <= v).
+__device__ __forceinline__ uint32_t last_le(const uint64_t *a, uint32_t n, uint64_t v)
+{
+    uint32_t lo = 0, hi = n;              // invariant: a[lo] <= v, answer in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (a[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// First s in [0, n] with a[s] >= v, n + 1 if none.
+__device__ __forceinline__ uint32_t first_ge(const uint64_t *a, uint32_t n, uint64_t v)
+{
+    uint32_t lo = 0, hi = n + 1;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Wave64 inclusive prefix sum.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T o = __shfl_up(v, d, kWave);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Workgroup exclusive prefix sum over kBlock threads; returns the exclusive value and
+// writes the workgroup total to *total.  `sh` must hold kBlock / kWave elements.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *sh, T *total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    T inc = wave_incl_scan(v);
+    if (lane == kWave - 1) sh[wv] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; i++) {
+        const T s = sh[i];
+        if (i < wv) before += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__device__ __forceinline__ void set_status(uint32_t *status, uint32_t bits)
+{
+    if (status) atomicOr(status, bits);
+}
+
+}  // namespace gd

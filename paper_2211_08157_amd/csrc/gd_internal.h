@@ -1,0 +1,149 @@
+// Host-side launchers shared between the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gd_common.h"
+
+namespace gd {
+
+namespace trace {
+bool enabled();
+// Records HIP events on stream s around the kernel launched during its lifetime.
+class Scope {
+  public:
+    Scope(const char *name, hipStream_t s);
+    ~Scope();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_, b_;
+};
+}  // namespace trace
+
+// Launch a kernel on stream s, bracketed by trace events when tracing is on.
+#define GD_LAUNCH(kernel, grid, block, shmem, s, ...)                        \
+    do {                                                                      \
+        ::gd::trace::Scope gd_scope_(#kernel, s);                             \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, __VA_ARGS__);       \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves sub-buffers out of the caller's workspace.  With base == nullptr it only
+// measures, so the same plan code sizes and lays out the workspace.
+struct Bump {
+    char *base;
+    size_t off = 0;
+    explicit Bump(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = align_up(off, 256);
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T) + 16;   // +16: vector loads may touch a little beyond
+        return p;
+    }
+};
+
+// ---- fill / scan (gd_scan.hip) ----
+hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+// Scratch (in uint64 elements) that exclusive_scan needs for n inputs.
+size_t scan_scratch(size_t n);
+// out[i] = sum_{j<i} in[j] for i in [0, n]; in is uint32 or uint64.
+hipError_t exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *scratch,
+                              hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint64_t *out, size_t n, uint64_t *scratch,
+                              hipStream_t s);
+
+// ---- sparsify / sketch (gd_sketch.hip) ----
+enum ValMode : int { VAL_LOCAL32 = 0, VAL_GLOBAL32 = 1, VAL_SEQ64 = 2 };
+
+// Geometry of the sketch tiles for a given w.
+struct TileGeom {
+    int H;   // halo k-mers on each side (multiple of 16, >= w - 1)
+    int T;   // output k-mers per tile
+};
+TileGeom tile_geom(int w);
+
+// Device batch view used by the launchers.
+struct Batch {
+    const uint8_t *bases;
+    const uint64_t *offsets;
+    uint32_t n_seq;
+    uint64_t n_bases;
+};
+
+// Per-sequence kept counts (shift from shift[] or the uniform value) -> out[n_seq].
+hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
+                       uint32_t uniform_shift, uint64_t *kept, uint32_t *status, hipStream_t s);
+// Patterned stream (uint32 words, 16 bases each) of `words` words from pofs.
+hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
+                           uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
+                           size_t words, hipStream_t s);
+
+struct SketchOut {
+    uint64_t *keys;
+    void *vals;
+    int val_mode;
+    uint64_t *mz_offsets;   // n_seq + 1, may be null
+    uint64_t capacity;
+    uint64_t *n_out;        // may be null
+};
+// Minimizers of the patterned stream; tile_state holds tiles_bound(np_bound) words.
+size_t sketch_tiles_bound(uint64_t np_bound, int w);
+hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
+                         uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
+                         uint64_t np_bound, int k, int w, const SketchOut &o,
+                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *status,
+                         hipStream_t s);
+
+// Words of the patterned stream buffer for an upper bound on kept bases.
+inline size_t psw_words(uint64_t np_bound) { return (size_t)(np_bound / 16) + 8; }
+
+// ---- index sort (gd_sort.hip) ----
+struct SortPlan {
+    int B;                 // bucket bits (top bits of the key)
+    size_t nbuckets;
+};
+SortPlan sort_plan(uint64_t expected_records);
+// Scratch pieces the sort needs.
+struct SortWs {
+    uint32_t *hist;        // nbuckets
+    uint64_t *bofs;        // nbuckets + 1
+    uint32_t *cursor;      // nbuckets
+    uint64_t *scan_tmp;    // scan_scratch(nbuckets)
+    uint64_t *tkeys;       // capacity
+    void *tvals;           // capacity (4 or 8 bytes each)
+    uint32_t *overflow;    // nbuckets
+    uint32_t *overflow_n;  // 1
+};
+hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void *vals,
+                       int val_bytes, const uint64_t *n_ptr, uint64_t capacity, hipStream_t s);
+
+// ---- lookups, alignment, anchors (gd_seed.hip) ----
+hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
+                         const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
+                         hipStream_t s);
+
+struct AlignArgs {
+    const uint64_t *mzofs;   // shift-major: [n_shift][n_reads + 1]
+    const uint32_t *occ;     // shift-major: [n_shift][stride]
+    const uint32_t *lb;
+    const uint32_t *qval;
+    size_t stride;           // records per shift slot
+    uint32_t n_reads;
+    uint32_t n_shift;        // sketched shifts (p, or 1 for a fixed shift)
+    int32_t fixed_shift;     // -1 when the shifts 0..p-1 were sketched
+    uint32_t align_t, max_occ;
+};
+hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_slot,
+                        uint32_t *anchor_cnt, hipStream_t s);
+hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot,
+                         const uint64_t *read_off, const void *ivals, uint32_t *anchors,
+                         uint64_t capacity, uint32_t *status, hipStream_t s);
+
+}  // namespace gd

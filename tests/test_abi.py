@@ -1,0 +1,120 @@
+"""CPU-side checks of the C ABI: the built library exports every function the header
+declares, the host-only helpers follow their closed forms, and argument errors are
+rejected on the host (before anything would be enqueued on a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "godiet.h")
+
+
+def _lib():
+    import paper_2211_08157_amd as gd
+    try:
+        return gd.lib()
+    except ImportError as e:
+        pytest.fail(str(e))
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(godiet_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    names = declared_functions()
+    assert "godiet_seed" in names and "godiet_index_build" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _seqs(n_seq, n_bases):
+    from paper_2211_08157_amd.api import Seqs
+    # non-null dummy addresses: the host-side checks never dereference device pointers
+    return Seqs(0x1000, 0x2000, n_seq, n_bases)
+
+
+def test_kept_bound_and_sparsify_bytes():
+    L = _lib()
+    s = _seqs(3, 1000)
+    # floor(1000/3)*2 + 3*2 = 672 for '110'
+    assert L.godiet_kept_bound(ctypes.byref(s), b"110") == 672
+    assert L.godiet_kept_bound(ctypes.byref(s), b"1") == 1000
+    assert L.godiet_kept_bound(ctypes.byref(s), b"2") == 2**64 - 1
+    assert L.godiet_sparsify_bytes(ctypes.byref(s), b"10") == ((500 + 3) // 16 + 8) * 4
+
+
+@pytest.mark.parametrize("pattern,k,w,ok", [
+    ("10", 21, 11, True), ("", 21, 11, False), ("000", 21, 11, False), ("1a", 21, 11, False),
+    ("1" * 64, 21, 11, True), ("1" * 65, 21, 11, False), ("10", 0, 11, False),
+    ("10", 33, 11, False), ("10", 32, 11, True), ("10", 21, 0, False), ("10", 21, 257, False),
+    ("10", 1, 256, True)])
+def test_workspace_size_validates_parameters(pattern, k, w, ok):
+    from paper_2211_08157_amd.api import Params, OP_SKETCH
+    L = _lib()
+    s = _seqs(2, 500)
+    p = Params(pattern.encode(), k, w)
+    size = L.godiet_workspace_size(OP_SKETCH, ctypes.byref(s), ctypes.byref(p), 0)
+    assert (size > 0) == ok
+
+
+def test_host_rejects_bad_arguments_before_launch():
+    from paper_2211_08157_amd.api import Params, Index, SeedOpts, E_INVAL, E_WORKSPACE, E_RANGE
+    from paper_2211_08157_amd.api import E_UNSUPPORTED
+    L = _lib()
+    s = _seqs(2, 500)
+    dummy = ctypes.c_void_p(0x3000)
+    bad = Params(b"102", 21, 11)
+    good = Params(b"10", 21, 11)
+    assert L.godiet_sketch(ctypes.byref(s), ctypes.byref(bad), None, dummy, dummy, dummy, 10,
+                           dummy, 1 << 30, dummy, None) == E_INVAL
+    # workspace too small
+    assert L.godiet_sketch(ctypes.byref(s), ctypes.byref(good), None, dummy, dummy, dummy, 10,
+                           dummy, 16, dummy, None) == E_WORKSPACE
+    assert L.godiet_sketch(ctypes.byref(s), ctypes.byref(good), None, dummy, dummy, dummy, 10,
+                           None, 1 << 30, dummy, None) == E_WORKSPACE
+    # missing status word
+    assert L.godiet_sketch(ctypes.byref(s), ctypes.byref(good), None, dummy, dummy, dummy, 10,
+                           dummy, 1 << 30, None, None) == E_INVAL
+    # 32-bit index values need fewer than 2^31 bases
+    big = _seqs(1, 1 << 31)
+    assert L.godiet_index_build(ctypes.byref(big), ctypes.byref(good), dummy, dummy, 32, 10, dummy,
+                                dummy, 1 << 40, dummy, None) == E_RANGE
+    assert L.godiet_index_build(ctypes.byref(s), ctypes.byref(good), dummy, dummy, 16, 10, dummy,
+                                dummy, 1 << 40, dummy, None) == E_INVAL
+    # seeding: shift_mode outside [-1, p), 64-bit index, null output offsets
+    ix = Index(0x4000, 0x5000, 100, 32, None, 0)
+    for mode in (-2, 2):
+        assert L.godiet_seed(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(good),
+                             ctypes.byref(SeedOpts(mode, 0, 0)), dummy, 10, dummy, None, dummy,
+                             1 << 40, dummy, None) == E_INVAL
+    ix64 = Index(0x4000, 0x5000, 100, 64, None, 0)
+    assert L.godiet_seed(ctypes.byref(ix64), ctypes.byref(s), ctypes.byref(good),
+                         ctypes.byref(SeedOpts(-1, 0, 0)), dummy, 10, dummy, None, dummy, 1 << 40,
+                         dummy, None) == E_UNSUPPORTED
+    assert L.godiet_seed(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(good),
+                         ctypes.byref(SeedOpts(-1, 0, 0)), dummy, 10, None, None, dummy, 1 << 40,
+                         dummy, None) == E_INVAL
+
+
+def test_status_strings():
+    L = _lib()
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert L.godiet_status_string(code)
+
+
+def test_pack_layout():
+    import numpy as np
+    import paper_2211_08157_amd as gd
+    codes = np.array([0, 1, 2, 3, 3, 2, 1], np.uint8)
+    p = gd.pack(codes)
+    assert p[0] == (0 | 1 << 2 | 2 << 4 | 3 << 6)
+    assert p[1] == (3 | 2 << 2 | 1 << 4)
+    assert p.size % 16 == 0
+    with pytest.raises(ValueError):
+        gd.pack(np.array([4], np.uint8))
