@@ -1,0 +1,253 @@
+"""Benchmark of the sparsified-seeding hot path on one MI355X.
+
+One step = the whole path over one batch: compressed indexing of the reference
+(sparsify + sketch + sort into the seed index) followed by pattern alignment and
+compressed seeding of the read batch (sketch at every shift, lookups, shift choice,
+anchor expansion).  Inputs are generated (seeded, synthetic) and resident in HBM
+before the timed region; nothing is copied to or from the host inside it.
+
+Default workload: 100 Mbp reference with 5 % repeats, 1M x 150 bp reads (0.5 %
+substitutions, 0.05 % indels, both strands), pattern "10", k=21, w=11.
+
+Prints one JSON line: reads/s of the whole step, the dominant kernel's roofline
+(timed live with HIP events on the stream the kernels run on), sketch GB/s of the
+reference, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Session:
+    """Preallocated buffers so that a step only enqueues kernels."""
+
+    def __init__(self, gd, data, pattern, k, w):
+        import torch
+        from paper_2211_08157_amd import api
+        self.torch, self.api, self.gd = torch, api, gd
+        self.pattern, self.k, self.w = pattern, k, w
+        self.ref = gd.to_device(data["ref"], data["ref_offsets"])
+        self.reads = gd.to_device(data["reads"], data["read_offsets"])
+        self.prm = api.Params(pattern.encode(), k, w)
+        self.cref, self.creads = self.ref.c(), self.reads.c()
+        dev = "cuda"
+        # learn the index size once (same inputs every step)
+        ix = gd.index_build(self.ref, pattern, k, w)
+        self.n_index = ix.n
+        self.capacity = ix.n
+        self.ikeys = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+        self.ivals = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+        self.n_out = torch.empty(1, dtype=torch.int64, device=dev)
+        self.st_i = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_i = torch.empty(api.workspace_size(api.OP_INDEX_BUILD, self.ref, pattern, k, w,
+                                                   self.capacity), dtype=torch.uint8, device=dev)
+        a, off, _ = gd.seed(ix, self.reads, pattern, k, w)
+        self.n_anchors = int(off[-1].item())
+        self.acap = self.n_anchors
+        self.anchors = torch.empty(self.acap * 4, dtype=torch.int32, device=dev)
+        self.roff = torch.empty(self.reads.n_seq + 1, dtype=torch.int64, device=dev)
+        self.shift = torch.empty(self.reads.n_seq, dtype=torch.uint8, device=dev)
+        self.st_s = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_s = torch.empty(api.workspace_size(api.OP_SEED, self.reads, pattern, k, w, ix.n),
+                                dtype=torch.uint8, device=dev)
+        self.cix = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32, None, 0)
+        self.opts = api.SeedOpts(-1, 0, 0)
+        del ix, a, off
+        # per-shift query counts (minimizers of the reads at every shift) for byte accounting
+        self.queries = 0
+        self.read_np = 0
+        for s in range(len(pattern)):
+            kq, _, _ = gd.sketch(self.reads, pattern, k, w,
+                                 shift=np.full(self.reads.n_seq, s, np.uint32))
+            self.queries += kq.numel()
+            del kq
+        torch.cuda.synchronize()
+
+    def step(self):
+        L = self.api.lib()
+        st = ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+        r = L.godiet_index_build(ctypes.byref(self.cref), ctypes.byref(self.prm),
+                                 ctypes.c_void_p(self.ikeys.data_ptr()),
+                                 ctypes.c_void_p(self.ivals.data_ptr()), 32, self.capacity,
+                                 ctypes.c_void_p(self.n_out.data_ptr()),
+                                 ctypes.c_void_p(self.ws_i.data_ptr()), self.ws_i.numel(),
+                                 ctypes.c_void_p(self.st_i.data_ptr()), st)
+        if r != 0:
+            raise RuntimeError("godiet_index_build failed: %d" % r)
+        r = L.godiet_seed(ctypes.byref(self.cix), ctypes.byref(self.creads), ctypes.byref(self.prm),
+                          ctypes.byref(self.opts), ctypes.c_void_p(self.anchors.data_ptr()),
+                          self.acap, ctypes.c_void_p(self.roff.data_ptr()),
+                          ctypes.c_void_p(self.shift.data_ptr()),
+                          ctypes.c_void_p(self.ws_s.data_ptr()), self.ws_s.numel(),
+                          ctypes.c_void_p(self.st_s.data_ptr()), st)
+        if r != 0:
+            raise RuntimeError("godiet_seed failed: %d" % r)
+
+    def check(self):
+        self.torch.cuda.synchronize()
+        if int(self.st_i.item()) != 0 or int(self.st_s.item()) != 0:
+            raise RuntimeError("device status set: index %d seed %d" % (int(self.st_i.item()),
+                                                                         int(self.st_s.item())))
+        if int(self.n_out.item()) != self.n_index or int(self.roff[-1].item()) != self.n_anchors:
+            raise RuntimeError("output sizes changed between steps")
+
+    def digest(self):
+        h = hashlib.sha256()
+        h.update(self.ikeys.cpu().numpy().tobytes())
+        h.update(self.ivals.cpu().numpy().tobytes())
+        h.update(self.anchors.cpu().numpy().tobytes())
+        h.update(self.shift.cpu().numpy().tobytes())
+        return h.hexdigest()[:16]
+
+
+def sketch_gbps(gd, torch, seqs, pattern, k, w, reps=5):
+    """Reference sketch throughput: (ceil(L/4) + 12 bytes per minimizer) / device time of
+    the kernels of one godiet_sketch call (kept counts, scan, sparsify, sketch)."""
+    keys, vals, mz = gd.sketch(seqs, pattern, k, w)
+    m = keys.numel()
+    del keys, vals, mz
+    torch.cuda.synchronize()
+    gd.trace_dump()
+    gd.trace_enable(True)
+    for _ in range(reps):
+        gd.sketch(seqs, pattern, k, w, capacity=m)
+    torch.cuda.synchronize()
+    gd.trace_enable(False)
+    tr = gd.trace_dump()
+    ms = sum(v[1] for kname, v in tr.items() if not kname.startswith("k_fill")) / reps
+    by = (seqs.n_bases + 3) // 4 + 12 * m
+    return by / (ms * 1e-3) / 1e9, ms, m, {kn: v[1] / reps for kn, v in tr.items()}
+
+
+def cpu_baseline(data, pattern, k, w, sample_reads):
+    import oracle
+    t0 = time.perf_counter()
+    ik, iv = oracle.index_build(data["ref"], data["ref_offsets"], pattern, k, w)
+    t1 = time.perf_counter()
+    ro = data["read_offsets"][:sample_reads + 1]
+    oracle.seed(ik, iv, data["reads"][:int(ro[-1])], ro, pattern, k, w)
+    t2 = time.perf_counter()
+    n_reads = data["read_offsets"].size - 1
+    per_read = (t2 - t1) / sample_reads
+    total = (t1 - t0) + per_read * n_reads
+    return dict(value=n_reads / total, unit="reads/s", cores=1, kind="oracle",
+                sample="index of the full reference (%.1f s) + seeding of the first %d of %d "
+                       "reads (%.1f s), scaled to the full batch" % (t1 - t0, sample_reads,
+                                                                    n_reads, t2 - t1))
+
+
+def kernel_bytes(name, s):
+    """Algorithmic bytes of all launches of one kernel in one step (None if unmodelled)."""
+    ref_np = s.ref.n_bases // 2 if s.pattern == "10" else None
+    if name == "k_lookup":
+        # query key in, (lb, occ) out, and one 64-byte line of the index per query
+        return s.queries * (8 + 8 + 64)
+    if name == "k_sketch" and ref_np is not None:
+        reads_np = s.reads.n_bases // 2
+        return (ref_np + reads_np * len(s.pattern)) / 4 + 12 * (s.n_index + s.queries)
+    if name.startswith("k_bucket_sort") or name.startswith("k_scatter"):
+        return 24 * s.n_index
+    if name == "k_expand":
+        return 16 * s.n_anchors
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-reads", type=int, default=200_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for "
+              "how the path would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import datagen
+    import paper_2211_08157_amd as gd
+
+    log("[bench] generating the 100 Mbp / 1M-read workload")
+    data = datagen.workload_illumina()
+    pattern, k, w = "10", data["k"], data["w"]
+    torch.cuda.set_device(0)
+    log("[bench] uploading and sizing")
+    s = Session(gd, data, pattern, k, w)
+    log("[bench] index %d records, %d anchors, %d lookups per step" % (s.n_index, s.n_anchors,
+                                                                      s.queries))
+    for _ in range(args.warmup):
+        s.step()
+    s.check()
+    digest = s.digest()
+
+    torch.cuda.synchronize()
+    gd.trace_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gd.trace_enable(False)
+    s.check()
+    trace = gd.trace_dump()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = s.reads.n_seq / (ms_step * 1e-3)
+    log("[bench] %.3f ms/step, %.3e reads/s" % (ms_step, value))
+    per_kernel = {kname: dict(launches=n, ms_per_step=ms / args.steps)
+                  for kname, (n, ms) in sorted(trace.items(), key=lambda kv: -kv[1][1])}
+    dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
+    n_l, ms_l = trace[dom]
+    by = kernel_bytes(dom, s)
+    roof = None
+    if by is not None:
+        achieved = by * args.steps / (ms_l * 1e-3) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBPS, traffic=None,
+                    avg_launch_ms=ms_l / n_l, launches_per_step=n_l / args.steps)
+
+    gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
+    log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(data, pattern, k, w, args.cpu_sample_reads)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "reads/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "illumina-100Mbp: 100 Mbp reference (5% repeats), 1M x 150 bp "
+                               "reads, pattern 10, k=21, w=11; step = index build + seeding",
+                   "lookup": "binary_search", "global_batch": s.reads.n_seq,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "sketch_GBps": gbps, "sketch_ms": sk_ms, "sketch_bytes_rule": "ceil(L/4) + 12 B/minimizer",
+        "sketch_kernels_ms": sk_kernels,
+        "index_records": s.n_index, "anchors": s.n_anchors, "lookups_per_step": s.queries,
+        "kernels": per_kernel, "output_sha256_16": digest,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

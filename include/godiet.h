@@ -183,8 +183,9 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
 /* Kernel tracing, a profiling aid outside the method.  While enabled, every kernel launch
  * of the library is bracketed by HIP events recorded on the launch's stream.  After the
  * caller has synchronised, godiet_trace_dump writes one line "kernel launches total_ms"
- * per kernel into buf (truncated to len bytes, NUL-terminated), forgets the records and
- * returns the number of bytes the full text needs including the NUL. */
+ * per kernel into buf (truncated to len bytes, NUL-terminated) and forgets the records;
+ * with buf NULL or len 0 it only measures.  Returns the bytes the full text needs
+ * including the NUL. */
 void godiet_trace_enable(int on);
 size_t godiet_trace_dump(char *buf, size_t len);
 

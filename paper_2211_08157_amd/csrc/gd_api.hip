@@ -97,14 +97,14 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     plan_sketch_ws(b, ref->n_seq, npb, w, &o->sk);
     uint64_t expected = npb * 2 / (uint64_t)(w + 1) + 1;
     if (expected > capacity) expected = capacity;
-    o->sp = sort_plan(expected);
-    o->so.hist = b.take<uint32_t>(o->sp.nbuckets);
-    o->so.bofs = b.take<uint64_t>(o->sp.nbuckets + 1);
-    o->so.cursor = b.take<uint32_t>(o->sp.nbuckets);
-    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nbuckets));
+    o->sp = sort_plan(expected, capacity, val_bytes);
+    o->so.hist = b.take<uint32_t>(o->sp.nfine);
+    o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
+    o->so.cursor = b.take<uint32_t>(o->sp.nfine);
+    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
     o->so.tkeys = b.take<uint64_t>(capacity);
-    o->so.tvals = b.take<uint8_t>(capacity * (uint64_t)val_bytes);
-    o->so.overflow = b.take<uint32_t>(o->sp.nbuckets);
+    o->so.tvals = b.take<uint8_t>(capacity * 8);
+    o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
     o->so.overflow_n = b.take<uint32_t>(1);
 }
 
@@ -259,7 +259,7 @@ godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_par
     const int vb = val_bits / 8;
     Bump b(ws);
     IndexWs W;
-    plan_index_ws(b, ref, P, prm->w, capacity, 8, &W);
+    plan_index_ws(b, ref, P, prm->w, capacity, vb, &W);
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));

@@ -106,19 +106,21 @@ inline size_t psw_words(uint64_t np_bound) { return (size_t)(np_bound / 16) + 8;
 
 // ---- index sort (gd_sort.hip) ----
 struct SortPlan {
-    int B;                 // bucket bits (top bits of the key)
-    size_t nbuckets;
+    int Bf;                // fine-histogram bits (top bits of the key)
+    size_t nfine;          // 2^Bf fine bins
+    size_t target;         // records per coarse bucket
+    size_t ncoarse;        // coarse buckets launched
 };
-SortPlan sort_plan(uint64_t expected_records);
+SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes);
 // Scratch pieces the sort needs.
 struct SortWs {
-    uint32_t *hist;        // nbuckets
-    uint64_t *bofs;        // nbuckets + 1
-    uint32_t *cursor;      // nbuckets
-    uint64_t *scan_tmp;    // scan_scratch(nbuckets)
+    uint32_t *hist;        // nfine
+    uint64_t *fofs;        // nfine + 1
+    uint32_t *cursor;      // nfine
+    uint64_t *scan_tmp;    // scan_scratch(nfine)
     uint64_t *tkeys;       // capacity
     void *tvals;           // capacity (4 or 8 bytes each)
-    uint32_t *overflow;    // nbuckets
+    uint32_t *overflow;    // ncoarse
     uint32_t *overflow_n;  // 1
 };
 hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void *vals,

@@ -256,31 +256,46 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     // ---- stage 3: position-ordered compaction across tiles (decoupled look-back)
     uint64_t total;
     const uint64_t excl = block_excl_scan<uint64_t>((uint64_t)__popc(sel), sh_scan, &total);
-    if (t == 0) {
+    // Wave 0 publishes this tile's aggregate, then looks back over 64 predecessors per
+    // step: it adds every aggregate up to the nearest tile that already carries its
+    // inclusive prefix, and waits only while one of the tiles in between has not
+    // published yet.  The flag and the value share one 64-bit word, so relaxed atomics
+    // suffice (no other data of a predecessor is read).
+    if (t < kWave) {
         uint64_t before = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&A.tile_state[0], kFlagP | total, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&A.tile_state[tile], kFlagA | total, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int64_t look = (int64_t)tile - 1;
-            while (true) {
-                const uint64_t st = __hip_atomic_load(&A.tile_state[look], __ATOMIC_ACQUIRE,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t f = st & ~kValMask;
-                if (f == 0) { __builtin_amdgcn_s_sleep(1); continue; }
-                before += st & kValMask;
-                if (f == kFlagP) break;
-                look--;
+        if (t == 0)
+            __hip_atomic_store(&A.tile_state[tile], (tile == 0 ? kFlagP : kFlagA) | total,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t end = (int64_t)tile - 1;          // newest predecessor not yet added
+        while (end >= 0) {
+            const int64_t idx = end - t;
+            const uint64_t st = idx >= 0 ? __hip_atomic_load(&A.tile_state[idx], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)
+                                         : kFlagP;
+            const uint64_t f = st & ~kValMask;
+            const uint64_t pmask = __ballot(f == kFlagP);
+            const uint64_t zmask = __ballot(f == 0);
+            const int first_p = pmask ? __ffsll((unsigned long long)pmask) - 1 : kWave;
+            const int first_z = zmask ? __ffsll((unsigned long long)zmask) - 1 : kWave;
+            if (first_z < first_p) {              // a nearer predecessor is not ready yet
+                __builtin_amdgcn_s_sleep(2);
+                continue;
             }
-            __hip_atomic_store(&A.tile_state[tile], kFlagP | (before + total), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t v = t <= first_p ? (st & kValMask) : 0;
+            v = wave_sum<uint64_t>(v);
+            before += v;
+            if (first_p < kWave) break;
+            end -= kWave;
         }
-        sh_base = before;
-        if (tile == n_tiles - 1) {
-            if (A.n_out) *A.n_out = before + total;
-            if (before + total > A.capacity) set_status(A.status, 1u);
+        if (t == 0) {
+            if (tile != 0)
+                __hip_atomic_store(&A.tile_state[tile], kFlagP | (before + total),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh_base = before;
+            if (tile == n_tiles - 1) {
+                if (A.n_out) *A.n_out = before + total;
+                if (before + total > A.capacity) set_status(A.status, 1u);
+            }
         }
     }
     __syncthreads();

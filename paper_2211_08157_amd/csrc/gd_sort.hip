@@ -1,14 +1,21 @@
 // Sort of the reference minimizer records by (hash, val) for the seed index.
 //
-// Most-significant-digit bucketing: the top B bits of the 64-bit hash pick one of 2^B
-// buckets (hashes are uniform, so B is chosen for ~512 records per bucket).  A histogram
-// and a scan give bucket offsets, a scatter moves every record into its bucket, and one
-// workgroup per bucket finishes the bucket in LDS: a counting sort on the next 8 hash
-// bits followed by an insertion sort of each (tiny) sub-bucket, or an LDS bitonic sort
-// when a sub-bucket is large (many equal hashes).  Buckets larger than the LDS capacity
-// are listed and sorted by a fallback kernel in global memory (LDS-sorted runs merged by
-// ranking).  (hash, val) pairs are unique, so the result does not depend on the order in
-// which the scatter's atomics land.
+// Minimizer hashes are window minima, so they are NOT uniform: small values are several
+// times denser than large ones, and fixed top-bit buckets overflow at the dense end.
+// The partition is therefore data driven:
+//   1. a fine histogram over the top Bf bits (about 8 records per fine bin);
+//   2. its exclusive scan gives the start of every fine bin;
+//   3. a scatter moves each record into its fine bin (one atomic per record, spread
+//      over ~N/8 addresses);
+//   4. coarse bucket c is the run of fine bins whose start lies in [c*T, (c+1)*T), so
+//      every coarse bucket holds about T records whatever the key distribution; one
+//      workgroup loads it into LDS, sorts each fine bin (already in key order relative
+//      to the others) by insertion sort, or the whole bucket by an LDS bitonic sort when a
+//      fine bin is large (many equal hashes), and writes it back.
+// A coarse bucket larger than the LDS capacity (only possible when one fine bin holds
+// thousands of records) is listed and sorted by a fallback kernel in global memory.
+// (hash, val) pairs are unique, so the result does not depend on the order in which the
+// scatter's atomics land.
 #include "gd_internal.h"
 
 namespace gd {
@@ -16,8 +23,8 @@ namespace gd {
 namespace {
 
 // records a workgroup sorts in LDS (a power of two, so bitonic padding fits)
-template <typename V> struct Cap { static constexpr int value = sizeof(V) == 4 ? 2048 : 1024; };
-constexpr int kSmall = 24;          // sub-bucket size handled by insertion sort
+template <typename V> struct Cap { static constexpr int value = sizeof(V) == 4 ? 4096 : 2048; };
+constexpr int kSmall = 48;          // fine-bin size handled by insertion sort
 
 template <typename V>
 __device__ __forceinline__ bool rec_less(uint64_t ka, V va, uint64_t kb, V vb)
@@ -26,19 +33,19 @@ __device__ __forceinline__ bool rec_less(uint64_t ka, V va, uint64_t kb, V vb)
 }
 
 __global__ __launch_bounds__(kBlock) void k_hist(const uint64_t *keys, const uint64_t *n_ptr,
-                                                 uint64_t capacity, int B, uint32_t *hist)
+                                                 uint64_t capacity, int Bf, uint32_t *hist)
 {
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock)
-        atomicAdd(&hist[keys[i] >> (64 - B)], 1u);
+        atomicAdd(&hist[keys[i] >> (64 - Bf)], 1u);
 }
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const V *vals,
                                                     const uint64_t *n_ptr, uint64_t capacity,
-                                                    int B, const uint64_t *bofs,
+                                                    int Bf, const uint64_t *fofs,
                                                     uint32_t *cursor, uint64_t *tkeys, V *tvals)
 {
     uint64_t n = *n_ptr;
@@ -46,11 +53,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const 
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t key = keys[i];
-        const uint64_t b = key >> (64 - B);
-        const uint64_t pos = bofs[b] + atomicAdd(&cursor[b], 1u);
+        const uint64_t f = key >> (64 - Bf);
+        const uint64_t pos = fofs[f] + atomicAdd(&cursor[f], 1u);
         tkeys[pos] = key;
         tvals[pos] = vals[i];
     }
+}
+
+// Fine bins [f0, f1) of coarse bucket c (bins whose start lies in [c*T, (c+1)*T)).
+__device__ __forceinline__ void coarse_range(const uint64_t *fofs, uint32_t nfine, uint64_t c,
+                                             uint32_t target, uint32_t *f0, uint32_t *f1)
+{
+    const uint32_t a = first_ge(fofs, nfine, c * target);
+    const uint32_t b = first_ge(fofs, nfine, (c + 1) * target);
+    *f0 = a > nfine ? nfine : a;
+    *f1 = b > nfine ? nfine : b;
 }
 
 // In-LDS bitonic sort of n records, padded with maximal records to the next power of two
@@ -79,79 +96,68 @@ __device__ void lds_bitonic(uint64_t *K, V *Vv, int n)
 }
 
 template <typename V>
+__device__ void insertion_sort(uint64_t *K, V *Vv, int lo, int hi)
+{
+    for (int i = lo + 1; i < hi; i++) {
+        const uint64_t kx = K[i];
+        const V vx = Vv[i];
+        int j = i - 1;
+        while (j >= lo && rec_less(kx, vx, K[j], Vv[j])) {
+            K[j + 1] = K[j];
+            Vv[j + 1] = Vv[j];
+            j--;
+        }
+        K[j + 1] = kx;
+        Vv[j + 1] = vx;
+    }
+}
+
+template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, const V *tvals,
-                                                        const uint64_t *bofs, int B,
-                                                        uint64_t *okeys, V *ovals,
+                                                        const uint64_t *fofs, uint32_t nfine,
+                                                        uint32_t target, uint64_t *okeys, V *ovals,
                                                         uint32_t *overflow, uint32_t *overflow_n)
 {
     constexpr int kCap = Cap<V>::value;
-    __shared__ uint64_t K0[kCap], K1[kCap];
-    __shared__ V V0[kCap], V1[kCap];
-    __shared__ uint32_t cnt[256], start[257], fill[256];
+    __shared__ uint64_t K[kCap];
+    __shared__ V Vv[kCap];
     __shared__ uint32_t sh_max;
 
-    const uint32_t b = blockIdx.x;
-    const uint64_t base = bofs[b];
-    const uint64_t n64 = bofs[b + 1] - base;
+    uint32_t f0, f1;
+    coarse_range(fofs, nfine, blockIdx.x, target, &f0, &f1);
+    const uint64_t base = fofs[f0];
+    const uint64_t n64 = fofs[f1] - base;
     if (n64 == 0) return;
     if (n64 > (uint64_t)kCap) {
-        if (threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = b;
+        if (threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
         return;
     }
     const int n = (int)n64;
     const int t = threadIdx.x;
-    for (int i = t; i < n; i += kBlock) { K0[i] = tkeys[base + i]; V0[i] = tvals[base + i]; }
-    cnt[t] = 0;
-    fill[t] = 0;
     if (t == 0) sh_max = 0;
-    __syncthreads();
-    const int sh = 56 - B;           // next 8 bits below the bucket bits
-    for (int i = t; i < n; i += kBlock) atomicAdd(&cnt[(K0[i] >> sh) & 255u], 1u);
-    __syncthreads();
-    if (t < kWave) {                 // one wave scans the 256 counts
-        uint32_t c[4], s4 = 0, mx = 0;
-#pragma unroll
-        for (int j = 0; j < 4; j++) { c[j] = cnt[4 * t + j]; s4 += c[j]; mx = c[j] > mx ? c[j] : mx; }
-        const uint32_t inc = wave_incl_scan<uint32_t>(s4);
-        uint32_t run = inc - s4;
-#pragma unroll
-        for (int j = 0; j < 4; j++) { start[4 * t + j] = run; run += c[j]; }
-        if (t == kWave - 1) start[256] = inc;
-        atomicMax(&sh_max, mx);
+    for (int i = t; i < n; i += kBlock) { K[i] = tkeys[base + i]; Vv[i] = tvals[base + i]; }
+    uint32_t mx = 0;
+    for (uint32_t f = f0 + t; f < f1; f += kBlock) {
+        const uint32_t sz = (uint32_t)(fofs[f + 1] - fofs[f]);
+        mx = sz > mx ? sz : mx;
     }
     __syncthreads();
-    for (int i = t; i < n; i += kBlock) {
-        const uint32_t d = (K0[i] >> sh) & 255u;
-        const uint32_t slot = start[d] + atomicAdd(&fill[d], 1u);
-        K1[slot] = K0[i];
-        V1[slot] = V0[i];
-    }
+    if (mx > 1) atomicMax(&sh_max, mx);
     __syncthreads();
     if (sh_max <= (uint32_t)kSmall) {
-        const int lo = start[t], hi = start[t + 1];
-        for (int i = lo + 1; i < hi; i++) {
-            const uint64_t kx = K1[i];
-            const V vx = V1[i];
-            int j = i - 1;
-            while (j >= lo && rec_less(kx, vx, K1[j], V1[j])) {
-                K1[j + 1] = K1[j];
-                V1[j + 1] = V1[j];
-                j--;
-            }
-            K1[j + 1] = kx;
-            V1[j + 1] = vx;
-        }
+        for (uint32_t f = f0 + t; f < f1; f += kBlock)
+            insertion_sort<V>(K, Vv, (int)(fofs[f] - base), (int)(fofs[f + 1] - base));
         __syncthreads();
     } else {
-        lds_bitonic<V>(K1, V1, n);
+        lds_bitonic<V>(K, Vv, n);
     }
-    for (int i = t; i < n; i += kBlock) { okeys[base + i] = K1[i]; ovals[base + i] = V1[i]; }
+    for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
 }
 
-// Fallback for buckets larger than the LDS capacity: sort runs of kCap in LDS (in place in the
-// scatter buffer), then merge pairs of runs by ranking (an element's output index is its
-// index in its own run plus the number of smaller elements in the other run), ping-
-// ponging between the scatter buffer and the output.
+// Fallback for coarse buckets larger than the LDS capacity: sort runs in LDS (in place in
+// the scatter buffer), then merge pairs of runs by ranking (an element's output index is
+// its index in its own run plus the number of smaller elements in the other run),
+// ping-ponging between the scatter buffer and the output.
 template <typename V>
 __device__ uint64_t rank_in(const uint64_t *K, const V *Vv, uint64_t lo, uint64_t n, uint64_t kx,
                             V vx)
@@ -167,7 +173,8 @@ __device__ uint64_t rank_in(const uint64_t *K, const V *Vv, uint64_t lo, uint64_
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *tvals,
-                                                            const uint64_t *bofs,
+                                                            const uint64_t *fofs, uint32_t nfine,
+                                                            uint32_t target,
                                                             const uint32_t *overflow,
                                                             const uint32_t *overflow_n,
                                                             uint64_t *okeys, V *ovals)
@@ -177,9 +184,10 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *
     __shared__ V Vv[kCap];
     const uint32_t nov = *overflow_n;
     for (uint32_t oi = blockIdx.x; oi < nov; oi += gridDim.x) {
-        const uint32_t b = overflow[oi];
-        const uint64_t base = bofs[b];
-        const uint64_t n = bofs[b + 1] - base;
+        uint32_t f0, f1;
+        coarse_range(fofs, nfine, overflow[oi], target, &f0, &f1);
+        const uint64_t base = fofs[f0];
+        const uint64_t n = fofs[f1] - base;
         for (uint64_t r0 = 0; r0 < n; r0 += kCap) {
             const int m = (int)min((uint64_t)kCap, n - r0);
             for (int i = threadIdx.x; i < m; i += kBlock) {
@@ -227,30 +235,33 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
                      const uint64_t *n_ptr, uint64_t capacity, hipStream_t s)
 {
     hipError_t e;
-    if ((e = fill_u32(w.hist, 0, sp.nbuckets, s)) != hipSuccess) return e;
-    if ((e = fill_u32(w.cursor, 0, sp.nbuckets, s)) != hipSuccess) return e;
+    if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
+    if ((e = fill_u32(w.cursor, 0, sp.nfine, s)) != hipSuccess) return e;
     if ((e = fill_u32(w.overflow_n, 0, 1, s)) != hipSuccess) return e;
     const unsigned grid = 4096;
-    GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.B, w.hist);
-    if ((e = exclusive_scan_u32(w.hist, w.bofs, sp.nbuckets, w.scan_tmp, s)) != hipSuccess) return e;
-    GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity,
-                       sp.B, w.bofs, w.cursor, w.tkeys, (V *)w.tvals);
-    GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.nbuckets), dim3(kBlock), 0, s, w.tkeys,
-                       (const V *)w.tvals, w.bofs, sp.B, keys, vals, w.overflow, w.overflow_n);
-    GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.tkeys, (V *)w.tvals,
-                       w.bofs, w.overflow, w.overflow_n, keys, vals);
+    GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.Bf, w.hist);
+    if ((e = exclusive_scan_u32(w.hist, w.fofs, sp.nfine, w.scan_tmp, s)) != hipSuccess) return e;
+    GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity, sp.Bf,
+              w.fofs, w.cursor, w.tkeys, (V *)w.tvals);
+    GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s, w.tkeys,
+              (const V *)w.tvals, w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, keys, vals,
+              w.overflow, w.overflow_n);
+    GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.tkeys, (V *)w.tvals, w.fofs,
+              (uint32_t)sp.nfine, (uint32_t)sp.target, w.overflow, w.overflow_n, keys, vals);
     return hipGetLastError();
 }
 
 }  // namespace
 
-SortPlan sort_plan(uint64_t expected_records)
+SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
 {
     SortPlan sp;
-    int B = 1;
-    while (B < 22 && (expected_records >> B) > 512) B++;
-    sp.B = B;
-    sp.nbuckets = (size_t)1 << B;
+    int Bf = 4;
+    while (Bf < 26 && (expected_records >> Bf) > 8) Bf++;
+    sp.Bf = Bf;
+    sp.nfine = (size_t)1 << Bf;
+    sp.target = val_bytes == 4 ? 2048 : 1024;
+    sp.ncoarse = (size_t)(capacity / sp.target) + 2;
     return sp;
 }
 

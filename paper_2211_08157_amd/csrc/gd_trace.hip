@@ -55,6 +55,7 @@ void godiet_trace_enable(int on) { gd::trace::g_on.store(on != 0); }
 size_t godiet_trace_dump(char *buf, size_t len)
 {
     using namespace gd::trace;
+    const bool consume = buf && len > 0;     // a NULL buffer only measures
     std::map<std::string, std::pair<uint64_t, double>> agg;
     {
         std::lock_guard<std::mutex> g(g_mu);
@@ -64,10 +65,12 @@ size_t godiet_trace_dump(char *buf, size_t len)
             auto &e = agg[r.name];
             e.first += 1;
             e.second += ms;
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
+            if (consume) {
+                hipEventDestroy(r.a);
+                hipEventDestroy(r.b);
+            }
         }
-        g_recs.clear();
+        if (consume) g_recs.clear();
     }
     std::string out;
     char line[256];
@@ -76,7 +79,7 @@ size_t godiet_trace_dump(char *buf, size_t len)
                  (unsigned long long)kv.second.first, kv.second.second);
         out += line;
     }
-    if (buf && len > 0) {
+    if (consume) {
         const size_t n = out.size() < len - 1 ? out.size() : len - 1;
         memcpy(buf, out.data(), n);
         buf[n] = 0;
