@@ -104,6 +104,7 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
     o->so.tkeys = b.take<uint64_t>(capacity);
     o->so.tvals = b.take<uint8_t>(capacity * 8);
+    o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
     o->so.overflow_n = b.take<uint32_t>(1);
 }
@@ -114,6 +115,7 @@ struct SeedWs {
     uint64_t *qkeys;      // n_shift * stride
     uint32_t *qvals, *lb, *occ;
     uint32_t *slot, *cnt;
+    uint32_t *long_ids, *long_n;
     uint64_t *scan;
     size_t stride;
 };
@@ -132,6 +134,8 @@ void plan_seed_ws(Bump &b, const godiet_seqs *reads, const Pattern &P, int w, ui
     o->occ = b.take<uint32_t>(o->stride * n_shift);
     o->slot = b.take<uint32_t>(nr + 1);
     o->cnt = b.take<uint32_t>(nr + 1);
+    o->long_ids = b.take<uint32_t>(nr + 1);
+    o->long_n = b.take<uint32_t>(1);
     o->scan = b.take<uint64_t>(scan_scratch(nr + 1));
 }
 
@@ -317,10 +321,10 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
     A.fixed_shift = opts->shift_mode;
     A.align_t = opts->align_t;
     A.max_occ = opts->max_occ;
-    GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, stream));
+    GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, W.long_ids, W.long_n, stream));
     GD_TRY(exclusive_scan_u32(W.cnt, read_anchor_off, nr, W.scan, stream));
     GD_TRY(launch_expand(A, W.slot, read_anchor_off, index->vals, (uint32_t *)anchors, capacity,
-                         status, stream));
+                         status, W.long_ids, W.long_n, stream));
     return GODIET_OK;
 }
 

@@ -120,6 +120,7 @@ struct SortWs {
     uint64_t *scan_tmp;    // scan_scratch(nfine)
     uint64_t *tkeys;       // capacity
     void *tvals;           // capacity (4 or 8 bytes each)
+    uint32_t *cstart;      // ncoarse + 1: first fine bin of each coarse bucket
     uint32_t *overflow;    // ncoarse
     uint32_t *overflow_n;  // 1
 };
@@ -142,10 +143,13 @@ struct AlignArgs {
     int32_t fixed_shift;     // -1 when the shifts 0..p-1 were sketched
     uint32_t align_t, max_occ;
 };
+// Shift choice and per-read anchor counts; reads with many records go to long_ids
+// (n_reads entries) for a wave-per-read pass, long_n counts them.
 hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_slot,
-                        uint32_t *anchor_cnt, hipStream_t s);
+                        uint32_t *anchor_cnt, uint32_t *long_ids, uint32_t *long_n, hipStream_t s);
 hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot,
                          const uint64_t *read_off, const void *ivals, uint32_t *anchors,
-                         uint64_t capacity, uint32_t *status, hipStream_t s);
+                         uint64_t capacity, uint32_t *status, const uint32_t *long_ids,
+                         const uint32_t *long_n, hipStream_t s);
 
 }  // namespace gd

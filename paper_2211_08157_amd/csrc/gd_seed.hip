@@ -56,85 +56,177 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
 }
 
 constexpr int kReadsPerBlock = kBlock / kWave;
+// Reads whose minimizer records (summed over the sketched shifts) exceed this are handled
+// by one wave each; shorter reads by one thread each.
+constexpr uint64_t kShortRecords = 192;
 
-__global__ __launch_bounds__(kBlock) void k_align(AlignArgs A, uint8_t *shift_out,
-                                                  uint32_t *shift_slot, uint32_t *anchor_cnt)
+// Records of read r at shift slot s: [mzofs[s][r], mzofs[s][r+1]).
+__device__ __forceinline__ uint64_t rec_beg(const AlignArgs &A, uint32_t s, uint32_t r)
 {
-    const uint32_t r = blockIdx.x * kReadsPerBlock + threadIdx.x / kWave;
+    return A.mzofs[s * ((size_t)A.n_reads + 1) + r];
+}
+
+__device__ __forceinline__ uint64_t read_records(const AlignArgs &A, uint32_t r)
+{
+    uint64_t n = 0;
+    for (uint32_t s = 0; s < A.n_shift; s++) n += rec_beg(A, s, r + 1) - rec_beg(A, s, r);
+    return n;
+}
+
+__device__ __forceinline__ uint32_t keep_occ(const AlignArgs &A, uint32_t o)
+{
+    return (A.max_occ == 0 || o < A.max_occ) ? o : 0u;
+}
+
+// n* = min over the sketched shifts of the record count, capped at t.
+__device__ __forceinline__ uint64_t align_nstar(const AlignArgs &A, uint32_t r)
+{
+    uint64_t nstar = kMax64;
+    for (uint32_t s = 0; s < A.n_shift; s++) {
+        const uint64_t c = rec_beg(A, s, r + 1) - rec_beg(A, s, r);
+        nstar = c < nstar ? c : nstar;
+    }
+    if (A.align_t > 0 && (uint64_t)A.align_t < nstar) nstar = A.align_t;
+    return nstar;
+}
+
+__device__ __forceinline__ void align_store(const AlignArgs &A, uint32_t r, uint32_t slot,
+                                            uint64_t cnt, uint8_t *shift_out, uint32_t *shift_slot,
+                                            uint32_t *anchor_cnt)
+{
+    shift_slot[r] = slot;
+    if (shift_out) shift_out[r] = (uint8_t)(A.fixed_shift >= 0 ? (uint32_t)A.fixed_shift : slot);
+    anchor_cnt[r] = (uint32_t)cnt;
+}
+
+// One thread per read; reads with many records are appended to long_ids instead.
+__global__ __launch_bounds__(kBlock) void k_align(AlignArgs A, uint8_t *shift_out,
+                                                  uint32_t *shift_slot, uint32_t *anchor_cnt,
+                                                  uint32_t *long_ids, uint32_t *long_n)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= A.n_reads) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const size_t mzs = (size_t)A.n_reads + 1;
+    if (read_records(A, r) > kShortRecords) {
+        long_ids[atomicAdd(long_n, 1u)] = r;
+        return;
+    }
     uint32_t slot = 0;
     if (A.n_shift > 1) {
-        uint64_t nstar = kMax64;
-        for (uint32_t s = 0; s < A.n_shift; s++) {
-            const uint64_t c = A.mzofs[s * mzs + r + 1] - A.mzofs[s * mzs + r];
-            nstar = c < nstar ? c : nstar;
-        }
-        if (A.align_t > 0 && (uint64_t)A.align_t < nstar) nstar = A.align_t;
+        const uint64_t nstar = align_nstar(A, r);
         uint64_t best = 0;
         for (uint32_t s = 0; s < A.n_shift; s++) {
-            const uint64_t beg = A.mzofs[s * mzs + r];
-            const uint32_t *occ = A.occ + s * A.stride + beg;
+            const uint32_t *occ = A.occ + s * A.stride + rec_beg(A, s, r);
             uint64_t sc = 0;
-            for (uint64_t j = lane; j < nstar; j += kWave) {
-                const uint32_t o = occ[j];
-                if (A.max_occ == 0 || o < A.max_occ) sc += o;
-            }
-            sc = wave_sum<uint64_t>(sc);
+            for (uint64_t j = 0; j < nstar; j++) sc += keep_occ(A, occ[j]);
             if (sc > best) { best = sc; slot = s; }
         }
     }
-    const uint64_t beg = A.mzofs[slot * mzs + r], end = A.mzofs[slot * mzs + r + 1];
+    const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
     const uint32_t *occ = A.occ + slot * A.stride;
     uint64_t cnt = 0;
-    for (uint64_t j = beg + lane; j < end; j += kWave) {
-        const uint32_t o = occ[j];
-        if (A.max_occ == 0 || o < A.max_occ) cnt += o;
-    }
-    cnt = wave_sum<uint64_t>(cnt);
-    if (lane == 0) {
-        shift_slot[r] = slot;
-        if (shift_out) shift_out[r] = (uint8_t)(A.fixed_shift >= 0 ? (uint32_t)A.fixed_shift : slot);
-        anchor_cnt[r] = (uint32_t)cnt;
+    for (uint64_t j = beg; j < end; j++) cnt += keep_occ(A, occ[j]);
+    align_store(A, r, slot, cnt, shift_out, shift_slot, anchor_cnt);
+}
+
+// One wave per read of the long list (grid-stride over the list).
+__global__ __launch_bounds__(kBlock) void k_align_long(AlignArgs A, uint8_t *shift_out,
+                                                       uint32_t *shift_slot, uint32_t *anchor_cnt,
+                                                       const uint32_t *long_ids,
+                                                       const uint32_t *long_n)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nl = *long_n;
+    for (uint32_t li = blockIdx.x * kReadsPerBlock + threadIdx.x / kWave; li < nl;
+         li += gridDim.x * kReadsPerBlock) {
+        const uint32_t r = long_ids[li];
+        uint32_t slot = 0;
+        if (A.n_shift > 1) {
+            const uint64_t nstar = align_nstar(A, r);
+            uint64_t best = 0;
+            for (uint32_t s = 0; s < A.n_shift; s++) {
+                const uint32_t *occ = A.occ + s * A.stride + rec_beg(A, s, r);
+                uint64_t sc = 0;
+                for (uint64_t j = lane; j < nstar; j += kWave) sc += keep_occ(A, occ[j]);
+                sc = wave_sum<uint64_t>(sc);
+                if (sc > best) { best = sc; slot = s; }
+            }
+        }
+        const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
+        const uint32_t *occ = A.occ + slot * A.stride;
+        uint64_t cnt = 0;
+        for (uint64_t j = beg + lane; j < end; j += kWave) cnt += keep_occ(A, occ[j]);
+        cnt = wave_sum<uint64_t>(cnt);
+        if (lane == 0) align_store(A, r, slot, cnt, shift_out, shift_slot, anchor_cnt);
     }
 }
 
+// One thread per short read: its anchors in (qpos, index order) into a contiguous run.
 __global__ __launch_bounds__(kBlock) void k_expand(AlignArgs A, const uint32_t *shift_slot,
                                                    const uint64_t *read_off, const uint32_t *ivals,
                                                    uint4 *anchors, uint64_t capacity,
                                                    uint32_t *status)
 {
-    const uint32_t r = blockIdx.x * kReadsPerBlock + threadIdx.x / kWave;
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= A.n_reads) return;
-    const int lane = threadIdx.x & (kWave - 1);
     if (read_off[A.n_reads] > capacity) {
-        if (r == 0 && lane == 0) set_status(status, 1u);
+        if (r == 0) set_status(status, 1u);
         return;
     }
-    const size_t mzs = (size_t)A.n_reads + 1;
+    if (read_records(A, r) > kShortRecords) return;          // expanded by k_expand_long
     const uint32_t slot = shift_slot[r];
-    const uint64_t beg = A.mzofs[slot * mzs + r], end = A.mzofs[slot * mzs + r + 1];
+    const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
     const uint32_t *occ = A.occ + slot * A.stride;
     const uint32_t *lb = A.lb + slot * A.stride;
     const uint32_t *qv = A.qval + slot * A.stride;
     uint64_t out = read_off[r];
-    for (uint64_t j0 = beg; j0 < end; j0 += kWave) {
-        const uint64_t j = j0 + lane;
-        uint32_t o = 0, l = 0, q = 0;
-        if (j < end) {
-            o = occ[j];
-            if (A.max_occ != 0 && o >= A.max_occ) o = 0;
-            l = lb[j];
-            q = qv[j];
-        }
-        const uint32_t incl = wave_incl_scan<uint32_t>(o);
-        const uint64_t at = out + (incl - o);
+    for (uint64_t j = beg; j < end; j++) {
+        const uint32_t o = keep_occ(A, occ[j]);
+        const uint32_t l = lb[j], q = qv[j];
         for (uint32_t e = 0; e < o; e++) {
             const uint32_t v = ivals[l + e];
-            anchors[at + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
+            anchors[out + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
         }
-        out += __shfl(incl, kWave - 1, kWave);
+        out += o;
+    }
+}
+
+// One wave per read of the long list: lanes stride over the records, a wave scan places
+// each record's anchors.
+__global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint32_t *shift_slot,
+                                                        const uint64_t *read_off,
+                                                        const uint32_t *ivals, uint4 *anchors,
+                                                        uint64_t capacity,
+                                                        const uint32_t *long_ids,
+                                                        const uint32_t *long_n)
+{
+    if (read_off[A.n_reads] > capacity) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nl = *long_n;
+    for (uint32_t li = blockIdx.x * kReadsPerBlock + threadIdx.x / kWave; li < nl;
+         li += gridDim.x * kReadsPerBlock) {
+        const uint32_t r = long_ids[li];
+        const uint32_t slot = shift_slot[r];
+        const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
+        const uint32_t *occ = A.occ + slot * A.stride;
+        const uint32_t *lb = A.lb + slot * A.stride;
+        const uint32_t *qv = A.qval + slot * A.stride;
+        uint64_t out = read_off[r];
+        for (uint64_t j0 = beg; j0 < end; j0 += kWave) {
+            const uint64_t j = j0 + lane;
+            uint32_t o = 0, l = 0, q = 0;
+            if (j < end) {
+                o = keep_occ(A, occ[j]);
+                l = lb[j];
+                q = qv[j];
+            }
+            const uint32_t incl = wave_incl_scan<uint32_t>(o);
+            const uint64_t at = out + (incl - o);
+            for (uint32_t e = 0; e < o; e++) {
+                const uint32_t v = ivals[l + e];
+                anchors[at + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
+            }
+            out += __shfl(incl, kWave - 1, kWave);
+        }
     }
 }
 
@@ -153,23 +245,30 @@ hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
 }
 
 hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_slot,
-                        uint32_t *anchor_cnt, hipStream_t s)
+                        uint32_t *anchor_cnt, uint32_t *long_ids, uint32_t *long_n, hipStream_t s)
 {
     if (a.n_reads == 0) return hipSuccess;
-    const unsigned blocks = (a.n_reads + kReadsPerBlock - 1) / kReadsPerBlock;
-    GD_LAUNCH(k_align, dim3(blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot,
-                       anchor_cnt);
+    hipError_t e = fill_u32(long_n, 0, 1, s);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
+    GD_LAUNCH(k_align, dim3(blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot, anchor_cnt,
+              long_ids, long_n);
+    GD_LAUNCH(k_align_long, dim3(1024), dim3(kBlock), 0, s, a, shift_out, shift_slot, anchor_cnt,
+              (const uint32_t *)long_ids, (const uint32_t *)long_n);
     return hipGetLastError();
 }
 
 hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot, const uint64_t *read_off,
                          const void *ivals, uint32_t *anchors, uint64_t capacity,
-                         uint32_t *status, hipStream_t s)
+                         uint32_t *status, const uint32_t *long_ids, const uint32_t *long_n,
+                         hipStream_t s)
 {
     if (a.n_reads == 0) return hipSuccess;
-    const unsigned blocks = (a.n_reads + kReadsPerBlock - 1) / kReadsPerBlock;
+    const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
     GD_LAUNCH(k_expand, dim3(blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
-                       (const uint32_t *)ivals, (uint4 *)anchors, capacity, status);
+              (const uint32_t *)ivals, (uint4 *)anchors, capacity, status);
+    GD_LAUNCH(k_expand_long, dim3(1024), dim3(kBlock), 0, s, a, shift_slot, read_off,
+              (const uint32_t *)ivals, (uint4 *)anchors, capacity, long_ids, long_n);
     return hipGetLastError();
 }
 

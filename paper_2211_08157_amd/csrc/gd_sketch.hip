@@ -40,6 +40,65 @@ __device__ __forceinline__ uint32_t seq_shift(const uint32_t *shift, uint32_t un
     return shift ? shift[s] : uniform;
 }
 
+// Sequence boundaries of one workgroup's range of patterned positions, cached in LDS.
+// A batch of reads puts tens of sequences into every tile; looking each position's
+// sequence up with a binary search over millions of global offsets would dominate.
+constexpr int kSeqCache = 512;
+
+struct SeqCache {
+    const uint64_t *pofs;   // global boundaries, n_seq + 1 entries
+    uint32_t n_seq;
+    const uint64_t *sh;     // LDS copy of pofs[lo .. lo + n]
+    uint32_t lo, n;         // n == 0: no cache
+    __device__ __forceinline__ uint64_t at(uint32_t s) const
+    {
+        const uint32_t d = s - lo;
+        return d <= n ? sh[d] : pofs[s];
+    }
+    // last s with pofs[s] <= j (j < pofs[n_seq])
+    __device__ __forceinline__ uint32_t find(uint64_t j) const
+    {
+        if (n > 0 && j >= sh[0] && j < sh[n]) {
+            uint32_t a = 0, b = n;          // sh[a] <= j < sh[b]
+            while (b - a > 1) {
+                const uint32_t m = (a + b) >> 1;
+                if (sh[m] <= j) a = m; else b = m;
+            }
+            return lo + a;
+        }
+        return last_le(pofs, n_seq, j);
+    }
+};
+
+// Fill the cache for positions [jlo, jhi] (all threads of the workgroup call this).
+__device__ __forceinline__ SeqCache seq_cache(const uint64_t *pofs, uint32_t n_seq, uint64_t jlo,
+                                              uint64_t jhi, uint64_t *sh, uint32_t *sh_lohi)
+{
+    if (threadIdx.x == 0) {
+        const uint64_t np = pofs[n_seq];
+        uint32_t lo = 0, n = 0;
+        if (np > 0 && jlo < np) {
+            if (jhi >= np) jhi = np - 1;
+            lo = last_le(pofs, n_seq, jlo);
+            const uint32_t hi = last_le(pofs, n_seq, jhi);
+            n = hi - lo + 1;                 // sequences lo..hi, boundaries lo..hi+1
+            if (n + 1 > (uint32_t)kSeqCache) n = 0;
+        }
+        sh_lohi[0] = lo;
+        sh_lohi[1] = n;
+    }
+    __syncthreads();
+    SeqCache c;
+    c.pofs = pofs;
+    c.n_seq = n_seq;
+    c.sh = sh;
+    c.lo = sh_lohi[0];
+    c.n = sh_lohi[1];
+    for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += kBlock) sh[i] = pofs[c.lo + i];
+    __syncthreads();
+    return c;
+}
+
 // ---------------------------------------------------------------- kept counts
 
 __global__ __launch_bounds__(kBlock) void k_kept(const uint64_t *offsets, uint32_t n_seq,
@@ -61,33 +120,64 @@ __device__ __forceinline__ uint32_t base_at(const uint8_t *bases, uint64_t g)
     return (bases[g >> 2] >> ((g & 3) * 2)) & 3u;
 }
 
+// Bases 2i (i = 0..15) of a 64-bit run of 32 bases: the kept half under a period-2
+// pattern, compacted into one 16-base word.
+__device__ __forceinline__ uint32_t unzip_even(uint64_t y)
+{
+    y &= 0x3333333333333333ull;
+    y = (y | (y >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    y = (y | (y >> 4)) & 0x00FF00FF00FF00FFull;
+    y = (y | (y >> 8)) & 0x0000FFFF0000FFFFull;
+    y = (y | (y >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)y;
+}
+
 // One thread per output word: gathers the 16 kept bases [16q, 16q+16) of the batch.
+// nbytes = ceil(n_bases / 4), the readable size of `bases`.
 __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const uint64_t *offsets,
                                                      uint32_t n_seq, Pattern P,
                                                      const uint32_t *shift, uint32_t uniform,
                                                      const uint64_t *pofs, uint32_t *psw,
-                                                     size_t words)
+                                                     size_t words, uint64_t nbytes)
 {
+    __shared__ uint64_t sh_pofs[kSeqCache];
+    __shared__ uint32_t sh_lohi[2];
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kBlock * 16;
+    const SeqCache C = seq_cache(pofs, n_seq, blk0, blk0 + kBlock * 16 - 1, sh_pofs, sh_lohi);
     const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
     if (q >= words) return;
     const uint64_t np = pofs[n_seq];
     const uint64_t j0 = (uint64_t)q * 16;
     uint32_t word = 0;
     if (j0 < np) {
-        uint32_t s = last_le(pofs, n_seq, j0);
-        uint64_t end = pofs[s + 1];
-        while (j0 >= end) { s++; end = pofs[s + 1]; }
+        uint32_t s = C.find(j0);
+        uint64_t end = C.at(s + 1);
+        while (j0 >= end) { s++; end = C.at(s + 1); }
         uint32_t a = seq_shift(shift, uniform, s);
         if (a >= P.p) a = 0;
-        uint64_t li = j0 - pofs[s];
+        uint64_t li = j0 - C.at(s);
         uint64_t per = li / P.x;                 // period index
         uint32_t r = (uint32_t)(li - per * P.x); // rank within the period
         uint64_t obase = offsets[s];
+        // period 2, one kept base: the 16 kept bases are every other base of a run of 32
+        if (P.p == 2 && P.x == 1 && j0 + 16 <= end) {
+            const uint64_t o0 = obase + per * 2 + kept_phase(P, a, 0);
+            const uint64_t g = o0 >> 4;
+            if ((g + 3) * 4 <= nbytes) {
+                const uint32_t *wd = (const uint32_t *)bases;
+                const uint32_t W0 = wd[g], W1 = wd[g + 1], W2 = wd[g + 2];
+                const int sh = 2 * (int)(o0 & 15);
+                const uint32_t lo = __builtin_amdgcn_alignbit(W1, W0, sh);
+                const uint32_t hi = __builtin_amdgcn_alignbit(W2, W1, sh);
+                psw[q] = unzip_even(((uint64_t)hi << 32) | lo);
+                return;
+            }
+        }
         for (int u = 0; u < 16; u++) {
             const uint64_t j = j0 + u;
             if (j >= np) break;
             if (j >= end) {
-                while (j >= end) { s++; end = pofs[s + 1]; }
+                while (j >= end) { s++; end = C.at(s + 1); }
                 a = seq_shift(shift, uniform, s);
                 if (a >= P.p) a = 0;
                 per = 0;
@@ -106,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
 
 constexpr int kE = kBlock * 16;     // LDS positions per tile (T + 2H)
 constexpr uint64_t kFlagA = 1ull << 62, kFlagP = 2ull << 62, kValMask = (1ull << 62) - 1;
+constexpr int kMaxRegW = 17;        // largest w handled by the register path
 
 struct SketchArgs {
     const uint32_t *psw;
@@ -115,6 +206,7 @@ struct SketchArgs {
     uint32_t uniform;
     uint32_t n_seq;
     Pattern P;
+    double inv_x;                   // 1 / x, for the period division
     int k, w, H, T;
     uint64_t kmask;
     uint64_t *keys;
@@ -128,29 +220,207 @@ struct SketchArgs {
     uint32_t *status;
 };
 
-// Reverse the order of the 2-bit groups of a 64-bit word.
-__device__ __forceinline__ uint64_t rev_groups(uint64_t x)
+// A 16-base word with base 0 in the low bits turned into one with base 0 in the top
+// bits (bit reversal, then the two bits of every base swapped back).
+__device__ __forceinline__ uint32_t msb_first(uint32_t w)
 {
-    x = __builtin_bitreverse64(x);
-    return ((x >> 1) & 0x5555555555555555ull) | ((x & 0x5555555555555555ull) << 1);
+    w = __builtin_bitreverse32(w);
+    return ((w >> 1) & 0x55555555u) | ((w & 0x55555555u) << 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
+// 64 bits of the patterned stream starting at base u of the chunk, base u in the low bits
+// (the reverse-complement code is its complement), from LSB-first words w0..w2.
+__device__ __forceinline__ uint64_t kmer_lsb(uint32_t w0, uint32_t w1, uint32_t w2, int u)
 {
-    __shared__ uint64_t sh_m[kE];     // work array of the sliding reductions
-    __shared__ uint64_t sh_scan[kBlock / kWave];
-    __shared__ uint32_t sh_tile;
-    __shared__ uint64_t sh_base;
+    const uint32_t lo = u == 0 ? w0 : __builtin_amdgcn_alignbit(w1, w0, 2 * u);
+    const uint32_t hi = u == 0 ? w1 : __builtin_amdgcn_alignbit(w2, w1, 2 * u);
+    return ((uint64_t)hi << 32) | lo;
+}
 
+// 64 bits of the patterned stream starting at base u, base u in the top bits (shifted
+// right by 64 - 2k it is the forward code), from MSB-first words m0..m2.
+__device__ __forceinline__ uint64_t kmer_msb(uint32_t m0, uint32_t m1, uint32_t m2, int u)
+{
+    const uint32_t hi = u == 0 ? m0 : __builtin_amdgcn_alignbit(m0, m1, 32 - 2 * u);
+    const uint32_t lo = u == 0 ? m1 : __builtin_amdgcn_alignbit(m1, m2, 32 - 2 * u);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// (li / x, li % x) without an integer divide: a double estimate, corrected.
+__device__ __forceinline__ void div_x(uint64_t li, uint32_t x, double inv_x, uint64_t *q,
+                                      uint32_t *r)
+{
+    int64_t qq = (int64_t)((double)li * inv_x);
+    int64_t rr = (int64_t)li - qq * (int64_t)x;
+    while (rr < 0) { qq--; rr += x; }
+    while (rr >= (int64_t)x) { qq++; rr -= x; }
+    *q = (uint64_t)qq;
+    *r = (uint32_t)rr;
+}
+
+// Minimizer selection for the 16 positions of this thread, w = W known at compile time.
+// Window minima of the windows starting in the chunk come from the chunk's suffix minima
+// and the next chunk's prefix minima (windows reaching into it) or from a split at a
+// position common to all windows inside the chunk; the opening (max over the windows
+// containing a position) is built the same way from the previous chunk's suffix maxima.
+// ex is an LDS array of kE words used for the two neighbour exchanges.
+template <int W>
+__device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], const uint32_t (&fv)[16],
+                                               uint64_t *ex, bool owner)
+{
     const int t = threadIdx.x;
-    const int H = A.H, T = A.T, w = A.w, k = A.k;
-    const uint64_t np = A.pofs[A.n_seq];
-    const uint64_t n_tiles = np / (uint64_t)T + 1;     // the last tile covers position np
-
-    if (t == 0) sh_tile = atomicAdd(A.tile_counter, 1u);
+    uint64_t P[16], S[16], mw[16];
+    P[0] = v[0];
+#pragma unroll
+    for (int u = 1; u < 16; u++) P[u] = min(P[u - 1], v[u]);
+#pragma unroll
+    for (int u = 0; u < W - 1; u++) ex[u * kBlock + t] = P[u];
     __syncthreads();
-    const uint64_t tile = sh_tile;
-    if (tile >= n_tiles) return;
+    uint64_t Pn[W > 1 ? W - 1 : 1];
+#pragma unroll
+    for (int u = 0; u < W - 1; u++) Pn[u] = t + 1 < kBlock ? ex[u * kBlock + t + 1] : kMax64;
+    __syncthreads();
+    S[15] = v[15];
+#pragma unroll
+    for (int u = 14; u >= 0; u--) S[u] = min(S[u + 1], v[u]);
+    // windows reaching into the next chunk
+#pragma unroll
+    for (int s = (17 - W > 0 ? 17 - W : 0); s < 16; s++) mw[s] = W == 1 ? v[s] : min(S[s], Pn[s + W - 1 - 16]);
+    // windows inside the chunk (none when W == 17)
+    if constexpr (W >= 9 && W <= 16) {
+        constexpr int m = 16 - W;               // contained in every inner window
+        uint64_t SA[m + 1], PB[16];
+        SA[m] = v[m];
+#pragma unroll
+        for (int s = m - 1; s >= 0; s--) SA[s] = min(SA[s + 1], v[s]);
+        PB[m + 1] = v[m + 1];
+#pragma unroll
+        for (int e = m + 2; e < 16; e++) PB[e] = min(PB[e - 1], v[e]);
+#pragma unroll
+        for (int s = 0; s <= m; s++) mw[s] = min(SA[s], PB[s + W - 1]);
+    } else if constexpr (W <= 8) {
+#pragma unroll
+        for (int s = 0; s <= 16 - W; s++) {
+            uint64_t x = v[s];
+#pragma unroll
+            for (int d = 1; d < W; d++) x = min(x, v[s + d]);
+            mw[s] = x;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; s++) mw[s] = (fv[s] & 2u) ? mw[s] : 0;
+
+    // opening
+    uint64_t SM[16], PM[16], op[16];
+    SM[15] = mw[15];
+#pragma unroll
+    for (int u = 14; u >= 0; u--) SM[u] = max(SM[u + 1], mw[u]);
+#pragma unroll
+    for (int u = 17 - W; u < 16; u++) ex[u * kBlock + t] = SM[u];
+    __syncthreads();
+    uint64_t Sp[W > 1 ? W - 1 : 1];
+#pragma unroll
+    for (int j = 0; j < W - 1; j++) Sp[j] = t > 0 ? ex[(17 - W + j) * kBlock + t - 1] : 0;
+    PM[0] = mw[0];
+#pragma unroll
+    for (int u = 1; u < 16; u++) PM[u] = max(PM[u - 1], mw[u]);
+#pragma unroll
+    for (int u = 0; u < (W - 1 < 16 ? W - 1 : 16); u++) op[u] = max(PM[u], Sp[u]);
+    if constexpr (W >= 9 && W <= 16) {
+        constexpr int m = W - 1;                // contained in every inner range
+        uint64_t SA[m + 1], PB[16];
+        SA[m] = mw[m];
+#pragma unroll
+        for (int s = m - 1; s >= 0; s--) SA[s] = max(SA[s + 1], mw[s]);
+        if constexpr (m < 16) op[m] = SA[0];
+        if constexpr (m + 1 < 16) {
+            PB[m + 1] = mw[m + 1];
+#pragma unroll
+            for (int e = m + 2; e < 16; e++) PB[e] = max(PB[e - 1], mw[e]);
+#pragma unroll
+            for (int u = m + 1; u < 16; u++) op[u] = max(SA[u - W + 1], PB[u]);
+        }
+    } else if constexpr (W <= 8) {
+#pragma unroll
+        for (int u = (W - 1 > 0 ? W - 1 : 0); u < 16; u++) {
+            uint64_t x = mw[u];
+#pragma unroll
+            for (int d = 1; d < W; d++) x = max(x, mw[u - d]);
+            op[u] = x;
+        }
+    }
+    uint32_t sel = 0;
+#pragma unroll
+    for (int u = 0; u < 16; u++)
+        if (owner && (fv[u] & 1u) && v[u] == op[u]) sel |= 1u << u;
+    return sel;
+}
+
+// Any w: window minima and the opening by doubling in LDS (ex holds kE words).
+__device__ uint32_t select_lds(const uint64_t (&v)[16], const uint32_t (&fv)[16], uint64_t *ex,
+                               int w, bool owner)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 16; u++) ex[16 * t + u] = v[u];
+    __syncthreads();
+    int q2 = 1;                       // largest power of two <= w
+    while (q2 * 2 <= w) q2 *= 2;
+    const int r2 = w - q2;
+    for (int d = 1; d < q2; d *= 2) {
+        uint64_t x[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int i = 16 * t + u;
+            x[u] = min(ex[i], i + d < kE ? ex[i + d] : kMax64);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; u++) ex[16 * t + u] = x[u];
+        __syncthreads();
+    }
+    {
+        uint64_t x[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int i = 16 * t + u;
+            x[u] = (fv[u] & 2u) ? min(ex[i], i + r2 < kE ? ex[i + r2] : kMax64) : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; u++) ex[16 * t + u] = x[u];
+        __syncthreads();
+    }
+    for (int d = 1; d < q2; d *= 2) {
+        uint64_t x[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int i = 16 * t + u;
+            x[u] = max(ex[i], i - d >= 0 ? ex[i - d] : 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; u++) ex[16 * t + u] = x[u];
+        __syncthreads();
+    }
+    uint32_t sel = 0;
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int i = 16 * t + u;
+        const uint64_t opened = max(ex[i], i - r2 >= 0 ? ex[i - r2] : 0);
+        if (owner && (fv[u] & 1u) && v[u] == opened) sel |= 1u << u;
+    }
+    return sel;
+}
+
+// One tile: the T positions [tile*T, tile*T + T) of the batch's patterned stream.
+template <int W>
+__device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
+                                            uint64_t n_tiles, uint64_t *ex, uint64_t *sh_scan,
+                                            uint64_t *sh_base_p, const SeqCache &C)
+{
+    const int t = threadIdx.x;
+    const int H = A.H, T = A.T, w = W > 0 ? W : A.w, k = A.k;
 
     const int64_t j0 = (int64_t)(tile * (uint64_t)T);
     const int64_t jc = j0 - H + 16 * t;                  // first position of this chunk
@@ -165,93 +435,77 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     uint32_t seq0 = 0;
     uint64_t beg0 = 0, end0 = 0;
     if (jc >= 0 && (uint64_t)jc < np) {
-        uint32_t seq = last_le(A.pofs, A.n_seq, (uint64_t)jc);
-        uint64_t seq_beg = A.pofs[seq], seq_end = A.pofs[seq + 1];
-        while ((uint64_t)jc >= seq_end) { seq++; seq_beg = seq_end; seq_end = A.pofs[seq + 1]; }
+        uint32_t seq = C.find((uint64_t)jc);
+        uint64_t seq_beg = C.at(seq), seq_end = C.at(seq + 1);
+        while ((uint64_t)jc >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
         seq0 = seq; beg0 = seq_beg; end0 = seq_end;
         const size_t wi = (size_t)jc / 16;
-        const uint64_t lo64 = (uint64_t)A.psw[wi] | ((uint64_t)A.psw[wi + 1] << 32);
-        const uint64_t w2 = A.psw[wi + 2];
+        const uint32_t w0 = A.psw[wi], w1 = A.psw[wi + 1], w2 = A.psw[wi + 2];
+        const uint32_t mw0 = msb_first(w0), mw1 = msb_first(w1), mw2 = msb_first(w2);
+        const int fsh = 64 - 2 * k;
+        // every position of the chunk has its k-mer and a valid window in one sequence
+        const bool interior = (uint64_t)jc + 16 + (uint64_t)(k + w - 2) <= seq_end &&
+                              seq_end - seq_beg >= (uint64_t)(k + w - 1);
+        if (interior && (k & 1)) {
+            // odd k: a k-mer never equals its reverse complement
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const uint64_t j = (uint64_t)jc + u;
-            if (j < np) {
-                while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = A.pofs[seq + 1]; }
-                const bool kvalid = j + (uint64_t)k <= seq_end;
-                const bool wvalid = j + (uint64_t)(k + w - 1) <= seq_end;
-                const bool seq_ok = seq_end - seq_beg >= (uint64_t)(k + w - 1);
-                if (kvalid) {
-                    // bits [2u, 2u + 64) of the stream: base u of the chunk in the low bits
-                    const uint64_t X = u == 0 ? lo64 : ((lo64 >> (2 * u)) | (w2 << (64 - 2 * u)));
-                    const uint64_t rc = (~X) & A.kmask;
-                    const uint64_t fwd = rev_groups(X) >> (64 - 2 * k);
-                    if (fwd == rc) {
-                        fv[u] = wvalid ? 2u : 0u;
-                    } else {
-                        const bool strand = rc < fwd;
-                        hv[u] = mix64(strand ? rc : fwd);
-                        fv[u] = (seq_ok ? 1u : 0u) | (wvalid ? 2u : 0u) | (strand ? 4u : 0u);
+            for (int u = 0; u < 16; u++) {
+                const uint64_t X = kmer_lsb(w0, w1, w2, u);
+                const uint64_t F = kmer_msb(mw0, mw1, mw2, u);
+                const uint64_t rc = (~X) & A.kmask;
+                const uint64_t fwd = F >> fsh;
+                const bool strand = rc < fwd;
+                hv[u] = mix64(strand ? rc : fwd);
+                fv[u] = 3u | (strand ? 4u : 0u);
+            }
+        } else if (interior) {
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const uint64_t X = kmer_lsb(w0, w1, w2, u);
+                const uint64_t F = kmer_msb(mw0, mw1, mw2, u);
+                const uint64_t rc = (~X) & A.kmask;
+                const uint64_t fwd = F >> fsh;
+                const bool strand = rc < fwd;
+                const uint64_t h = mix64(strand ? rc : fwd);
+                const bool pal = fwd == rc;
+                hv[u] = pal ? kMax64 : h;
+                fv[u] = (pal ? 0u : 1u) | 2u | (strand ? 4u : 0u);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const uint64_t j = (uint64_t)jc + u;
+                if (j < np) {
+                    while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
+                    const bool kvalid = j + (uint64_t)k <= seq_end;
+                    const bool wvalid = j + (uint64_t)(k + w - 1) <= seq_end;
+                    const bool seq_ok = seq_end - seq_beg >= (uint64_t)(k + w - 1);
+                    if (kvalid) {
+                        const uint64_t X = kmer_lsb(w0, w1, w2, u);
+                        const uint64_t F = kmer_msb(mw0, mw1, mw2, u);
+                        const uint64_t rc = (~X) & A.kmask;
+                        const uint64_t fwd = F >> fsh;
+                        if (fwd == rc) {
+                            fv[u] = wvalid ? 2u : 0u;
+                        } else {
+                            const bool strand = rc < fwd;
+                            hv[u] = mix64(strand ? rc : fwd);
+                            fv[u] = (seq_ok ? 1u : 0u) | (wvalid ? 2u : 0u) | (strand ? 4u : 0u);
+                        }
                     }
                 }
             }
         }
     }
-#pragma unroll
-    for (int u = 0; u < 16; u++) sh_m[16 * t + u] = hv[u];
-    __syncthreads();
 
-    // ---- stage 2: window minima (forward doubling), then the opening (backward doubling)
-    int q2 = 1;                       // largest power of two <= w
-    while (q2 * 2 <= w) q2 *= 2;
-    const int r2 = w - q2;
-    for (int d = 1; d < q2; d *= 2) {
-        uint64_t v[16];
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int x = 16 * t + u;
-            const uint64_t o = x + d < kE ? sh_m[x + d] : kMax64;
-            v[u] = min(sh_m[x], o);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 16; u++) sh_m[16 * t + u] = v[u];
-        __syncthreads();
-    }
-    {
-        uint64_t v[16];
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int x = 16 * t + u;
-            const uint64_t o = x + r2 < kE ? sh_m[x + r2] : kMax64;
-            v[u] = (fv[u] & 2u) ? min(sh_m[x], o) : 0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 16; u++) sh_m[16 * t + u] = v[u];
-        __syncthreads();
-    }
-    for (int d = 1; d < q2; d *= 2) {
-        uint64_t v[16];
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int x = 16 * t + u;
-            const uint64_t o = x - d >= 0 ? sh_m[x - d] : 0;
-            v[u] = max(sh_m[x], o);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 16; u++) sh_m[16 * t + u] = v[u];
-        __syncthreads();
-    }
+    // ---- stage 2: minimizer selection (window minima, then the opening)
     const bool owner = 16 * t >= H && 16 * t < H + T;
-    uint32_t sel = 0;
+    uint32_t sel;
+    if constexpr (W > 0) sel = select_reg<W>(hv, fv, ex, owner);
+    else sel = select_lds(hv, fv, ex, w, owner);
+    uint32_t smask = 0;              // strand of each position
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        const int x = 16 * t + u;
-        const uint64_t o = x - r2 >= 0 ? sh_m[x - r2] : 0;
-        const uint64_t opened = max(sh_m[x], o);
-        if (owner && (fv[u] & 1u) && hv[u] == opened) sel |= 1u << u;
-    }
+    for (int u = 0; u < 16; u++) smask |= ((fv[u] >> 2) & 1u) << u;
 
     // ---- stage 3: position-ordered compaction across tiles (decoupled look-back)
     uint64_t total;
@@ -291,70 +545,103 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
             if (tile != 0)
                 __hip_atomic_store(&A.tile_state[tile], kFlagP | (before + total),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh_base = before;
+            *sh_base_p = before;
             if (tile == n_tiles - 1) {
                 if (A.n_out) *A.n_out = before + total;
                 if (before + total > A.capacity) set_status(A.status, 1u);
             }
         }
     }
+    // own hashes to LDS (every read of the exchange array finished before the scan's
+    // barriers), so the record loop below can index them by position
+#pragma unroll
+    for (int u = 0; u < 16; u++) ex[u * kBlock + t] = hv[u];
     __syncthreads();
-    const uint64_t base = sh_base + excl;
+    const uint64_t base = *sh_base_p + excl;
 
     if (!owner || (uint64_t)jc > np) return;
 
     // per-sequence record offsets of the sequences that start inside this chunk
     if (A.mz_offsets) {
-        uint32_t s = first_ge(A.pofs, A.n_seq, (uint64_t)jc);
-        while (s <= A.n_seq && A.pofs[s] < (uint64_t)jc + 16) {
-            const uint32_t below = (uint32_t)(A.pofs[s] - (uint64_t)jc);
+        uint32_t s = (uint64_t)jc < np ? seq0 : first_ge(A.pofs, A.n_seq, (uint64_t)jc);
+        while (s > 0 && C.at(s - 1) >= (uint64_t)jc) s--;       // empty sequences
+        while (s <= A.n_seq && C.at(s) < (uint64_t)jc) s++;
+        while (s <= A.n_seq && C.at(s) < (uint64_t)jc + 16) {
+            const uint32_t below = (uint32_t)(C.at(s) - (uint64_t)jc);
             A.mz_offsets[s] = base + __popc(sel & ((1u << below) - 1u));
             s++;
         }
     }
     if (sel == 0) return;
 
-    // records, in position order: walk the chunk's positions keeping the original
-    // coordinate as (period, rank within period)
+    // records, in position order.  The original coordinate of patterned position li of a
+    // sequence is (li / x) * p + phase(li % x); the division is done once per chunk (or
+    // per sequence start) and then advanced by small offsets with a reciprocal multiply.
     uint32_t seq = seq0;
     uint64_t seq_beg = beg0, seq_end = end0;
     uint32_t a = seq_shift(A.shift, A.uniform, seq);
     if (a >= A.P.p) a = 0;
-    const uint64_t li0 = (uint64_t)jc - seq_beg;
-    uint64_t per = li0 / A.P.x;
-    uint32_t rk = (uint32_t)(li0 - per * A.P.x);
+    uint64_t per0;
+    uint32_t r0;
+    div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
+    uint64_t jb = (uint64_t)jc;                // position whose rank is (per0, r0)
+    const uint32_t magic = (65536u + A.P.x - 1) / A.P.x;
     uint64_t idx = base;
-#pragma unroll
-    for (int u = 0; u < 16; u++) {
+    uint32_t bits = sel;
+    while (bits) {
+        const int u = __ffs(bits) - 1;
+        bits &= bits - 1;
         const uint64_t j = (uint64_t)jc + u;
-        if (j < np) {
-            if (j >= seq_end) {
-                while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = A.pofs[seq + 1]; }
-                a = seq_shift(A.shift, A.uniform, seq);
-                if (a >= A.P.p) a = 0;
-                per = 0;
-                rk = 0;
-            }
-            if ((sel >> u) & 1u) {
-                const uint64_t local = per * A.P.p + kept_phase(A.P, a, rk);
-                const uint32_t strand = (fv[u] >> 2) & 1u;
-                if (idx < A.capacity) {
-                    A.keys[idx] = hv[u];
-                    if (A.val_mode == VAL_SEQ64) {
-                        if (local >= (1ull << 31)) set_status(A.status, 2u);
-                        ((uint64_t *)A.vals)[idx] = ((uint64_t)seq << 32) | (local << 1) | strand;
-                    } else {
-                        const uint64_t pos =
-                            A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] + local : local;
-                        if (pos >= (1ull << 31)) set_status(A.status, 2u);
-                        ((uint32_t *)A.vals)[idx] = (uint32_t)((pos << 1) | strand);
-                    }
-                }
-                idx++;
-            }
-            if (++rk == A.P.x) { rk = 0; per++; }
+        if (j >= seq_end) {
+            while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
+            a = seq_shift(A.shift, A.uniform, seq);
+            if (a >= A.P.p) a = 0;
+            per0 = 0;
+            r0 = 0;
+            jb = seq_beg;
         }
+        const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
+        const uint32_t q = (rr * magic) >> 16;
+        const uint64_t local = (per0 + q) * A.P.p + kept_phase(A.P, a, rr - q * A.P.x);
+        const uint32_t strand = (smask >> u) & 1u;
+        if (idx < A.capacity) {
+            A.keys[idx] = ex[u * kBlock + t];
+            if (A.val_mode == VAL_SEQ64) {
+                if (local >= (1ull << 31)) set_status(A.status, 2u);
+                ((uint64_t *)A.vals)[idx] = ((uint64_t)seq << 32) | (local << 1) | strand;
+            } else {
+                const uint64_t pos = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] + local : local;
+                if (pos >= (1ull << 31)) set_status(A.status, 2u);
+                ((uint32_t *)A.vals)[idx] = (uint32_t)((pos << 1) | strand);
+            }
+        }
+        idx++;
     }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
+{
+    __shared__ uint64_t ex[kE];       // neighbour exchange / sliding-reduction work array
+    __shared__ uint64_t sh_scan[kBlock / kWave];
+    __shared__ uint64_t sh_base;
+    __shared__ uint32_t sh_tile;
+    __shared__ uint64_t sh_pofs[kSeqCache];
+    __shared__ uint32_t sh_lohi[2];
+
+    const uint64_t np = A.pofs[A.n_seq];
+    const uint64_t n_tiles = np / (uint64_t)A.T + 1;    // the last tile covers position np
+    // tiles are numbered in the order workgroups start, so every predecessor a tile looks
+    // back on is already running
+    if (threadIdx.x == 0) sh_tile = atomicAdd(A.tile_counter, 1u);
+    __syncthreads();
+    const uint64_t tile = sh_tile;
+    if (tile >= n_tiles) return;
+    const int64_t j0 = (int64_t)(tile * (uint64_t)A.T);
+    const uint64_t jlo = j0 > A.H ? (uint64_t)(j0 - A.H) : 0;
+    const SeqCache C = seq_cache(A.pofs, A.n_seq, jlo, (uint64_t)(j0 + A.T + A.H + 48), sh_pofs,
+                                 sh_lohi);
+    sketch_tile<W>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C);
 }
 
 }  // namespace
@@ -375,7 +662,7 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
 {
     const size_t blocks = (words + kBlock - 1) / kBlock;
     GD_LAUNCH(k_sparsify, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.bases, b.offsets,
-                       b.n_seq, P, shift, uniform_shift, pofs, psw, words);
+              b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4);
     return hipGetLastError();
 }
 
@@ -413,7 +700,15 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     A.tile_state = tile_state;
     A.tile_counter = tile_counter;
     A.status = status;
-    GD_LAUNCH(k_sketch, dim3((unsigned)tiles), dim3(kBlock), 0, s, A);
+    A.inv_x = 1.0 / (double)P.x;
+    const size_t grid = tiles;
+    switch (w) {
+#define GD_W(n) case n: GD_LAUNCH(k_sketch<n>, dim3((unsigned)grid), dim3(kBlock), 0, s, A); break;
+        GD_W(2) GD_W(3) GD_W(4) GD_W(5) GD_W(6) GD_W(7) GD_W(8) GD_W(9) GD_W(10) GD_W(11)
+        GD_W(12) GD_W(13) GD_W(14) GD_W(15) GD_W(16) GD_W(17)
+#undef GD_W
+    default: GD_LAUNCH(k_sketch<0>, dim3((unsigned)grid), dim3(kBlock), 0, s, A); break;
+    }
     return hipGetLastError();
 }
 

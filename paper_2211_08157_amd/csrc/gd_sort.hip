@@ -3,15 +3,18 @@
 // Minimizer hashes are window minima, so they are NOT uniform: small values are several
 // times denser than large ones, and fixed top-bit buckets overflow at the dense end.
 // The partition is therefore data driven:
-//   1. a fine histogram over the top Bf bits (about 8 records per fine bin);
+//   1. a fine histogram over the top Bf bits (about 2 records per fine bin on average,
+//      a few times more at the dense low end);
 //   2. its exclusive scan gives the start of every fine bin;
 //   3. a scatter moves each record into its fine bin (one atomic per record, spread
-//      over ~N/8 addresses);
+//      over ~N/2 addresses);
 //   4. coarse bucket c is the run of fine bins whose start lies in [c*T, (c+1)*T), so
-//      every coarse bucket holds about T records whatever the key distribution; one
-//      workgroup loads it into LDS, sorts each fine bin (already in key order relative
-//      to the others) by insertion sort, or the whole bucket by an LDS bitonic sort when a
-//      fine bin is large (many equal hashes), and writes it back.
+//      every coarse bucket holds about T records whatever the key distribution (its
+//      first fine bin comes from one pass over the fine bins); one workgroup loads it
+//      into LDS, sorts each run of one fine bin (already in key order relative to the
+//      others) by insertion sort, or the whole bucket by an LDS bitonic sort when a run is
+//      long (many equal hashes), and writes it back.  The work per bucket depends on its
+//      records only, not on the number of (possibly empty) fine bins it spans.
 // A coarse bucket larger than the LDS capacity (only possible when one fine bin holds
 // thousands of records) is listed and sorted by a fallback kernel in global memory.
 // (hash, val) pairs are unique, so the result does not depend on the order in which the
@@ -60,14 +63,20 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const 
     }
 }
 
-// Fine bins [f0, f1) of coarse bucket c (bins whose start lies in [c*T, (c+1)*T)).
-__device__ __forceinline__ void coarse_range(const uint64_t *fofs, uint32_t nfine, uint64_t c,
-                                             uint32_t target, uint32_t *f0, uint32_t *f1)
+// cstart[c] = first fine bin whose start is >= c*T (so coarse bucket c is the fine bins
+// [cstart[c], cstart[c+1])).  One thread per fine bin writes the c values it is first for:
+// c in (fofs[f-1] / T, fofs[f] / T].  Entries past N / T keep the fill value nfine.
+__global__ __launch_bounds__(kBlock) void k_coarse_starts(const uint64_t *fofs, uint32_t nfine,
+                                                          uint32_t target, uint32_t *cstart,
+                                                          uint64_t ncoarse)
 {
-    const uint32_t a = first_ge(fofs, nfine, c * target);
-    const uint32_t b = first_ge(fofs, nfine, (c + 1) * target);
-    *f0 = a > nfine ? nfine : a;
-    *f1 = b > nfine ? nfine : b;
+    const uint64_t f = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    if (f > nfine) return;
+    const uint64_t hi = fofs[f];
+    const uint64_t c_lo = f == 0 ? 0 : fofs[f - 1] / target + 1;
+    const uint64_t c_hi = hi / target;        // c*T <= hi
+    for (uint64_t c = c_lo; c <= c_hi && c < ncoarse; c++)
+        if (f == 0 || c * target > fofs[f - 1]) cstart[c] = (uint32_t)f;
 }
 
 // In-LDS bitonic sort of n records, padded with maximal records to the next power of two
@@ -114,17 +123,15 @@ __device__ void insertion_sort(uint64_t *K, V *Vv, int lo, int hi)
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, const V *tvals,
-                                                        const uint64_t *fofs, uint32_t nfine,
-                                                        uint32_t target, uint64_t *okeys, V *ovals,
+                                                        const uint64_t *fofs, const uint32_t *cstart,
+                                                        int Bf, uint64_t *okeys, V *ovals,
                                                         uint32_t *overflow, uint32_t *overflow_n)
 {
     constexpr int kCap = Cap<V>::value;
     __shared__ uint64_t K[kCap];
     __shared__ V Vv[kCap];
-    __shared__ uint32_t sh_max;
 
-    uint32_t f0, f1;
-    coarse_range(fofs, nfine, blockIdx.x, target, &f0, &f1);
+    const uint32_t f0 = cstart[blockIdx.x], f1 = cstart[blockIdx.x + 1];
     const uint64_t base = fofs[f0];
     const uint64_t n64 = fofs[f1] - base;
     if (n64 == 0) return;
@@ -134,23 +141,22 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, c
     }
     const int n = (int)n64;
     const int t = threadIdx.x;
-    if (t == 0) sh_max = 0;
     for (int i = t; i < n; i += kBlock) { K[i] = tkeys[base + i]; Vv[i] = tvals[base + i]; }
-    uint32_t mx = 0;
-    for (uint32_t f = f0 + t; f < f1; f += kBlock) {
-        const uint32_t sz = (uint32_t)(fofs[f + 1] - fofs[f]);
-        mx = sz > mx ? sz : mx;
-    }
     __syncthreads();
-    if (mx > 1) atomicMax(&sh_max, mx);
-    __syncthreads();
-    if (sh_max <= (uint32_t)kSmall) {
-        for (uint32_t f = f0 + t; f < f1; f += kBlock)
-            insertion_sort<V>(K, Vv, (int)(fofs[f] - base), (int)(fofs[f + 1] - base));
-        __syncthreads();
-    } else {
-        lds_bitonic<V>(K, Vv, n);
+    // the records are grouped by fine bin; each segment (run of one fine bin) is sorted by
+    // the thread that owns its first record.  Sorting permutes records inside a segment
+    // only, so the bin seen at a neighbouring segment's edge never changes.
+    const int sh = 64 - Bf;
+    int big = 0;
+    for (int i = t; i < n; i += kBlock) {
+        const uint64_t b = K[i] >> sh;
+        if (i > 0 && (K[i - 1] >> sh) == b) continue;
+        int e = i + 1;
+        while (e < n && (K[e] >> sh) == b) e++;
+        if (e - i > kSmall) big = 1;
+        else insertion_sort<V>(K, Vv, i, e);
     }
+    if (__syncthreads_or(big)) lds_bitonic<V>(K, Vv, n);
     for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
 }
 
@@ -173,8 +179,8 @@ __device__ uint64_t rank_in(const uint64_t *K, const V *Vv, uint64_t lo, uint64_
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *tvals,
-                                                            const uint64_t *fofs, uint32_t nfine,
-                                                            uint32_t target,
+                                                            const uint64_t *fofs,
+                                                            const uint32_t *cstart,
                                                             const uint32_t *overflow,
                                                             const uint32_t *overflow_n,
                                                             uint64_t *okeys, V *ovals)
@@ -184,10 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *
     __shared__ V Vv[kCap];
     const uint32_t nov = *overflow_n;
     for (uint32_t oi = blockIdx.x; oi < nov; oi += gridDim.x) {
-        uint32_t f0, f1;
-        coarse_range(fofs, nfine, overflow[oi], target, &f0, &f1);
-        const uint64_t base = fofs[f0];
-        const uint64_t n = fofs[f1] - base;
+        const uint32_t c = overflow[oi];
+        const uint64_t base = fofs[cstart[c]];
+        const uint64_t n = fofs[cstart[c + 1]] - base;
         for (uint64_t r0 = 0; r0 < n; r0 += kCap) {
             const int m = (int)min((uint64_t)kCap, n - r0);
             for (int i = threadIdx.x; i < m; i += kBlock) {
@@ -243,11 +248,15 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
     if ((e = exclusive_scan_u32(w.hist, w.fofs, sp.nfine, w.scan_tmp, s)) != hipSuccess) return e;
     GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity, sp.Bf,
               w.fofs, w.cursor, w.tkeys, (V *)w.tvals);
+    if ((e = fill_u32(w.cstart, (uint32_t)sp.nfine, sp.ncoarse + 1, s)) != hipSuccess) return e;
+    GD_LAUNCH(k_coarse_starts, dim3((unsigned)((sp.nfine + kBlock) / kBlock)), dim3(kBlock), 0, s,
+              (const uint64_t *)w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, w.cstart,
+              (uint64_t)sp.ncoarse + 1);
     GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s, w.tkeys,
-              (const V *)w.tvals, w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, keys, vals,
+              (const V *)w.tvals, w.fofs, (const uint32_t *)w.cstart, sp.Bf, keys, vals,
               w.overflow, w.overflow_n);
     GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.tkeys, (V *)w.tvals, w.fofs,
-              (uint32_t)sp.nfine, (uint32_t)sp.target, w.overflow, w.overflow_n, keys, vals);
+              (const uint32_t *)w.cstart, w.overflow, w.overflow_n, keys, vals);
     return hipGetLastError();
 }
 
@@ -257,7 +266,7 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
 {
     SortPlan sp;
     int Bf = 4;
-    while (Bf < 26 && (expected_records >> Bf) > 8) Bf++;
+    while (Bf < 26 && (expected_records >> Bf) > 2) Bf++;
     sp.Bf = Bf;
     sp.nfine = (size_t)1 << Bf;
     sp.target = val_bytes == 4 ? 2048 : 1024;

@@ -37,7 +37,7 @@ def ragged_batch(seed, lens):
 LENS = [0, 1, 5, 20, 21, 22, 40, 100, 4100, 0, 3, 9000, 151, 150, 37]
 
 
-@pytest.mark.parametrize("pattern", ["1", "10", "110", "101", "1001010011", "0001", "1" * 64,
+@pytest.mark.parametrize("pattern", ["1", "10", "01", "110", "101", "1001010011", "0001", "1" * 64,
                                      "10" * 32])
 def test_sparsify_matches_oracle(gpu, pattern):
     codes, offs = ragged_batch(1, LENS)
@@ -53,7 +53,8 @@ def test_sparsify_matches_oracle(gpu, pattern):
 
 SKETCH_CASES = [("10", 15, 10), ("10", 21, 11), ("110", 21, 11), ("1", 15, 12), ("1", 19, 19),
                 ("1", 28, 40), ("101001", 13, 5), ("1", 4, 1), ("10", 2, 3), ("1", 32, 2),
-                ("1110", 31, 17), ("100", 8, 6), ("1" * 64, 21, 11), ("1", 6, 256)]
+                ("1110", 31, 17), ("100", 8, 6), ("1" * 64, 21, 11), ("1", 6, 256),
+                ("01", 21, 11)]
 
 
 @pytest.mark.parametrize("pattern,k,w", SKETCH_CASES)
@@ -66,6 +67,19 @@ def test_sketch_matches_oracle(gpu, pattern, k, w):
     for sh in (None, shifts):
         keys, vals, mz = gpu.sketch(dev(gpu, codes, offs), pattern, k, w, shift=sh)
         ek, ev, em = oracle.sketch(codes, offs, pattern, k, w, shifts=sh)
+        assert np.array_equal(mz.cpu().numpy().view(np.uint64), em)
+        assert np.array_equal(u64(keys), ek)
+        assert np.array_equal(u32(vals).astype(np.uint64), ev)
+
+
+@pytest.mark.parametrize("w", list(range(1, 19)))
+def test_sketch_every_small_window(gpu, w):
+    # w 2..17 use the register selection path, the others the LDS doubling path
+    codes, offs = ragged_batch(12, [30_000, 0, 7, 60, 150, 151, 2000, 40])
+    codes[10_000:10_400] = 0
+    for pattern, k in [("10", 13), ("1", 8)]:
+        keys, vals, mz = gpu.sketch(dev(gpu, codes, offs), pattern, k, w)
+        ek, ev, em = oracle.sketch(codes, offs, pattern, k, w)
         assert np.array_equal(mz.cpu().numpy().view(np.uint64), em)
         assert np.array_equal(u64(keys), ek)
         assert np.array_equal(u32(vals).astype(np.uint64), ev)
