@@ -66,7 +66,14 @@ class Session:
         self.st_s = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws_s = torch.empty(api.workspace_size(api.OP_SEED, self.reads, pattern, k, w, ix.n),
                                 dtype=torch.uint8, device=dev)
+        self.log2_leaves = 18
+        nb = api.lib().godiet_rmi_size(self.log2_leaves)
+        blob = torch.empty(nb + 64, dtype=torch.uint8, device=dev)
+        off = (-blob.data_ptr()) % 64
+        self.rmi = blob[off:off + nb]
         self.cix = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32, None, 0)
+        self.cix_rmi = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
+                                 self.rmi.data_ptr(), self.rmi.numel())
         self.opts = api.SeedOpts(-1, 0, 0)
         del ix, a, off
         # per-shift query counts (minimizers of the reads at every shift) for byte accounting
@@ -79,7 +86,7 @@ class Session:
             del kq
         torch.cuda.synchronize()
 
-    def step(self):
+    def step(self, learned=False):
         L = self.api.lib()
         st = ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
         r = L.godiet_index_build(ctypes.byref(self.cref), ctypes.byref(self.prm),
@@ -90,7 +97,13 @@ class Session:
                                  ctypes.c_void_p(self.st_i.data_ptr()), st)
         if r != 0:
             raise RuntimeError("godiet_index_build failed: %d" % r)
-        r = L.godiet_seed(ctypes.byref(self.cix), ctypes.byref(self.creads), ctypes.byref(self.prm),
+        if learned:
+            r = L.godiet_rmi_train(ctypes.byref(self.cix), 1, self.log2_leaves,
+                                   ctypes.c_void_p(self.rmi.data_ptr()), self.rmi.numel(), st)
+            if r != 0:
+                raise RuntimeError("godiet_rmi_train failed: %d" % r)
+        cix = self.cix_rmi if learned else self.cix
+        r = L.godiet_seed(ctypes.byref(cix), ctypes.byref(self.creads), ctypes.byref(self.prm),
                           ctypes.byref(self.opts), ctypes.c_void_p(self.anchors.data_ptr()),
                           self.acap, ctypes.c_void_p(self.roff.data_ptr()),
                           ctypes.c_void_p(self.shift.data_ptr()),
@@ -155,10 +168,10 @@ def cpu_baseline(data, pattern, k, w, sample_reads):
 def kernel_bytes(name, s):
     """Algorithmic bytes of all launches of one kernel in one step (None if unmodelled)."""
     ref_np = s.ref.n_bases // 2 if s.pattern == "10" else None
-    if name == "k_lookup":
+    if name.startswith("k_lookup"):
         # query key in, (lb, occ) out, and one 64-byte line of the index per query
         return s.queries * (8 + 8 + 64)
-    if name == "k_sketch" and ref_np is not None:
+    if name.startswith("k_sketch") and ref_np is not None:
         reads_np = s.reads.n_bases // 2
         return (ref_np + reads_np * len(s.pattern)) / 4 + 12 * (s.n_index + s.queries)
     if name.startswith("k_bucket_sort") or name.startswith("k_scatter"):
@@ -175,6 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=200_000)
+    ap.add_argument("--no-1gbp", action="store_true", help="skip the 1 Gbp reference sketch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for "
@@ -193,24 +207,39 @@ def main():
     s = Session(gd, data, pattern, k, w)
     log("[bench] index %d records, %d anchors, %d lookups per step" % (s.n_index, s.n_anchors,
                                                                       s.queries))
-    for _ in range(args.warmup):
-        s.step()
-    s.check()
-    digest = s.digest()
-
-    torch.cuda.synchronize()
-    gd.trace_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    gd.trace_enable(False)
-    s.check()
-    trace = gd.trace_dump()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = s.reads.n_seq / (ms_step * 1e-3)
-    log("[bench] %.3f ms/step, %.3e reads/s" % (ms_step, value))
+    modes = {}
+    for learned in (False, True):
+        for _ in range(args.warmup):
+            s.step(learned)
+        s.check()
+        digest = s.digest()
+        torch.cuda.synchronize()
+        gd.trace_dump()
+        gd.trace_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.step(learned)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gd.trace_enable(False)
+        s.check()
+        if s.digest() != digest:
+            raise RuntimeError("outputs changed between steps")
+        trace = gd.trace_dump()
+        ms_step = (t1 - t0) * 1e3 / args.steps
+        modes["learned_index" if learned else "binary_search"] = dict(
+            ms_per_step=ms_step, reads_per_s=s.reads.n_seq / (ms_step * 1e-3), digest=digest,
+            trace=trace)
+        log("[bench] %s: %.3f ms/step, %.3e reads/s" % ("learned index" if learned else
+                                                         "binary search", ms_step,
+                                                         s.reads.n_seq / (ms_step * 1e-3)))
+    if modes["learned_index"]["digest"] != modes["binary_search"]["digest"]:
+        raise RuntimeError("learned-index anchors differ from binary-search anchors")
+    head = "learned_index"
+    ms_step = modes[head]["ms_per_step"]
+    value = modes[head]["reads_per_s"]
+    trace = modes[head]["trace"]
+    digest = modes[head]["digest"]
     per_kernel = {kname: dict(launches=n, ms_per_step=ms / args.steps)
                   for kname, (n, ms) in sorted(trace.items(), key=lambda kv: -kv[1][1])}
     dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
@@ -226,6 +255,24 @@ def main():
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
 
+    n_reads, n_index, n_anchors, queries = s.reads.n_seq, s.n_index, s.n_anchors, s.queries
+    sketch_1g = None
+    if not args.no_1gbp:
+        del s
+        torch.cuda.empty_cache()
+        log("[bench] generating the 1 Gbp reference")
+        big = datagen.add_repeats(datagen.random_genome(1_000_000_000, 3), 203)
+        bseq = gd.to_device(big, [0, big.size])
+        del big
+        sketch_1g = {}
+        for pat in ("10", "110"):
+            g, ms, m, kern = sketch_gbps(gd, torch, bseq, pat, k, w)
+            sketch_1g[pat] = dict(GBps=g, ms=ms, minimizers=m, frac_of_hbm_peak=g / HBM_PEAK_GBPS,
+                                  kernels_ms=kern)
+            log("[bench] 1 Gbp sketch, pattern %s: %.3f ms, %.1f GB/s" % (pat, ms, g))
+        del bseq
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -236,14 +283,21 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "illumina-100Mbp: 100 Mbp reference (5% repeats), 1M x 150 bp "
-                               "reads, pattern 10, k=21, w=11; step = index build + seeding",
-                   "lookup": "binary_search", "global_batch": s.reads.n_seq,
-                   "parallelism": "single GPU"},
+                               "reads, pattern 10, k=21, w=11; step = index build + learned-index "
+                               "training + seeding (pattern alignment, anchors)",
+                   "lookup": "learned_index (2-stage FP32 RMI, 2^18 leaves)",
+                   "global_batch": n_reads, "parallelism": "single GPU"},
+        "binary_search": {"ms_per_step": modes["binary_search"]["ms_per_step"],
+                          "reads_per_s": modes["binary_search"]["reads_per_s"],
+                          "kernels": {kn: dict(launches=n, ms_per_step=ms / args.steps)
+                                      for kn, (n, ms) in modes["binary_search"]["trace"].items()}},
+        "learned_vs_binary_speedup": modes["binary_search"]["ms_per_step"] / ms_step,
         "roofline": roof,
         "cpu_baseline": cpu,
         "sketch_GBps": gbps, "sketch_ms": sk_ms, "sketch_bytes_rule": "ceil(L/4) + 12 B/minimizer",
         "sketch_kernels_ms": sk_kernels,
-        "index_records": s.n_index, "anchors": s.n_anchors, "lookups_per_step": s.queries,
+        "sketch_1Gbp": sketch_1g,
+        "index_records": n_index, "anchors": n_anchors, "lookups_per_step": queries,
         "kernels": per_kernel, "output_sha256_16": digest,
     }
     print(json.dumps(out), flush=True)

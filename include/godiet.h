@@ -93,7 +93,8 @@ typedef struct {
 /* A sorted seed index as produced by godiet_index_build.  val_bits 32: vals is uint32
  * global position << 1 | strand; val_bits 64: vals is uint64 sequence id << 32 |
  * position << 1 | strand.  rmi: NULL for binary-search lookups, else a learned index
- * trained on exactly these keys by godiet_rmi_train (rmi_bytes its size). */
+ * trained on exactly these keys by godiet_rmi_train (rmi_bytes its size); a model trained
+ * on other keys is detected by its key count and ignored (binary search is used). */
 typedef struct {
     const uint64_t *keys;
     const void *vals;
@@ -179,6 +180,27 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
                           godiet_anchor *anchors, uint64_t capacity, uint64_t *read_anchor_off,
                           uint8_t *shift_out, void *ws, size_t ws_bytes, uint32_t *status,
                           hipStream_t stream);
+
+/* Exact-match lookups in a sorted index (Section 3.3, "finds exact matches of minimizers
+ * ... by querying the seed index"): for every query q[i], lb[i] = first index e with
+ * keys[e] >= q[i] and occ[i] = number of e with keys[e] == q[i].  Uses index->rmi when it
+ * is non-NULL, plain binary search otherwise; the results are identical either way.
+ * q, lb, occ: device arrays of n_q entries.  Needs index->n < 2^32. */
+godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64_t n_q,
+                            uint32_t *lb, uint32_t *occ, hipStream_t stream);
+
+/* Learned index (not part of the paper; its counterpart there is the hash table of
+ * Section 3.1): a two-stage recursive model index over index->keys.  The root (root_kind
+ * 0: linear, 1: 1->32->1 ReLU network with knots at key quantiles) routes the FP32 image
+ * of a key to one of 2^log2_leaves linear leaves, each predicting the key's rank from its
+ * integer offset to the leaf's first key and storing its largest under/over-prediction.
+ * A lookup searches only the predicted window after checking that it brackets the
+ * answer, and falls back to binary search otherwise, so results equal binary search.
+ * rmi: device buffer of godiet_rmi_size(log2_leaves) bytes, 64-byte aligned, written
+ * entirely by this call (no workspace needed); log2_leaves in 1..24. */
+size_t godiet_rmi_size(uint32_t log2_leaves);
+godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uint32_t log2_leaves,
+                               void *rmi, size_t rmi_bytes, hipStream_t stream);
 
 /* Kernel tracing, a profiling aid outside the method.  While enabled, every kernel launch
  * of the library is bracketed by HIP events recorded on the launch's stream.  After the

@@ -69,6 +69,12 @@ def lib():
         L.godiet_seed.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), P, u64, P, P, P, sz,
                                   P, P]
         L.godiet_seed.restype = i32
+        L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
+        L.godiet_lookup.restype = i32
+        L.godiet_rmi_size.argtypes = [u32]
+        L.godiet_rmi_size.restype = sz
+        L.godiet_rmi_train.argtypes = [S(Index), i32, u32, P, sz, P]
+        L.godiet_rmi_train.restype = i32
         L.godiet_trace_enable.argtypes = [ctypes.c_int]
         L.godiet_trace_enable.restype = None
         L.godiet_trace_dump.argtypes = [ctypes.c_char_p, sz]
@@ -226,13 +232,49 @@ def sketch(seqs, pattern, k, w, shift=None, capacity=None):
 
 
 class DeviceIndex:
-    """A sorted seed index in device memory (keys as int64 bit patterns of uint64)."""
+    """A sorted seed index in device memory (keys as int64 bit patterns of uint64), with an
+    optional learned-index model (uint8 tensor) used for its lookups."""
 
-    def __init__(self, keys, vals, n, val_bits):
+    def __init__(self, keys, vals, n, val_bits, rmi=None):
         self.keys, self.vals, self.n, self.val_bits = keys, vals, int(n), int(val_bits)
+        self.rmi = rmi
 
     def c(self):
-        return Index(self.keys.data_ptr(), self.vals.data_ptr(), self.n, self.val_bits, None, 0)
+        return Index(self.keys.data_ptr(), self.vals.data_ptr(), self.n, self.val_bits,
+                     self.rmi.data_ptr() if self.rmi is not None else None,
+                     self.rmi.numel() if self.rmi is not None else 0)
+
+    def with_rmi(self, rmi):
+        return DeviceIndex(self.keys, self.vals, self.n, self.val_bits, rmi)
+
+
+def rmi_train(index, root="mlp", log2_leaves=18):
+    """Train a learned index on index.keys; returns a copy of the index that uses it."""
+    torch = _torch()
+    L = lib()
+    nbytes = L.godiet_rmi_size(int(log2_leaves))
+    if nbytes == 0:
+        raise ValueError("log2_leaves must be in 1..24")
+    blob = torch.empty(nbytes + 64, dtype=torch.uint8, device="cuda")
+    off = (-blob.data_ptr()) % 64
+    blob = blob[off:off + nbytes]
+    ix = index.c()
+    kind = {"linear": 0, "mlp": 1}[root]
+    _check(L.godiet_rmi_train(ctypes.byref(ix), kind, int(log2_leaves), _ptr(blob), nbytes,
+                              _stream()), "godiet_rmi_train")
+    return index.with_rmi(blob)
+
+
+def lookup(index, queries):
+    """(lb, occ) int32 tensors (uint32 bits) of int64 query tensor `queries` (uint64 bits)."""
+    torch = _torch()
+    n = queries.numel()
+    lb = _empty(n, torch.int32)
+    occ = _empty(n, torch.int32)
+    ix = index.c()
+    _check(lib().godiet_lookup(ctypes.byref(ix), _ptr(queries), n, _ptr(lb), _ptr(occ),
+                               _stream()), "godiet_lookup")
+    return lb[:n], occ[:n]
 
 
 def index_build(ref, pattern, k, w, val_bits=32, capacity=None):

@@ -287,7 +287,6 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
     if (index->val_bits != 32) return GODIET_E_UNSUPPORTED;
     if (index->n > 0 && (!index->keys || !index->vals)) return GODIET_E_INVAL;
     if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
-    if (index->rmi) return GODIET_E_UNSUPPORTED;
     if (opts->shift_mode < -1 || opts->shift_mode >= (int32_t)P.p) return GODIET_E_INVAL;
     if (capacity > 0 && !anchors) return GODIET_E_INVAL;
     const uint64_t npb = kept_bound(reads, P);
@@ -308,7 +307,7 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
                              prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
-                             W.occ + si * W.stride, stream));
+                             W.occ + si * W.stride, index->rmi, stream));
     }
     AlignArgs A;
     A.mzofs = W.mzofs;
@@ -325,6 +324,37 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
     GD_TRY(exclusive_scan_u32(W.cnt, read_anchor_off, nr, W.scan, stream));
     GD_TRY(launch_expand(A, W.slot, read_anchor_off, index->vals, (uint32_t *)anchors, capacity,
                          status, W.long_ids, W.long_n, stream));
+    return GODIET_OK;
+}
+
+size_t godiet_rmi_size(uint32_t log2_leaves)
+{
+    if (log2_leaves < 1 || log2_leaves > 24) return 0;
+    return rmi_bytes(log2_leaves);
+}
+
+godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uint32_t log2_leaves,
+                               void *rmi, size_t rmi_bytes_, hipStream_t stream)
+{
+    if (!index || !rmi || (root_kind != 0 && root_kind != 1)) return GODIET_E_INVAL;
+    if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    const size_t need = godiet_rmi_size(log2_leaves);
+    if (need == 0) return GODIET_E_INVAL;
+    if (rmi_bytes_ < need) return GODIET_E_WORKSPACE;
+    if (((uintptr_t)rmi & 63) != 0) return GODIET_E_INVAL;
+    GD_TRY(launch_rmi_train(index->keys, index->n, root_kind, log2_leaves, rmi, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64_t n_q,
+                            uint32_t *lb, uint32_t *occ, hipStream_t stream)
+{
+    if (!index || (n_q > 0 && (!q || !lb || !occ))) return GODIET_E_INVAL;
+    if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (n_q == 0) return GODIET_OK;
+    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, stream));
     return GODIET_OK;
 }
 

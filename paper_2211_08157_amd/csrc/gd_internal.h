@@ -128,9 +128,15 @@ hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void
                        int val_bytes, const uint64_t *n_ptr, uint64_t capacity, hipStream_t s);
 
 // ---- lookups, alignment, anchors (gd_seed.hip) ----
+// lb/occ of min(*n_q, q_cap) queries (n_q may be null: q_cap queries); rmi nullable.
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         hipStream_t s);
+                         const void *rmi, hipStream_t s);
+
+// ---- learned index (gd_rmi.hip)
+size_t rmi_bytes(uint32_t log2_leaves);
+hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t log2_leaves,
+                            void *rmi, hipStream_t s);
 
 struct AlignArgs {
     const uint64_t *mzofs;   // shift-major: [n_shift][n_reads + 1]

@@ -1,0 +1,150 @@
+// Learned index over the sorted minimizer keys: a two-stage recursive model index with
+// FP32 inference and a bounded, self-checking last-mile search.
+//
+// Model blob (device memory, godiet_rmi_size bytes):
+//   RmiHeader                      magic, root kind, log2 of the leaf count, key count
+//   root parameters                linear: leaf = a*x + b;  MLP: 1 -> 32 ReLU -> 1 with
+//                                  hidden unit i = relu(x - t_i), out = c0 + sum c_i h_i,
+//                                  x = key * 2^-64 (FP32), out = predicted rank / n
+//   RmiLeaf[L]                     first key, base position, slope, intercept, errors
+//
+// Routing is monotone in the key (FP32 conversion, non-negative slopes, floor), so each
+// leaf owns a contiguous run of the sorted keys.  A leaf predicts
+//     p = base + floor(icpt + slope * float(q - kmin))
+// and the answer is searched in [p - err_lo, p + err_hi + 1].  The window is accepted
+// only if keys[lo-1] < q <= keys[hi] (with the array ends as sentinels); otherwise the
+// lookup falls back to a full binary search, so results never depend on the model or on
+// floating-point details, only its speed does.
+#include "gd_internal.h"
+#include "gd_rmi_model.h"
+
+namespace gd {
+
+namespace {
+
+// ---- training
+
+// One workgroup: root parameters from the sorted keys (knots at key quantiles; the
+// network interpolates the rank/n curve linearly between them).
+__global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint64_t n, int kind,
+                                                     uint32_t log2_leaves, RmiHeader *H)
+{
+    if (threadIdx.x != 0) return;
+    RmiHeader h;
+    for (size_t i = 0; i < sizeof(h) / 4; i++) ((uint32_t *)&h)[i] = 0;
+    h.magic = kRmiMagic;
+    h.kind = (uint32_t)kind;
+    h.log2_leaves = log2_leaves;
+    h.n_keys = n;
+    const double L = (double)(1u << log2_leaves);
+    if (n > 0) {
+        const double x0 = (double)keys[0] * 0x1p-64, x1 = (double)keys[n - 1] * 0x1p-64;
+        const double a = x1 > x0 ? L / (x1 - x0) : 0.0;
+        h.a = (float)a;
+        h.b = (float)(-a * x0);
+        // knots at ranks j*n/32 and the rank/n value at each knot
+        double tx[kKnots + 1], ty[kKnots + 1];
+        for (int j = 0; j <= kKnots; j++) {
+            const uint64_t r = j == kKnots ? n - 1 : (uint64_t)((double)n * j / kKnots);
+            tx[j] = (double)keys[r] * 0x1p-64;
+            ty[j] = (double)r / (double)n;
+        }
+        // slope of each segment; hidden unit i switches on at knot i
+        double prev = 0.0;
+        h.c[0] = (float)ty[0];
+        for (int i = 0; i < kKnots; i++) {
+            const double dx = tx[i + 1] - tx[i];
+            const double s = dx > 0 ? (ty[i + 1] - ty[i]) / dx : 0.0;
+            h.t[i] = (float)tx[i];
+            h.c[i + 1] = (float)(s - prev);
+            prev = s;
+        }
+    }
+    *H = h;
+}
+
+// Leaf boundaries: leaf l starts at the first key routed to a leaf >= l.  Stored in the
+// leaves' base field for the fitting pass.
+__global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
+                                                       const RmiHeader *Hp, RmiLeaf *leaves)
+{
+    const RmiHeader H = *Hp;
+    const uint32_t L = 1u << H.log2_leaves;
+    for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i <= n;
+         i += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t cur = i < n ? route(H, keys[i]) : L;          // past the end: L
+        const uint32_t prv = i > 0 ? route(H, keys[i - 1]) : 0;
+        const uint32_t from = i > 0 ? prv + 1 : 0;
+        for (uint32_t l = from; l <= cur && l < L; l++) leaves[l].base = (uint32_t)i;
+    }
+}
+
+// One thread per leaf: least-squares line through (key - kmin, position) in FP64, then
+// the largest under- and over-prediction over the leaf's keys with the lookup's own
+// prediction function.
+__global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64_t n,
+                                                    const RmiHeader *Hp, RmiLeaf *leaves)
+{
+    const uint32_t L = 1u << Hp->log2_leaves;
+    const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= L) return;
+    const uint64_t lo = leaves[l].base;
+    const uint64_t hi = l + 1 < L ? leaves[l + 1].base : n;
+    RmiLeaf lf;
+    lf.base = (uint32_t)lo;
+    lf.kmin = lo < n ? keys[lo] : kMax64;
+    lf.slope = 0.f;
+    lf.icpt = 0.f;
+    lf.err_lo = 0;
+    lf.err_hi = 0;
+    lf.pad = 0;
+    const uint64_t m = hi > lo ? hi - lo : 0;
+    if (m >= 2) {
+        double sx = 0, sy = 0, sxx = 0, sxy = 0;
+        for (uint64_t i = lo; i < hi; i++) {
+            const double x = (double)(keys[i] - lf.kmin), y = (double)(i - lo);
+            sx += x; sy += y; sxx += x * x; sxy += x * y;
+        }
+        const double var = sxx - sx * sx / (double)m;
+        const double sl = var > 0 ? (sxy - sx * sy / (double)m) / var : 0.0;
+        lf.slope = (float)(sl > 0 ? sl : 0.0);
+        lf.icpt = (float)((sy - sl * sx) / (double)m);
+    }
+    // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]
+    int64_t elo = 0, ehi = 0;
+    for (uint64_t i = lo; i < hi; i++) {
+        if (i > lo && keys[i] == keys[i - 1]) continue;
+        const int64_t p = predict(lf, keys[i]);
+        const int64_t d = (int64_t)i - p;
+        if (d > ehi) ehi = d;
+        if (-d > elo) elo = -d;
+    }
+    lf.err_lo = (int32_t)(elo < 0x7fffffff ? elo : 0x7fffffff);
+    lf.err_hi = (int32_t)(ehi < 0x7fffffff ? ehi : 0x7fffffff);
+    leaves[l] = lf;
+}
+
+}  // namespace
+
+size_t rmi_bytes(uint32_t log2_leaves)
+{
+    return sizeof(RmiHeader) + ((size_t)1 << log2_leaves) * sizeof(RmiLeaf);
+}
+
+hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t log2_leaves,
+                            void *rmi, hipStream_t s)
+{
+    RmiHeader *H = (RmiHeader *)rmi;
+    RmiLeaf *leaves = (RmiLeaf *)((char *)rmi + sizeof(RmiHeader));
+    const uint32_t L = 1u << log2_leaves;
+    GD_LAUNCH(k_rmi_root, dim3(1), dim3(kBlock), 0, s, keys, n, kind, log2_leaves, H);
+    uint64_t blocks = (n + 1 + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    GD_LAUNCH(k_rmi_bounds, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n,
+              (const RmiHeader *)H, leaves);
+    GD_LAUNCH(k_rmi_fit, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, keys, n,
+              (const RmiHeader *)H, leaves);
+    return hipGetLastError();
+}
+
+}  // namespace gd

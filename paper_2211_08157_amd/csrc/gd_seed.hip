@@ -8,6 +8,7 @@
 // minimizer records and combine with wave reductions/scans, so anchors of a read are
 // written as one contiguous, coalesced run in (qpos, rpos) order.
 #include "gd_internal.h"
+#include "gd_rmi_model.h"
 
 namespace gd {
 
@@ -39,16 +40,19 @@ __device__ __forceinline__ uint64_t run_end(const uint64_t *keys, uint64_t n, ui
     return a;
 }
 
+// One lane per query; `rmi` (nullable) switches the lower bound to the learned index.
+template <bool kModel>
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64_t in,
                                                    const uint64_t *q, const uint64_t *n_q,
-                                                   uint64_t q_cap, uint32_t *lb, uint32_t *occ)
+                                                   uint64_t q_cap, uint32_t *lb, uint32_t *occ,
+                                                   const void *rmi)
 {
-    uint64_t n = *n_q;
+    uint64_t n = n_q ? *n_q : q_cap;
     if (n > q_cap) n = q_cap;
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t x = q[i];
-        const uint64_t l = lower_bound_u64(ikeys, in, x);
+        const uint64_t l = kModel ? rmi_lower_bound(rmi, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
         const uint64_t u = run_end(ikeys, in, l, x);
         lb[i] = (uint32_t)l;
         occ[i] = (uint32_t)(u - l);
@@ -234,13 +238,17 @@ __global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint3
 
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         hipStream_t s)
+                         const void *rmi, hipStream_t s)
 {
     uint64_t blocks = (q_cap + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    GD_LAUNCH(k_lookup, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                       q_cap, lb, occ);
+    if (rmi)
+        GD_LAUNCH(k_lookup<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, rmi);
+    else
+        GD_LAUNCH(k_lookup<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, rmi);
     return hipGetLastError();
 }
 
