@@ -181,6 +181,19 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
                           uint8_t *shift_out, void *ws, size_t ws_bytes, uint32_t *status,
                           hipStream_t stream);
 
+/* Containment-style search (Section 2.2, the k-mer-set intersection behind containment
+ * search; the paper then thresholds these counts): index is a multi-genome index built
+ * with val_bits 64 (genome id = val >> 32).  H_sample = distinct hashes of every read's
+ * minimizers at its aligned shift (alignment exactly as in godiet_seed, opts included);
+ * for genome g, H_g = distinct hashes among its index records.  counts[g] =
+ * |H_sample intersect H_g| and genome_sizes[g] = |H_g| for g < n_genomes (device arrays,
+ * overwritten).  Records whose genome id is >= n_genomes are skipped and raise
+ * GODIET_ST_RANGE.  ws: godiet_workspace_size(GODIET_OP_CONTAIN, reads, prm, index->n). */
+godiet_status godiet_contain(const godiet_index *index, const godiet_seqs *reads,
+                             const godiet_sketch_params *prm, const godiet_seed_opts *opts,
+                             uint32_t n_genomes, uint32_t *counts, uint32_t *genome_sizes,
+                             void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
 /* Exact-match lookups in a sorted index (Section 3.3, "finds exact matches of minimizers
  * ... by querying the seed index"): for every query q[i], lb[i] = first index e with
  * keys[e] >= q[i] and occ[i] = number of e with keys[e] == q[i].  Uses index->rmi when it

@@ -69,6 +69,9 @@ def lib():
         L.godiet_seed.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), P, u64, P, P, P, sz,
                                   P, P]
         L.godiet_seed.restype = i32
+        L.godiet_contain.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), u32, P, P, P, sz,
+                                     P, P]
+        L.godiet_contain.restype = i32
         L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
         L.godiet_lookup.restype = i32
         L.godiet_rmi_size.argtypes = [u32]
@@ -329,3 +332,24 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capac
             capacity = n
             continue
         return anchors[:4 * n].view(n, 4), off, shift[:reads.n_seq]
+
+
+def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, max_occ=0):
+    """Per-genome shared distinct minimizer counts against a 64-bit-val (genome id) index.
+    Returns (counts, sizes) int32 tensors (uint32 bits)."""
+    torch = _torch()
+    s = reads.c()
+    L = lib()
+    prm = _params(pattern, k, w)
+    ix = index.c()
+    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ))
+    ws = _empty(workspace_size(OP_CONTAIN, reads, pattern, k, w, index.n), torch.uint8)
+    counts = _empty(n_genomes, torch.int32)
+    sizes = _empty(n_genomes, torch.int32)
+    st = _empty(1, torch.int32)
+    _check(L.godiet_contain(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(prm),
+                            ctypes.byref(opts), int(n_genomes), _ptr(counts), _ptr(sizes),
+                            _ptr(ws), ws.numel(), _ptr(st), _stream()), "godiet_contain")
+    if _status_value(st) & STATUS_RANGE:
+        raise ValueError("an index record names a genome id >= n_genomes")
+    return counts[:n_genomes], sizes[:n_genomes]

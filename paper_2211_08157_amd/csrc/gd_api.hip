@@ -139,6 +139,53 @@ void plan_seed_ws(Bump &b, const godiet_seqs *reads, const Pattern &P, int w, ui
     o->scan = b.take<uint64_t>(scan_scratch(nr + 1));
 }
 
+// Pattern alignment front end shared by seeding and containment: every shift (or the
+// fixed one) is sparsified, sketched and looked up, then each read's shift is chosen.
+// With mark non-null the workspace also carries an index-sized byte array for it.
+godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, const Pattern &P,
+                         const godiet_sketch_params *prm, const godiet_seed_opts *opts, void *ws,
+                         size_t ws_bytes, uint8_t *shift_out, uint32_t *status, hipStream_t stream,
+                         SeedWs *Wp, AlignArgs *Ap, uint8_t **mark)
+{
+    if (index->n > 0 && (!index->keys || !index->vals)) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (opts->shift_mode < -1 || opts->shift_mode >= (int32_t)P.p) return GODIET_E_INVAL;
+    const uint64_t npb = kept_bound(reads, P);
+    const uint32_t n_shift = opts->shift_mode >= 0 ? 1u : P.p;
+    Bump b(ws);
+    SeedWs &W = *Wp;
+    plan_seed_ws(b, reads, P, prm->w, n_shift, &W);
+    if (mark) *mark = b.take<uint8_t>((index->n + 3) / 4 * 4);
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    const size_t nr = reads->n_seq;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    for (uint32_t si = 0; si < n_shift; si++) {
+        const uint32_t a = opts->shift_mode >= 0 ? (uint32_t)opts->shift_mode : si;
+        GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, status, stream));
+        uint64_t *mz = W.mzofs + si * (nr + 1);
+        uint64_t *qk = W.qkeys + si * W.stride;
+        uint32_t *qv = W.qvals + si * W.stride;
+        SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
+        GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
+                             prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
+        GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
+                             W.occ + si * W.stride, index->rmi, stream));
+    }
+    AlignArgs &A = *Ap;
+    A.mzofs = W.mzofs;
+    A.occ = W.occ;
+    A.lb = W.lb;
+    A.qval = W.qvals;
+    A.stride = W.stride;
+    A.n_reads = reads->n_seq;
+    A.n_shift = n_shift;
+    A.fixed_shift = opts->shift_mode;
+    A.align_t = opts->align_t;
+    A.max_occ = opts->max_occ;
+    GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, W.long_ids, W.long_n, stream));
+    return GODIET_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,10 +242,12 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
         plan_index_ws(b, seqs, P, prm->w, n_index, 8, &o);
         return b.off;
     }
-    case GODIET_OP_SEED: {
+    case GODIET_OP_SEED:
+    case GODIET_OP_CONTAIN: {
         if (!valid_params(prm, &P)) return 0;
         SeedWs o;
         plan_seed_ws(b, seqs, P, prm->w, P.p, &o);
+        if (op == GODIET_OP_CONTAIN) b.take<uint8_t>((n_index + 3) / 4 * 4);
         return b.off;
     }
     default: return 0;
@@ -285,45 +334,36 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
         !status)
         return GODIET_E_INVAL;
     if (index->val_bits != 32) return GODIET_E_UNSUPPORTED;
-    if (index->n > 0 && (!index->keys || !index->vals)) return GODIET_E_INVAL;
-    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
-    if (opts->shift_mode < -1 || opts->shift_mode >= (int32_t)P.p) return GODIET_E_INVAL;
     if (capacity > 0 && !anchors) return GODIET_E_INVAL;
-    const uint64_t npb = kept_bound(reads, P);
-    const uint32_t n_shift = opts->shift_mode >= 0 ? 1u : P.p;
-    Bump b(ws);
     SeedWs W;
-    plan_seed_ws(b, reads, P, prm->w, n_shift, &W);
-    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
-    const size_t nr = reads->n_seq;
-    GD_TRY(fill_u32(status, 0, 1, stream));
-    for (uint32_t si = 0; si < n_shift; si++) {
-        const uint32_t a = opts->shift_mode >= 0 ? (uint32_t)opts->shift_mode : si;
-        GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, status, stream));
-        uint64_t *mz = W.mzofs + si * (nr + 1);
-        uint64_t *qk = W.qkeys + si * W.stride;
-        uint32_t *qv = W.qvals + si * W.stride;
-        SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
-        GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
-                             prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
-        GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
-                             W.occ + si * W.stride, index->rmi, stream));
-    }
     AlignArgs A;
-    A.mzofs = W.mzofs;
-    A.occ = W.occ;
-    A.lb = W.lb;
-    A.qval = W.qvals;
-    A.stride = W.stride;
-    A.n_reads = reads->n_seq;
-    A.n_shift = n_shift;
-    A.fixed_shift = opts->shift_mode;
-    A.align_t = opts->align_t;
-    A.max_occ = opts->max_occ;
-    GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, W.long_ids, W.long_n, stream));
-    GD_TRY(exclusive_scan_u32(W.cnt, read_anchor_off, nr, W.scan, stream));
+    godiet_status st = seed_front(index, reads, P, prm, opts, ws, ws_bytes, shift_out, status,
+                                  stream, &W, &A, nullptr);
+    if (st != GODIET_OK) return st;
+    GD_TRY(exclusive_scan_u32(W.cnt, read_anchor_off, reads->n_seq, W.scan, stream));
     GD_TRY(launch_expand(A, W.slot, read_anchor_off, index->vals, (uint32_t *)anchors, capacity,
                          status, W.long_ids, W.long_n, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_contain(const godiet_index *index, const godiet_seqs *reads,
+                             const godiet_sketch_params *prm, const godiet_seed_opts *opts,
+                             uint32_t n_genomes, uint32_t *counts, uint32_t *genome_sizes,
+                             void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream)
+{
+    Pattern P;
+    if (!index || !valid_seqs(reads) || !valid_params(prm, &P) || !opts || !status)
+        return GODIET_E_INVAL;
+    if (index->val_bits != 64) return GODIET_E_UNSUPPORTED;
+    if (n_genomes > 0 && (!counts || !genome_sizes)) return GODIET_E_INVAL;
+    SeedWs W;
+    AlignArgs A;
+    uint8_t *mark = nullptr;
+    godiet_status st = seed_front(index, reads, P, prm, opts, ws, ws_bytes, nullptr, status,
+                                  stream, &W, &A, &mark);
+    if (st != GODIET_OK) return st;
+    GD_TRY(launch_contain(A, W.slot, index->keys, (const uint64_t *)index->vals, index->n, mark,
+                          n_genomes, counts, genome_sizes, status, stream));
     return GODIET_OK;
 }
 

@@ -158,4 +158,9 @@ hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot,
                          uint64_t capacity, uint32_t *status, const uint32_t *long_ids,
                          const uint32_t *long_n, hipStream_t s);
 
+// ---- containment counts (gd_contain.hip); mark holds ceil(in / 4) * 4 bytes
+hipError_t launch_contain(const AlignArgs &a, const uint32_t *shift_slot, const uint64_t *ikeys,
+                          const uint64_t *ivals, uint64_t in, uint8_t *mark, uint32_t n_genomes,
+                          uint32_t *counts, uint32_t *sizes, uint32_t *status, hipStream_t s);
+
 }  // namespace gd
