@@ -74,7 +74,7 @@ class Session:
         self.cix = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32, None, 0)
         self.cix_rmi = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
                                  self.rmi.data_ptr(), self.rmi.numel())
-        self.opts = api.SeedOpts(-1, 0, 0)
+        self.opts = api.SeedOpts(-1, 0, 0, 0, 0, 0)
         del ix, a, off
         # per-shift query counts (minimizers of the reads at every shift) for byte accounting
         self.queries = 0

@@ -109,6 +109,11 @@ typedef struct {
     uint32_t align_t;         /* 0: no limit; else at most t minimizers scored per shift */
     uint32_t max_occ;         /* 0: off; else minimizers with >= max_occ index hits are
                                  skipped in alignment scores and in seeding */
+    /* launch tuning, 0 = library default; these never change any result */
+    uint32_t long_records;    /* reads with more minimizer records (summed over the sketched
+                                 shifts) than this get a wave each instead of a thread */
+    uint32_t lookup_blocks;   /* workgroups of each lookup launch */
+    uint32_t long_blocks;     /* workgroups of the long-read alignment/expansion launches */
 } godiet_seed_opts;
 
 typedef struct {

@@ -36,7 +36,8 @@ class Index(ctypes.Structure):
 
 class SeedOpts(ctypes.Structure):
     _fields_ = [("shift_mode", ctypes.c_int32), ("align_t", ctypes.c_uint32),
-                ("max_occ", ctypes.c_uint32)]
+                ("max_occ", ctypes.c_uint32), ("long_records", ctypes.c_uint32),
+                ("lookup_blocks", ctypes.c_uint32), ("long_blocks", ctypes.c_uint32)]
 
 
 _lib = None
@@ -306,7 +307,8 @@ def index_build(ref, pattern, k, w, val_bits=32, capacity=None):
         return DeviceIndex(keys[:n], vals[:n], n, val_bits)
 
 
-def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capacity=None):
+def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capacity=None,
+         tuning=None):
     """Pattern alignment + compressed seeding.  Returns (anchors int32 tensor (n, 4) of
     read_id, qpos, rpos, strand; read_anchor_off int64 tensor; shift uint8 tensor)."""
     torch = _torch()
@@ -314,7 +316,9 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capac
     L = lib()
     prm = _params(pattern, k, w)
     ix = index.c()
-    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ))
+    t = tuning or {}
+    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), int(t.get("long_records", 0)),
+                    int(t.get("lookup_blocks", 0)), int(t.get("long_blocks", 0)))
     ws = _empty(workspace_size(OP_SEED, reads, pattern, k, w, index.n), torch.uint8)
     off = _empty(reads.n_seq + 1, torch.int64)
     shift = _empty(reads.n_seq, torch.uint8)
@@ -342,7 +346,7 @@ def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, ma
     L = lib()
     prm = _params(pattern, k, w)
     ix = index.c()
-    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ))
+    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), 0, 0, 0)
     ws = _empty(workspace_size(OP_CONTAIN, reads, pattern, k, w, index.n), torch.uint8)
     counts = _empty(n_genomes, torch.int32)
     sizes = _empty(n_genomes, torch.int32)

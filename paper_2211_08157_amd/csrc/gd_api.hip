@@ -169,7 +169,7 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
                              prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
-                             W.occ + si * W.stride, index->rmi, stream));
+                             W.occ + si * W.stride, index->rmi, opts->lookup_blocks, stream));
     }
     AlignArgs &A = *Ap;
     A.mzofs = W.mzofs;
@@ -182,6 +182,8 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
     A.fixed_shift = opts->shift_mode;
     A.align_t = opts->align_t;
     A.max_occ = opts->max_occ;
+    A.long_records = opts->long_records ? opts->long_records : 192u;
+    A.long_blocks = opts->long_blocks ? opts->long_blocks : 1024u;
     GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, W.long_ids, W.long_n, stream));
     return GODIET_OK;
 }
@@ -394,7 +396,7 @@ godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64
     if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
     if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
     if (n_q == 0) return GODIET_OK;
-    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, stream));
+    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, 0, stream));
     return GODIET_OK;
 }
 

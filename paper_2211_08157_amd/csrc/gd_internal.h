@@ -131,7 +131,7 @@ hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void
 // lb/occ of min(*n_q, q_cap) queries (n_q may be null: q_cap queries); rmi nullable.
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, hipStream_t s);
+                         const void *rmi, uint32_t blocks, hipStream_t s);
 
 // ---- learned index (gd_rmi.hip)
 size_t rmi_bytes(uint32_t log2_leaves);
@@ -148,6 +148,8 @@ struct AlignArgs {
     uint32_t n_shift;        // sketched shifts (p, or 1 for a fixed shift)
     int32_t fixed_shift;     // -1 when the shifts 0..p-1 were sketched
     uint32_t align_t, max_occ;
+    uint32_t long_records;   // reads with more records go to the wave-per-read kernels
+    uint32_t long_blocks;    // workgroups of those kernels
 };
 // Shift choice and per-read anchor counts; reads with many records go to long_ids
 // (n_reads entries) for a wave-per-read pass, long_n counts them.

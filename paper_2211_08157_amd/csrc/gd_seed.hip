@@ -60,9 +60,8 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
 }
 
 constexpr int kReadsPerBlock = kBlock / kWave;
-// Reads whose minimizer records (summed over the sketched shifts) exceed this are handled
-// by one wave each; shorter reads by one thread each.
-constexpr uint64_t kShortRecords = 192;
+// Reads whose minimizer records (summed over the sketched shifts) exceed A.long_records are
+// handled by one wave each; shorter reads by one thread each.
 
 // Records of read r at shift slot s: [mzofs[s][r], mzofs[s][r+1]).
 __device__ __forceinline__ uint64_t rec_beg(const AlignArgs &A, uint32_t s, uint32_t r)
@@ -110,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_align(AlignArgs A, uint8_t *shift_ou
 {
     const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= A.n_reads) return;
-    if (read_records(A, r) > kShortRecords) {
+    if (read_records(A, r) > A.long_records) {
         long_ids[atomicAdd(long_n, 1u)] = r;
         return;
     }
@@ -176,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(AlignArgs A, const uint32_t *
         if (r == 0) set_status(status, 1u);
         return;
     }
-    if (read_records(A, r) > kShortRecords) return;          // expanded by k_expand_long
+    if (read_records(A, r) > A.long_records) return;         // expanded by k_expand_long
     const uint32_t slot = shift_slot[r];
     const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
     const uint32_t *occ = A.occ + slot * A.stride;
@@ -238,10 +237,11 @@ __global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint3
 
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, hipStream_t s)
+                         const void *rmi, uint32_t max_blocks, hipStream_t s)
 {
     uint64_t blocks = (q_cap + kBlock - 1) / kBlock;
-    if (blocks > 8192) blocks = 8192;
+    const uint64_t cap = max_blocks ? max_blocks : 8192;
+    if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     if (rmi)
         GD_LAUNCH(k_lookup<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
@@ -261,7 +261,8 @@ hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_
     const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
     GD_LAUNCH(k_align, dim3(blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot, anchor_cnt,
               long_ids, long_n);
-    GD_LAUNCH(k_align_long, dim3(1024), dim3(kBlock), 0, s, a, shift_out, shift_slot, anchor_cnt,
+    GD_LAUNCH(k_align_long, dim3(a.long_blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot,
+              anchor_cnt,
               (const uint32_t *)long_ids, (const uint32_t *)long_n);
     return hipGetLastError();
 }
@@ -275,7 +276,7 @@ hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot, const u
     const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
     GD_LAUNCH(k_expand, dim3(blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
               (const uint32_t *)ivals, (uint4 *)anchors, capacity, status);
-    GD_LAUNCH(k_expand_long, dim3(1024), dim3(kBlock), 0, s, a, shift_slot, read_off,
+    GD_LAUNCH(k_expand_long, dim3(a.long_blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
               (const uint32_t *)ivals, (uint4 *)anchors, capacity, long_ids, long_n);
     return hipGetLastError();
 }

@@ -91,14 +91,14 @@ def test_host_rejects_bad_arguments_before_launch():
     ix = Index(0x4000, 0x5000, 100, 32, None, 0)
     for mode in (-2, 2):
         assert L.godiet_seed(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(good),
-                             ctypes.byref(SeedOpts(mode, 0, 0)), dummy, 10, dummy, None, dummy,
+                             ctypes.byref(SeedOpts(mode, 0, 0, 0, 0, 0)), dummy, 10, dummy, None, dummy,
                              1 << 40, dummy, None) == E_INVAL
     ix64 = Index(0x4000, 0x5000, 100, 64, None, 0)
     assert L.godiet_seed(ctypes.byref(ix64), ctypes.byref(s), ctypes.byref(good),
-                         ctypes.byref(SeedOpts(-1, 0, 0)), dummy, 10, dummy, None, dummy, 1 << 40,
+                         ctypes.byref(SeedOpts(-1, 0, 0, 0, 0, 0)), dummy, 10, dummy, None, dummy, 1 << 40,
                          dummy, None) == E_UNSUPPORTED
     assert L.godiet_seed(ctypes.byref(ix), ctypes.byref(s), ctypes.byref(good),
-                         ctypes.byref(SeedOpts(-1, 0, 0)), dummy, 10, None, None, dummy, 1 << 40,
+                         ctypes.byref(SeedOpts(-1, 0, 0, 0, 0, 0)), dummy, 10, None, None, dummy, 1 << 40,
                          dummy, None) == E_INVAL
 
 
