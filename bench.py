@@ -27,6 +27,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+# 256 CUs x 64 lanes x 2.4 GHz: int32 vector lane-operations per second, in GOP/s
+ALU_PEAK_GOPS = 256 * 64 * 2.4
+# Algorithmic int32 lane-operations of one k-mer in the sketch: forward and reverse-
+# complement codes 4, canonical choice and strand 3, the splitmix64 finalizer 17 (two
+# 64-bit multiplies of 4 each, three 64-bit xor-shifts of 3 each), window minimum and
+# opening with 3 amortised 64-bit compare-selects each (6 x 3 = 18).
+OPS_PER_KMER = 4 + 3 + 17 + 18
+# HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
+# kernel source; reported only while that source is unchanged.
+MEASURED_TRAFFIC = {
+    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="df3ccb0881a9fea7",
+                         bytes_per_step=427.3e6,
+                         summary="profiles/k_sketch_illumina-100Mbp_hbm_bytes.md"),
+}
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
 
 
@@ -42,6 +56,8 @@ class Session:
         from paper_2211_08157_amd import api
         self.torch, self.api, self.gd = torch, api, gd
         self.pattern, self.k, self.w = pattern, k, w
+        self.ref_offsets = np.asarray(data["ref_offsets"], np.int64)
+        self.read_lengths = np.diff(np.asarray(data["read_offsets"], np.int64))
         self.ref = gd.to_device(data["ref"], data["ref_offsets"])
         self.reads = gd.to_device(data["reads"], data["read_offsets"])
         self.prm = api.Params(pattern.encode(), k, w)
@@ -165,20 +181,69 @@ def cpu_baseline(data, pattern, k, w, sample_reads):
                                                                     n_reads, t2 - t1))
 
 
-def kernel_bytes(name, s):
-    """Algorithmic bytes of all launches of one kernel in one step (None if unmodelled)."""
-    ref_np = s.ref.n_bases // 2 if s.pattern == "10" else None
+def kept_counts(lengths, pattern, shift):
+    """Kept bases of sequences of the given lengths (closed form, for accounting)."""
+    p, x = len(pattern), pattern.count("1")
+    rot = [pattern[(t - shift) % p] == "1" for t in range(p)]
+    first = np.concatenate([[0], np.cumsum(rot)])          # ones among the first r phases
+    L = np.asarray(lengths, np.int64)
+    return (L // p) * x + first[L % p]
+
+
+def work_units(s):
+    """k-mers and patterned bases one step sketches (reference, then every read shift)."""
+    k = s.k
+    rl = np.diff(s.ref_offsets)
+    ref_np = int(kept_counts(rl, s.pattern, 0).sum())
+    ref_km = int(np.maximum(kept_counts(rl, s.pattern, 0) - k + 1, 0).sum())
+    read_np = read_km = 0
+    for a in range(len(s.pattern)):
+        kc = kept_counts(s.read_lengths, s.pattern, a)
+        read_np += int(kc.sum())
+        read_km += int(np.maximum(kc - k + 1, 0).sum())
+    return dict(ref_np=ref_np, ref_kmers=ref_km, read_np=read_np, read_kmers=read_km)
+
+
+def measured_traffic(name, launches_per_step):
+    """HBM bytes per launch from the committed counter runs, or None if the kernel's source
+    changed since they were taken."""
+    m = MEASURED_TRAFFIC.get(name)
+    if m is None:
+        return None
+    with open(os.path.join(ROOT, m["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != m["sha256_16"]:
+            return None
+    return m["bytes_per_step"] / launches_per_step
+
+
+def roofline(name, s, units, ms_total, steps, launches):
+    """Roofline entry of one kernel from its traced time over `steps` steps."""
+    sec = ms_total * 1e-3 / steps
+    base = dict(kernel=name, avg_launch_ms=ms_total / launches,
+                launches_per_step=launches / steps,
+                traffic=measured_traffic(name, launches / steps))
+    if name.startswith("k_sketch"):
+        kmers = units["ref_kmers"] + units["read_kmers"]
+        achieved = kmers * OPS_PER_KMER / sec / 1e9
+        by = (units["ref_np"] + units["read_np"]) / 4 + 12 * (s.n_index + s.queries)
+        base.update(bound="alu", achieved=achieved, peak=ALU_PEAK_GOPS, unit="GOP/s",
+                    frac=achieved / ALU_PEAK_GOPS, ops_per_kmer=OPS_PER_KMER,
+                    algorithmic_bytes_per_launch=by * steps / launches,
+                    hbm_view=dict(achieved=by / sec / 1e9, peak=HBM_PEAK_GBPS, unit="GB/s",
+                                  frac=by / sec / 1e9 / HBM_PEAK_GBPS))
+        return base
     if name.startswith("k_lookup"):
-        # query key in, (lb, occ) out, and one 64-byte line of the index per query
-        return s.queries * (8 + 8 + 64)
-    if name.startswith("k_sketch") and ref_np is not None:
-        reads_np = s.reads.n_bases // 2
-        return (ref_np + reads_np * len(s.pattern)) / 4 + 12 * (s.n_index + s.queries)
-    if name.startswith("k_bucket_sort") or name.startswith("k_scatter"):
-        return 24 * s.n_index
-    if name == "k_expand":
-        return 16 * s.n_anchors
-    return None
+        by = s.queries * (8 + 8 + 64)    # query in, (lb, occ) out, one 64-B index line
+    elif name.startswith("k_bucket_sort") or name.startswith("k_scatter"):
+        by = 24 * s.n_index
+    elif name.startswith("k_expand"):
+        by = 16 * s.n_anchors
+    else:
+        return None
+    achieved = by / sec / 1e9
+    base.update(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=achieved / HBM_PEAK_GBPS)
+    return base
 
 
 def main():
@@ -189,6 +254,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=200_000)
     ap.add_argument("--no-1gbp", action="store_true", help="skip the 1 Gbp reference sketch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for "
@@ -244,13 +311,10 @@ def main():
                   for kname, (n, ms) in sorted(trace.items(), key=lambda kv: -kv[1][1])}
     dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
     n_l, ms_l = trace[dom]
-    by = kernel_bytes(dom, s)
-    roof = None
-    if by is not None:
-        achieved = by * args.steps / (ms_l * 1e-3) / 1e9
-        roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBPS, traffic=None,
-                    avg_launch_ms=ms_l / n_l, launches_per_step=n_l / args.steps)
+    units = work_units(s)
+    roof = roofline(dom, s, units, ms_l, args.steps, n_l)
+    second = sorted(trace.items(), key=lambda kv: -kv[1][1])[1]
+    roof_next = roofline(second[0], s, units, second[1][1], args.steps, second[1][0])
 
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
@@ -293,6 +357,8 @@ def main():
                                       for kn, (n, ms) in modes["binary_search"]["trace"].items()}},
         "learned_vs_binary_speedup": modes["binary_search"]["ms_per_step"] / ms_step,
         "roofline": roof,
+        "roofline_second_kernel": roof_next,
+        "work_per_step": units,
         "cpu_baseline": cpu,
         "sketch_GBps": gbps, "sketch_ms": sk_ms, "sketch_bytes_rule": "ceil(L/4) + 12 B/minimizer",
         "sketch_kernels_ms": sk_kernels,
@@ -300,6 +366,12 @@ def main():
         "index_records": n_index, "anchors": n_anchors, "lookups_per_step": queries,
         "kernels": per_kernel, "output_sha256_16": digest,
     }
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 1 << 30
     print(json.dumps(out), flush=True)
 
 

@@ -186,7 +186,7 @@ godiet_status godiet_seed(const godiet_index *index, const godiet_seqs *reads,
                           uint8_t *shift_out, void *ws, size_t ws_bytes, uint32_t *status,
                           hipStream_t stream);
 
-/* Containment-style search (Section 2.2, the k-mer-set intersection behind containment
+/* Containment-style search (Section 2.3, the k-mer-set intersection behind containment
  * search; the paper then thresholds these counts): index is a multi-genome index built
  * with val_bits 64 (genome id = val >> 32).  H_sample = distinct hashes of every read's
  * minimizers at its aligned shift (alignment exactly as in godiet_seed, opts included);

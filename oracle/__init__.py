@@ -40,9 +40,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        override = os.environ.get("GODIET_ORACLE_LIB")
+        if override:
+            # a separately built copy (tests/oracle_mutants.py loads planted-mistake builds)
+            L = ctypes.CDLL(override)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
         L.gdo_mix64.argtypes = [u64]

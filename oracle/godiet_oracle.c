@@ -372,7 +372,7 @@ static int u64_cmp(const void *pa, const void *pb)
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
-/* Containment-style counts (the k-mer-set intersection of Section 2.2): H_sample is the
+/* Containment-style counts (the k-mer-set intersection of Section 2.3): H_sample is the
  * set of hashes of all reads' minimizers at their aligned shift; for genome g, H_g is the
  * set of hashes among index records whose val >> 32 == g (val_bits 64);
  * counts[g] = |H_sample intersect H_g| and sizes[g] = |H_g|. */
