@@ -148,7 +148,8 @@ godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const 
                               uint8_t *out_bases, uint64_t *out_offsets,
                               void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
 
-/* Minimizer sketch (Section 3.1 step 3, "double-strand (w,k)-minimizer"; Section 3.6.1):
+/* Minimizer sketch (Section 3.1 step 3, canonical (w,k)-minimizers of both strands;
+ * Section 3.6.1):
  * the minimizers of every sequence, sparsified with its shift (NULL: 0), as records
  * keys[i] = hash, vals[i] = position << 1 | strand (position in that sequence's own
  * original coordinates), in ascending sequence then position order.
@@ -199,8 +200,8 @@ godiet_status godiet_contain(const godiet_index *index, const godiet_seqs *reads
                              uint32_t n_genomes, uint32_t *counts, uint32_t *genome_sizes,
                              void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
 
-/* Exact-match lookups in a sorted index (Section 3.3, "finds exact matches of minimizers
- * ... by querying the seed index"): for every query q[i], lb[i] = first index e with
+/* Exact-match lookups in a sorted index (Section 3.3: each read minimizer is matched
+ * exactly against the seed index): for every query q[i], lb[i] = first index e with
  * keys[e] >= q[i] and occ[i] = number of e with keys[e] == q[i].  Uses index->rmi when it
  * is non-NULL, plain binary search otherwise; the results are identical either way.
  * q, lb, occ: device arrays of n_q entries.  Needs index->n < 2^32. */

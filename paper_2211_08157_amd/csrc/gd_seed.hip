@@ -4,9 +4,10 @@
 // Lookups are independent dependent-gather chains (a binary search over the sorted
 // keys, then a galloping search for the end of the run of equal keys), one lane per
 // query, so the kernel is bound by memory latency and the number of lines in flight.
-// Alignment and expansion run one wave64 per read: lanes stride over the read's
-// minimizer records and combine with wave reductions/scans, so anchors of a read are
-// written as one contiguous, coalesced run in (qpos, rpos) order.
+// Alignment and expansion take one thread per read when the read has few minimizer
+// records (short reads) and one wave64 per read from a device-built list otherwise (long
+// reads: lanes stride over the records and combine with wave reductions and scans); the
+// anchors of a read are written as one contiguous run in (qpos, rpos) order.
 #include "gd_internal.h"
 #include "gd_rmi_model.h"
 

@@ -12,8 +12,10 @@
 // Minimizer selection uses the identity: position i is a minimizer iff its hash equals
 // max over the valid windows containing i of the window minimum (every window minimum
 // is <= h_i, and equality holds exactly for the windows where i attains the minimum).
-// Both sliding reductions run by doubling in LDS.  The output is compacted in position
-// order with a single-pass decoupled look-back across tiles.
+// For w = 2..17 both sliding reductions run in registers (prefix and suffix scans of each
+// thread's 16 values plus two neighbour exchanges through LDS); other w use doubling in
+// LDS.  The output is compacted in position order with a single-pass decoupled look-back
+// across tiles.
 #include "gd_internal.h"
 
 namespace gd {
@@ -246,6 +248,12 @@ __device__ __forceinline__ uint64_t kmer_msb(uint32_t m0, uint32_t m1, uint32_t 
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Bits u in [0, 16) with u <= x.
+__device__ __forceinline__ uint32_t mask_le(int64_t x)
+{
+    return x < 0 ? 0u : (x >= 15 ? 0xFFFFu : (2u << x) - 1u);
+}
+
 // (li / x, li % x) without an integer divide: a double estimate, corrected.
 __device__ __forceinline__ void div_x(uint64_t li, uint32_t x, double inv_x, uint64_t *q,
                                       uint32_t *r)
@@ -472,28 +480,41 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 fv[u] = (pal ? 0u : 1u) | 2u | (strand ? 4u : 0u);
             }
         } else {
+            // The chunk meets a sequence end (reads put one into most chunks): bit masks of
+            // the positions whose k-mer (kv) and window (wv) fit in their sequence and of
+            // those in sequences long enough for one full window (okm), one run of the
+            // loop per sequence overlapping the chunk; then all 16 positions are hashed
+            // as in the interior and masked, without per-position branches.
+            uint32_t kv = 0, wv = 0, okm = 0;
+            {
+                uint64_t b = seq_beg, e = seq_end;
+                uint32_t s = seq;
+                int lo = 0;
+                while (true) {
+                    const int hi = e - (uint64_t)jc >= 16 ? 16 : (int)(e - (uint64_t)jc);
+                    const uint32_t span = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                    kv |= span & mask_le((int64_t)e - (int64_t)k - jc);
+                    wv |= span & mask_le((int64_t)e - (int64_t)(k + w - 1) - jc);
+                    if (e - b >= (uint64_t)(k + w - 1)) okm |= span;
+                    if (hi >= 16 || e >= np) break;
+                    s++;
+                    b = e;
+                    e = C.at(s + 1);
+                    lo = hi;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 16; u++) {
-                const uint64_t j = (uint64_t)jc + u;
-                if (j < np) {
-                    while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
-                    const bool kvalid = j + (uint64_t)k <= seq_end;
-                    const bool wvalid = j + (uint64_t)(k + w - 1) <= seq_end;
-                    const bool seq_ok = seq_end - seq_beg >= (uint64_t)(k + w - 1);
-                    if (kvalid) {
-                        const uint64_t X = kmer_lsb(w0, w1, w2, u);
-                        const uint64_t F = kmer_msb(mw0, mw1, mw2, u);
-                        const uint64_t rc = (~X) & A.kmask;
-                        const uint64_t fwd = F >> fsh;
-                        if (fwd == rc) {
-                            fv[u] = wvalid ? 2u : 0u;
-                        } else {
-                            const bool strand = rc < fwd;
-                            hv[u] = mix64(strand ? rc : fwd);
-                            fv[u] = (seq_ok ? 1u : 0u) | (wvalid ? 2u : 0u) | (strand ? 4u : 0u);
-                        }
-                    }
-                }
+                const uint64_t X = kmer_lsb(w0, w1, w2, u);
+                const uint64_t F = kmer_msb(mw0, mw1, mw2, u);
+                const uint64_t rc = (~X) & A.kmask;
+                const uint64_t fwd = F >> fsh;
+                const bool strand = rc < fwd;
+                const uint64_t h = mix64(strand ? rc : fwd);
+                const bool use = ((kv >> u) & 1u) && !((k & 1) == 0 && fwd == rc);
+                hv[u] = use ? h : kMax64;
+                fv[u] = (use && ((okm >> u) & 1u) ? 1u : 0u) | (((wv >> u) & 1u) << 1) |
+                        (strand ? 4u : 0u);
             }
         }
     }
