@@ -100,10 +100,9 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->sp = sort_plan(expected, capacity, val_bytes);
     o->so.hist = b.take<uint32_t>(o->sp.nfine);
     o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
-    o->so.cursor = b.take<uint32_t>(o->sp.nfine);
+    o->so.rank = b.take<uint32_t>(capacity);
     o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
-    o->so.tkeys = b.take<uint64_t>(capacity);
-    o->so.tvals = b.take<uint8_t>(capacity * 8);
+    o->so.trec = b.take<ulonglong2>(capacity);
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
     o->so.overflow_n = b.take<uint32_t>(1);

@@ -116,10 +116,9 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes);
 struct SortWs {
     uint32_t *hist;        // nfine
     uint64_t *fofs;        // nfine + 1
-    uint32_t *cursor;      // nfine
+    uint32_t *rank;        // capacity: rank of each record inside its fine bin
     uint64_t *scan_tmp;    // scan_scratch(nfine)
-    uint64_t *tkeys;       // capacity
-    void *tvals;           // capacity (4 or 8 bytes each)
+    ulonglong2 *trec;      // capacity: (key, value) records grouped by fine bin
     uint32_t *cstart;      // ncoarse + 1: first fine bin of each coarse bucket
     uint32_t *overflow;    // ncoarse
     uint32_t *overflow_n;  // 1

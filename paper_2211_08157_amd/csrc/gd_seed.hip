@@ -164,33 +164,79 @@ __global__ __launch_bounds__(kBlock) void k_align_long(AlignArgs A, uint8_t *shi
     }
 }
 
-// One thread per short read: its anchors in (qpos, index order) into a contiguous run.
+// Short reads: one wave per 64 consecutive reads (lane i holds read i's record range at
+// its chosen shift).  The wave walks the group's records in (read, record) order, one
+// record per lane, so neighbouring lanes read neighbouring records and write neighbouring
+// anchors; a record's anchors start at its read's offset plus the anchors of the read's
+// earlier records (a segmented wave scan, carried across chunks for the read that is
+// still open at a chunk's end).  Long reads contribute no records here.
 __global__ __launch_bounds__(kBlock) void k_expand(AlignArgs A, const uint32_t *shift_slot,
                                                    const uint64_t *read_off, const uint32_t *ivals,
                                                    uint4 *anchors, uint64_t capacity,
                                                    uint32_t *status)
 {
-    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= A.n_reads) return;
+    const uint64_t r64 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (read_off[A.n_reads] > capacity) {
-        if (r == 0) set_status(status, 1u);
+        if (r64 == 0) set_status(status, 1u);
         return;
     }
-    if (read_records(A, r) > A.long_records) return;         // expanded by k_expand_long
-    const uint32_t slot = shift_slot[r];
-    const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
-    const uint32_t *occ = A.occ + slot * A.stride;
-    const uint32_t *lb = A.lb + slot * A.stride;
-    const uint32_t *qv = A.qval + slot * A.stride;
-    uint64_t out = read_off[r];
-    for (uint64_t j = beg; j < end; j++) {
-        const uint32_t o = keep_occ(A, occ[j]);
-        const uint32_t l = lb[j], q = qv[j];
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t cnt = 0, slot = 0;
+    uint64_t beg = 0, out = 0;
+    if (r64 < A.n_reads) {
+        const uint32_t r = (uint32_t)r64;
+        if (read_records(A, r) <= A.long_records) {
+            slot = shift_slot[r];
+            beg = rec_beg(A, slot, r);
+            cnt = (uint32_t)(rec_beg(A, slot, r + 1) - beg);
+            out = read_off[r];
+        }
+    }
+    const uint32_t incl = wave_incl_scan<uint32_t>(cnt);
+    const uint32_t start = incl - cnt;                       // flat index of the first record
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    const uint64_t r_base = r64 - (uint64_t)lane;            // read id of lane 0
+    int open_read = -1;                                      // read still open across chunks
+    uint32_t open_sum = 0;                                   // its anchors so far
+    for (uint32_t f0 = 0; f0 < total; f0 += kWave) {
+        const uint32_t f = f0 + (uint32_t)lane;
+        const bool valid = f < total;
+        // read of flat record f: the last lane i with start_i <= f
+        int i = 0;
+#pragma unroll
+        for (int step = kWave / 2; step >= 1; step >>= 1) {
+            const uint32_t st = __shfl(start, i + step, kWave);
+            if (st <= f) i += step;
+        }
+        const uint32_t i_slot = __shfl(slot, i, kWave);
+        const uint64_t i_beg = __shfl(beg, i, kWave);
+        const uint32_t i_start = __shfl(start, i, kWave);
+        const uint64_t i_out = __shfl(out, i, kWave);
+        uint32_t o = 0, l = 0, q = 0;
+        if (valid) {
+            const size_t jj = (size_t)i_slot * A.stride + i_beg + (f - i_start);
+            o = keep_occ(A, A.occ[jj]);
+            l = A.lb[jj];
+            q = A.qval[jj];
+        }
+        // segmented exclusive scan of o by read
+        const uint32_t oi = wave_incl_scan<uint32_t>(o);
+        const uint32_t oe = oi - o;
+        const int prev_i = __shfl_up(i, 1, kWave);
+        const bool head = lane == 0 || prev_i != i;
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        const int hl = 63 - __clzll((long long)upto);
+        const uint32_t seg = oe - __shfl(oe, hl, kWave) + (i == open_read ? open_sum : 0u);
+        const uint32_t r = (uint32_t)(r_base + (uint64_t)i);
+        const uint64_t pos = i_out + seg;
         for (uint32_t e = 0; e < o; e++) {
             const uint32_t v = ivals[l + e];
-            anchors[out + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
+            anchors[pos + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
         }
-        out += o;
+        const int lv = (int)min((uint32_t)(kWave - 1), total - 1 - f0);
+        open_read = __shfl(i, lv, kWave);
+        open_sum = __shfl(seg + o, lv, kWave);
     }
 }
 
@@ -274,7 +320,7 @@ hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot, const u
                          hipStream_t s)
 {
     if (a.n_reads == 0) return hipSuccess;
-    const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
+    const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;     // one lane per read
     GD_LAUNCH(k_expand, dim3(blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
               (const uint32_t *)ivals, (uint4 *)anchors, capacity, status);
     GD_LAUNCH(k_expand_long, dim3(a.long_blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,

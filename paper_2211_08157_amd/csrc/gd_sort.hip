@@ -4,10 +4,11 @@
 // times denser than large ones, and fixed top-bit buckets overflow at the dense end.
 // The partition is therefore data driven:
 //   1. a fine histogram over the top Bf bits (about 2 records per fine bin on average,
-//      a few times more at the dense low end);
+//      a few times more at the dense low end); the value each record's atomic returns
+//      is its rank inside its bin;
 //   2. its exclusive scan gives the start of every fine bin;
-//   3. a scatter moves each record into its fine bin (one atomic per record, spread
-//      over ~N/2 addresses);
+//   3. a scatter moves each record to bin start + rank as one 16-byte (key, value)
+//      record (no atomics: the ranks are already known);
 //   4. coarse bucket c is the run of fine bins whose start lies in [c*T, (c+1)*T), so
 //      every coarse bucket holds about T records whatever the key distribution (its
 //      first fine bin comes from one pass over the fine bins); one workgroup loads it
@@ -36,30 +37,28 @@ __device__ __forceinline__ bool rec_less(uint64_t ka, V va, uint64_t kb, V vb)
 }
 
 __global__ __launch_bounds__(kBlock) void k_hist(const uint64_t *keys, const uint64_t *n_ptr,
-                                                 uint64_t capacity, int Bf, uint32_t *hist)
+                                                 uint64_t capacity, int Bf, uint32_t *hist,
+                                                 uint32_t *rank)
 {
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock)
-        atomicAdd(&hist[keys[i] >> (64 - Bf)], 1u);
+        rank[i] = atomicAdd(&hist[keys[i] >> (64 - Bf)], 1u);
 }
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const V *vals,
                                                     const uint64_t *n_ptr, uint64_t capacity,
                                                     int Bf, const uint64_t *fofs,
-                                                    uint32_t *cursor, uint64_t *tkeys, V *tvals)
+                                                    const uint32_t *rank, ulonglong2 *trec)
 {
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t key = keys[i];
-        const uint64_t f = key >> (64 - Bf);
-        const uint64_t pos = fofs[f] + atomicAdd(&cursor[f], 1u);
-        tkeys[pos] = key;
-        tvals[pos] = vals[i];
+        trec[fofs[key >> (64 - Bf)] + rank[i]] = make_ulonglong2(key, (uint64_t)vals[i]);
     }
 }
 
@@ -122,7 +121,7 @@ __device__ void insertion_sort(uint64_t *K, V *Vv, int lo, int hi)
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, const V *tvals,
+__global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
                                                         const uint64_t *fofs, const uint32_t *cstart,
                                                         int Bf, uint64_t *okeys, V *ovals,
                                                         uint32_t *overflow, uint32_t *overflow_n)
@@ -141,7 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, c
     }
     const int n = (int)n64;
     const int t = threadIdx.x;
-    for (int i = t; i < n; i += kBlock) { K[i] = tkeys[base + i]; Vv[i] = tvals[base + i]; }
+    for (int i = t; i < n; i += kBlock) {
+        const ulonglong2 r = trec[base + i];
+        K[i] = r.x;
+        Vv[i] = (V)r.y;
+    }
     __syncthreads();
     // the records are grouped by fine bin; each segment (run of one fine bin) is sorted by
     // the thread that owns its first record.  Sorting permutes records inside a segment
@@ -160,10 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const uint64_t *tkeys, c
     for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
 }
 
-// Fallback for coarse buckets larger than the LDS capacity: sort runs in LDS (in place in
-// the scatter buffer), then merge pairs of runs by ranking (an element's output index is
+// Fallback for coarse buckets larger than the LDS capacity: sort runs of kCap records in
+// LDS into the output, then merge pairs of runs by ranking (an element's output index is
 // its index in its own run plus the number of smaller elements in the other run),
-// ping-ponging between the scatter buffer and the output.
+// ping-ponging between the output and the bucket's own part of the scatter buffer (16
+// bytes per record, reused as separate key and value arrays once its records are read).
 template <typename V>
 __device__ uint64_t rank_in(const uint64_t *K, const V *Vv, uint64_t lo, uint64_t n, uint64_t kx,
                             V vx)
@@ -178,8 +182,7 @@ __device__ uint64_t rank_in(const uint64_t *K, const V *Vv, uint64_t lo, uint64_
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *tvals,
-                                                            const uint64_t *fofs,
+__global__ __launch_bounds__(kBlock) void k_bucket_sort_big(ulonglong2 *trec, const uint64_t *fofs,
                                                             const uint32_t *cstart,
                                                             const uint32_t *overflow,
                                                             const uint32_t *overflow_n,
@@ -196,20 +199,21 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(uint64_t *tkeys, V *
         for (uint64_t r0 = 0; r0 < n; r0 += kCap) {
             const int m = (int)min((uint64_t)kCap, n - r0);
             for (int i = threadIdx.x; i < m; i += kBlock) {
-                K[i] = tkeys[base + r0 + i];
-                Vv[i] = tvals[base + r0 + i];
+                const ulonglong2 r = trec[base + r0 + i];
+                K[i] = r.x;
+                Vv[i] = (V)r.y;
             }
             __syncthreads();
             lds_bitonic<V>(K, Vv, m);
             for (int i = threadIdx.x; i < m; i += kBlock) {
-                tkeys[base + r0 + i] = K[i];
-                tvals[base + r0 + i] = Vv[i];
+                okeys[base + r0 + i] = K[i];
+                ovals[base + r0 + i] = Vv[i];
             }
             __syncthreads();
         }
-        uint64_t *sk = tkeys + base, *dk = okeys + base;
-        V *sv = tvals + base, *dv = ovals + base;
-        bool in_out = false;
+        uint64_t *sk = okeys + base, *dk = (uint64_t *)(trec + base);
+        V *sv = ovals + base, *dv = (V *)(dk + n);
+        bool in_out = true;
         for (uint64_t width = kCap; width < n; width *= 2) {
             for (uint64_t lo = 0; lo < n; lo += 2 * width) {
                 const uint64_t mid = min(lo + width, n), hi = min(lo + 2 * width, n);
@@ -241,22 +245,23 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
 {
     hipError_t e;
     if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
-    if ((e = fill_u32(w.cursor, 0, sp.nfine, s)) != hipSuccess) return e;
     if ((e = fill_u32(w.overflow_n, 0, 1, s)) != hipSuccess) return e;
     const unsigned grid = 4096;
-    GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.Bf, w.hist);
+    GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.Bf, w.hist,
+              w.rank);
     if ((e = exclusive_scan_u32(w.hist, w.fofs, sp.nfine, w.scan_tmp, s)) != hipSuccess) return e;
     GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity, sp.Bf,
-              w.fofs, w.cursor, w.tkeys, (V *)w.tvals);
+              (const uint64_t *)w.fofs, (const uint32_t *)w.rank, w.trec);
     if ((e = fill_u32(w.cstart, (uint32_t)sp.nfine, sp.ncoarse + 1, s)) != hipSuccess) return e;
     GD_LAUNCH(k_coarse_starts, dim3((unsigned)((sp.nfine + kBlock) / kBlock)), dim3(kBlock), 0, s,
               (const uint64_t *)w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, w.cstart,
               (uint64_t)sp.ncoarse + 1);
-    GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s, w.tkeys,
-              (const V *)w.tvals, w.fofs, (const uint32_t *)w.cstart, sp.Bf, keys, vals,
-              w.overflow, w.overflow_n);
-    GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.tkeys, (V *)w.tvals, w.fofs,
-              (const uint32_t *)w.cstart, w.overflow, w.overflow_n, keys, vals);
+    GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
+              (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs, (const uint32_t *)w.cstart,
+              sp.Bf, keys, vals, w.overflow, w.overflow_n);
+    GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.trec,
+              (const uint64_t *)w.fofs, (const uint32_t *)w.cstart,
+              (const uint32_t *)w.overflow, (const uint32_t *)w.overflow_n, keys, vals);
     return hipGetLastError();
 }
 
