@@ -99,9 +99,21 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     lf.err_hi = 0;
     lf.pad = 0;
     const uint64_t m = hi > lo ? hi - lo : 0;
+    // (the key loops take 8 keys per step so that 8 loads are in flight per thread)
     if (m >= 2) {
         double sx = 0, sy = 0, sxx = 0, sxy = 0;
-        for (uint64_t i = lo; i < hi; i++) {
+        uint64_t i = lo;
+        for (; i + 8 <= hi; i += 8) {
+            uint64_t kk[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) kk[u] = keys[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const double x = (double)(kk[u] - lf.kmin), y = (double)(i + u - lo);
+                sx += x; sy += y; sxx += x * x; sxy += x * y;
+            }
+        }
+        for (; i < hi; i++) {
             const double x = (double)(keys[i] - lf.kmin), y = (double)(i - lo);
             sx += x; sy += y; sxx += x * x; sxy += x * y;
         }
@@ -112,12 +124,21 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     }
     // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]
     int64_t elo = 0, ehi = 0;
-    for (uint64_t i = lo; i < hi; i++) {
-        if (i > lo && keys[i] == keys[i - 1]) continue;
-        const int64_t p = predict(lf, keys[i]);
-        const int64_t d = (int64_t)i - p;
-        if (d > ehi) ehi = d;
-        if (-d > elo) elo = -d;
+    uint64_t prev = 0;
+    for (uint64_t i0 = lo; i0 < hi; i0 += 8) {
+        uint64_t kk[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) kk[u] = i0 + u < hi ? keys[i0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint64_t i = i0 + u;
+            if (i < hi && (i == lo || kk[u] != prev)) {
+                const int64_t d = (int64_t)i - predict(lf, kk[u]);
+                if (d > ehi) ehi = d;
+                if (-d > elo) elo = -d;
+            }
+            prev = kk[u];
+        }
     }
     lf.err_lo = (int32_t)(elo < 0x7fffffff ? elo : 0x7fffffff);
     lf.err_hi = (int32_t)(ehi < 0x7fffffff ? ehi : 0x7fffffff);

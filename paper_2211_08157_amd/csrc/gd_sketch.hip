@@ -135,12 +135,18 @@ __device__ __forceinline__ uint32_t unzip_even(uint64_t y)
 }
 
 // One thread per output word: gathers the 16 kept bases [16q, 16q+16) of the batch.
-// nbytes = ceil(n_bases / 4), the readable size of `bases`.
+// nbytes = ceil(n_bases / 4), the readable size of `bases`.  Three paths:
+//  * period 2 with one kept base, word inside one sequence: the 16 kept bases are every
+//    other base of a run of 32, one funnel shift and a bit unzip;
+//  * compact patterns (16 kept bases always within 49 original bases): per sequence
+//    segment of the word, one 64-base window of the input in registers, the kept phases
+//    walked as the set bits of the rotated pattern (no tables, no divisions per base);
+//  * otherwise one 2-bit load per base.
 __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const uint64_t *offsets,
                                                      uint32_t n_seq, Pattern P,
                                                      const uint32_t *shift, uint32_t uniform,
                                                      const uint64_t *pofs, uint32_t *psw,
-                                                     size_t words, uint64_t nbytes)
+                                                     size_t words, uint64_t nbytes, int compact)
 {
     __shared__ uint64_t sh_pofs[kSeqCache];
     __shared__ uint32_t sh_lohi[2];
@@ -153,17 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
     uint32_t word = 0;
     if (j0 < np) {
         uint32_t s = C.find(j0);
-        uint64_t end = C.at(s + 1);
-        while (j0 >= end) { s++; end = C.at(s + 1); }
+        uint64_t beg = C.at(s), end = C.at(s + 1);
+        while (j0 >= end) { s++; beg = end; end = C.at(s + 1); }
         uint32_t a = seq_shift(shift, uniform, s);
         if (a >= P.p) a = 0;
-        uint64_t li = j0 - C.at(s);
-        uint64_t per = li / P.x;                 // period index
-        uint32_t r = (uint32_t)(li - per * P.x); // rank within the period
-        uint64_t obase = offsets[s];
-        // period 2, one kept base: the 16 kept bases are every other base of a run of 32
         if (P.p == 2 && P.x == 1 && j0 + 16 <= end) {
-            const uint64_t o0 = obase + per * 2 + kept_phase(P, a, 0);
+            const uint64_t o0 = offsets[s] + ((j0 - beg) / P.x) * 2 + kept_phase(P, a, 0);
             const uint64_t g = o0 >> 4;
             if ((g + 3) * 4 <= nbytes) {
                 const uint32_t *wd = (const uint32_t *)bases;
@@ -175,20 +176,46 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                 return;
             }
         }
-        for (int u = 0; u < 16; u++) {
-            const uint64_t j = j0 + u;
+        int u = 0;
+        while (u < 16) {
+            const uint64_t j = j0 + (uint64_t)u;
             if (j >= np) break;
             if (j >= end) {
-                while (j >= end) { s++; end = C.at(s + 1); }
+                while (j >= end) { s++; beg = end; end = C.at(s + 1); }
                 a = seq_shift(shift, uniform, s);
                 if (a >= P.p) a = 0;
-                per = 0;
-                r = 0;
-                obase = offsets[s];
             }
-            const uint64_t o = obase + per * P.p + kept_phase(P, a, r);
-            word |= base_at(bases, o) << (2 * u);
-            if (++r == P.x) { r = 0; per++; }
+            const int seg = (int)min((uint64_t)(16 - u), end - j);   // bases of sequence s
+            const uint64_t li = j - beg;
+            const uint64_t per = li / P.x;
+            const uint32_t r = (uint32_t)(li - per * P.x);
+            const uint64_t rot = rotated_mask(P, a);
+            uint64_t m = rot;                      // kept phases of the period not yet used
+            for (uint32_t t = 0; t < r; t++) m &= m - 1;
+            const uint64_t ob = offsets[s] + per * P.p;                // period start
+            const uint64_t g = (ob + (uint64_t)__builtin_ctzll(m)) >> 4;
+            if (compact && (g + 4) * 4 <= nbytes) {
+                const uint32_t *wd = (const uint32_t *)bases;
+                const uint64_t lo64 = ((uint64_t)wd[g + 1] << 32) | wd[g];
+                const uint64_t hi64 = ((uint64_t)wd[g + 3] << 32) | wd[g + 2];
+                int64_t rel = (int64_t)(ob - 16 * g);                  // period start in window
+                for (int i = 0; i < seg; i++) {
+                    const int off = (int)(rel + __builtin_ctzll(m));   // < 64
+                    const uint64_t src = off < 32 ? lo64 : hi64;
+                    const uint32_t b2 = (uint32_t)(src >> (2 * (off & 31))) & 3u;
+                    word |= b2 << (2 * (u + i));
+                    m &= m - 1;
+                    if (m == 0) { m = rot; rel += P.p; }
+                }
+            } else {
+                uint64_t pb = ob;
+                for (int i = 0; i < seg; i++) {
+                    word |= base_at(bases, pb + (uint64_t)__builtin_ctzll(m)) << (2 * (u + i));
+                    m &= m - 1;
+                    if (m == 0) { m = rot; pb += P.p; }
+                }
+            }
+            u += seg;
         }
     }
     psw[q] = word;
@@ -682,8 +709,12 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
                            size_t words, hipStream_t s)
 {
     const size_t blocks = (words + kBlock - 1) / kBlock;
+    // 16 consecutive kept bases lie in at most ceil(15/x) + 1 periods; with that span
+    // <= 48 bases every base of a word's segment is inside a 64-base window that starts
+    // at most 15 bases before the segment's first kept base
+    const int compact = (int)(((15 + P.x - 1) / P.x + 1) * P.p <= 48);
     GD_LAUNCH(k_sparsify, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.bases, b.offsets,
-              b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4);
+              b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4, compact);
     return hipGetLastError();
 }
 

@@ -12,9 +12,10 @@
 //   4. coarse bucket c is the run of fine bins whose start lies in [c*T, (c+1)*T), so
 //      every coarse bucket holds about T records whatever the key distribution (its
 //      first fine bin comes from one pass over the fine bins); one workgroup loads it
-//      into LDS, sorts each run of one fine bin (already in key order relative to the
-//      others) by insertion sort, or the whole bucket by an LDS bitonic sort when a run is
-//      long (many equal hashes), and writes it back.  The work per bucket depends on its
+//      into LDS and writes every record to its segment's start plus its rank inside its
+//      run of one fine bin (runs are already in key order relative to each other), or
+//      sorts the whole bucket by an LDS bitonic sort when a run is long (many equal
+//      hashes).  The work per bucket depends on its
 //      records only, not on the number of (possibly empty) fine bins it spans.
 // A coarse bucket larger than the LDS capacity (only possible when one fine bin holds
 // thousands of records) is listed and sorted by a fallback kernel in global memory.
@@ -28,7 +29,7 @@ namespace {
 
 // records a workgroup sorts in LDS (a power of two, so bitonic padding fits)
 template <typename V> struct Cap { static constexpr int value = sizeof(V) == 4 ? 4096 : 2048; };
-constexpr int kSmall = 48;          // fine-bin size handled by insertion sort
+constexpr int kSmall = 48;          // longest fine-bin run placed by ranking
 
 template <typename V>
 __device__ __forceinline__ bool rec_less(uint64_t ka, V va, uint64_t kb, V vb)
@@ -104,23 +105,6 @@ __device__ void lds_bitonic(uint64_t *K, V *Vv, int n)
 }
 
 template <typename V>
-__device__ void insertion_sort(uint64_t *K, V *Vv, int lo, int hi)
-{
-    for (int i = lo + 1; i < hi; i++) {
-        const uint64_t kx = K[i];
-        const V vx = Vv[i];
-        int j = i - 1;
-        while (j >= lo && rec_less(kx, vx, K[j], Vv[j])) {
-            K[j + 1] = K[j];
-            Vv[j + 1] = Vv[j];
-            j--;
-        }
-        K[j + 1] = kx;
-        Vv[j + 1] = vx;
-    }
-}
-
-template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
                                                         const uint64_t *fofs, const uint32_t *cstart,
                                                         int Bf, uint64_t *okeys, V *ovals,
@@ -140,27 +124,57 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
     }
     const int n = (int)n64;
     const int t = threadIdx.x;
-    for (int i = t; i < n; i += kBlock) {
-        const ulonglong2 r = trec[base + i];
-        K[i] = r.x;
-        Vv[i] = (V)r.y;
+    constexpr int kPer = kCap / kBlock;
+    {
+        ulonglong2 r[kPer];                 // all loads in flight before the LDS stores
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            if (i < n) r[m] = trec[base + i];
+        }
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            if (i < n) { K[i] = r[m].x; Vv[i] = (V)r[m].y; }
+        }
     }
     __syncthreads();
-    // the records are grouped by fine bin; each segment (run of one fine bin) is sorted by
-    // the thread that owns its first record.  Sorting permutes records inside a segment
-    // only, so the bin seen at a neighbouring segment's edge never changes.
+    // The records are grouped by fine bin (a run of one bin is a segment).  Each record's
+    // final place is its segment's start plus the number of records of the segment that
+    // are smaller than it, so every thread places its own records independently.
     const int sh = 64 - Bf;
     int big = 0;
-    for (int i = t; i < n; i += kBlock) {
-        const uint64_t b = K[i] >> sh;
-        if (i > 0 && (K[i - 1] >> sh) == b) continue;
-        int e = i + 1;
-        while (e < n && (K[e] >> sh) == b) e++;
-        if (e - i > kSmall) big = 1;
-        else insertion_sort<V>(K, Vv, i, e);
+    int pos[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * kBlock;
+        pos[m] = i;
+        if (i >= n) continue;
+        const uint64_t k = K[i];
+        const V v = Vv[i];
+        const uint64_t b = k >> sh;
+        int lo = i, hi = i + 1;
+        while (lo > 0 && (K[lo - 1] >> sh) == b && i - lo < kSmall) lo--;
+        while (hi < n && (K[hi] >> sh) == b && hi - i < kSmall) hi++;
+        if ((lo > 0 && (K[lo - 1] >> sh) == b) || (hi < n && (K[hi] >> sh) == b) ||
+            hi - lo > kSmall) {
+            big = 1;                        // a long segment: the whole bucket is sorted below
+            continue;
+        }
+        int rank = 0;
+        for (int j = lo; j < hi; j++) rank += rec_less<V>(K[j], Vv[j], k, v) ? 1 : 0;
+        pos[m] = lo + rank;
     }
-    if (__syncthreads_or(big)) lds_bitonic<V>(K, Vv, n);
-    for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
+    if (__syncthreads_or(big)) {
+        lds_bitonic<V>(K, Vv, n);
+        for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
+        return;
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * kBlock;
+        if (i < n) { okeys[base + pos[m]] = K[i]; ovals[base + pos[m]] = Vv[i]; }
+    }
 }
 
 // Fallback for coarse buckets larger than the LDS capacity: sort runs of kCap records in
