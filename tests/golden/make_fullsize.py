@@ -1,0 +1,146 @@
+"""Record the oracle's results on the full-size workloads as digests.
+
+Writes tests/golden/fullsize_oracle.json, which the full-size GPU tests compare against.
+Every value in it comes from the oracle (oracle/) on inputs from datagen; nothing here
+calls the GPU library.  Run from the repository root:
+
+    python tests/golden/make_fullsize.py [--out FILE] [illumina] [uneven] [lookups] [containment]
+
+(no argument: all).  It needs about 20 GB of memory and takes tens of minutes on 8 cores.
+Seeding and lookups are split over threads by read and query ranges (each read's anchors
+and each query's result are independent of the others); index builds and containment
+counts run as one oracle call each.
+"""
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import datagen  # noqa: E402
+import fullsize  # noqa: E402
+import oracle  # noqa: E402
+
+OUT = os.path.join(HERE, "fullsize_oracle.json")
+K, W = 21, 11
+
+
+def log(msg, t0=[time.perf_counter()]):
+    print("[%7.1f s] %s" % (time.perf_counter() - t0[0], msg), flush=True)
+
+
+def parallel_seed(ik, iv, codes, offsets, pattern, chunk=20_000):
+    """oracle.seed over consecutive read ranges on threads (every read's anchors depend
+    only on that read and the index), stitched back into one batch's output."""
+    offsets = np.asarray(offsets, np.int64)
+    n_reads = offsets.size - 1
+    starts = list(range(0, n_reads, chunk))
+
+    def one(r0):
+        r1 = min(r0 + chunk, n_reads)
+        o = offsets[r0:r1 + 1] - offsets[r0]
+        return oracle.seed(ik, iv, codes[offsets[r0]:offsets[r1]], o, pattern, K, W)
+
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+        res = list(ex.map(one, starts))
+    total = sum(r[0].shape[0] for r in res)
+    anchors = np.empty((total, 4), np.uint32)
+    read_off = np.zeros(n_reads + 1, np.uint64)
+    shift = np.empty(n_reads, np.uint32)
+    pos = 0
+    for r0, (a, off, sh) in zip(starts, res):
+        m = a.shape[0]
+        anchors[pos:pos + m] = a
+        anchors[pos:pos + m, 0] += np.uint32(r0)
+        read_off[r0:r0 + off.size] = off + np.uint64(pos)
+        shift[r0:r0 + sh.size] = sh
+        pos += m
+    return anchors, read_off, shift
+
+
+def seed_entry(d, pattern):
+    ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], pattern, K, W)
+    log("%s %s: index %d records" % (d["name"], pattern, ik.size))
+    ent = dict(index=fullsize.index_digest(ik, iv))
+    a, off, sh = parallel_seed(ik, iv, d["reads"], d["read_offsets"], pattern)
+    log("%s %s: %d anchors" % (d["name"], pattern, a.shape[0]))
+    ent["anchors"] = fullsize.anchors_digest(a, off, sh)
+    return ent, ik
+
+
+def parallel_lookup(ik, q, chunk=10_000_000):
+    lb = np.empty(q.size, np.uint32)
+    occ = np.empty(q.size, np.uint32)
+
+    def one(lo):
+        hi = min(lo + chunk, q.size)
+        l, o = oracle.lookup(ik, q[lo:hi])
+        lb[lo:hi] = l
+        occ[lo:hi] = o
+
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+        list(ex.map(one, range(0, q.size, chunk)))
+    return lb, occ
+
+
+def main(which):
+    table = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            table = json.load(f)
+    oracle.lib()
+    if "illumina" in which:
+        d = datagen.workload_illumina()
+        log("illumina workload generated")
+        ent, _ = seed_entry(d, "10")
+        table["illumina-100Mbp/10"] = ent
+        del d
+    if "uneven" in which or "lookups" in which:
+        d = datagen.workload_uneven()
+        log("uneven workload generated")
+        for pattern in (["10", "110"] if "uneven" in which else []):
+            ent, ik = seed_entry(d, pattern)
+            table["uneven-1Gbp/" + pattern] = ent
+            del ik
+        if "lookups" in which:
+            ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], "10", K, W)
+            del iv
+            rk, _, _ = oracle.sketch(d["reads"], d["read_offsets"], "10", K, W)
+            log("lookups: %d index keys, %d read minimizers" % (ik.size, rk.size))
+            q = fullsize.lookup_queries(rk)
+            del rk
+            lb, occ = parallel_lookup(ik, q)
+            log("lookups: %d queries done" % q.size)
+            table["lookups-1Gbp/10"] = dict(lookups=fullsize.lookup_digest(lb, occ))
+            del q, lb, occ, ik
+        del d
+    if "containment" in which:
+        d = datagen.workload_containment()
+        log("containment workload generated")
+        ng = d["ref_offsets"].size - 1
+        ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], "10", K, W, val_bits=64)
+        log("containment: index %d records" % ik.size)
+        counts, sizes = oracle.contain(ik, iv, d["reads"], d["read_offsets"], "10", K, W, ng)
+        log("containment: counts done")
+        table["containment-1000/10"] = dict(index=fullsize.index_digest(ik, iv),
+                                            counts=counts.tolist(), sizes=sizes.tolist())
+        del d, ik, iv
+    with open(OUT, "w") as f:
+        json.dump(table, f, indent=0, sort_keys=True)
+        f.write("\n")
+    log("wrote " + OUT)
+
+
+if __name__ == "__main__":
+    args = sys.argv[1:]
+    if args[:1] == ["--out"]:
+        OUT = args[1]
+        args = args[2:]
+    main(set(args or ["illumina", "uneven", "lookups", "containment"]))

@@ -1,0 +1,175 @@
+"""Full-size parity: the library on the workloads at their real sizes, checked bit-exact
+against digests of the oracle's complete outputs on the same seeded inputs
+(tests/golden/fullsize_oracle.json, written by tests/golden/make_fullsize.py, which calls
+only the oracle).  Each digest covers every output element; its per-part digests name the
+part that differs when a check fails.
+
+  * Illumina-like 100 Mbp reference, 1M x 150 bp reads, '10', k21 w11: the benchmark's
+    own preallocated step (index build + seeding), with binary search and with the
+    learned index;
+  * 1 Gbp reference with one mixed batch of 2M short + 20k HiFi-like + 20k ONT-like reads,
+    '10' and '110': index build, then one HIP-graph-captured seeding pass with launch
+    parameters from the autotuner;
+  * 500M lookups (80 % drawn from that batch's read minimizers, 20 % random keys) in the
+    1 Gbp '10' index: learned index (MLP and linear roots, 2^18 leaves) equals binary
+    search equals the oracle; every result also satisfies the lower-bound property;
+  * 1,000-genome containment database with 10M reads: 64-bit-value index and per-genome
+    shared-minimizer counts, with binary search and with the learned index.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import fullsize
+
+pytestmark = pytest.mark.gpu
+K, W = 21, 11
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "fullsize_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def want(golden, key):
+    if key not in golden:
+        pytest.fail("no oracle digest for %s in %s" % (key, GOLDEN))
+    return golden[key]
+
+
+def host_u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def host_vals(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a.view(np.uint64)
+
+
+def assert_digest(got, exp, what):
+    bad = fullsize.diff_parts(got, exp)
+    assert got["n"] == exp["n"] and got["sha256"] == exp["sha256"], (
+        "%s differs from the oracle: n %d vs %d, differing parts %s"
+        % (what, got["n"], exp["n"], bad[:16]))
+
+
+@pytest.mark.timeout(900)
+def test_illumina_100mbp_benchmark_step(gpu, golden):
+    import bench
+    exp = want(golden, "illumina-100Mbp/10")
+    d = datagen.workload_illumina()
+    s = bench.Session(gpu, d, "10", K, W)
+    del d
+    for learned in (False, True):
+        s.step(learned)
+        s.check()
+        n = s.n_index
+        got = fullsize.index_digest(host_u64(s.ikeys[:n]), host_vals(s.ivals[:n]))
+        assert_digest(got, exp["index"], "index")
+        na = s.n_anchors
+        a = s.anchors[:4 * na].cpu().numpy().view(np.uint32)
+        got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
+        assert_digest(got, exp["anchors"], "anchors (learned index %s)" % learned)
+
+
+@pytest.fixture(scope="module")
+def uneven(gpu):
+    d = datagen.workload_uneven()
+    ref = gpu.to_device(d["ref"], d["ref_offsets"])
+    reads = gpu.to_device(d["reads"], d["read_offsets"])
+    return dict(ref=ref, reads=reads)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("pattern", ["10", "110"])
+def test_uneven_1gbp_graph_captured_autotuned(gpu, golden, uneven, pattern, tmp_path):
+    from paper_2211_08157_amd import autotune
+    from paper_2211_08157_amd.plan import SeedPlan
+    exp = want(golden, "uneven-1Gbp/" + pattern)
+    ix = gpu.index_build(uneven["ref"], pattern, K, W)
+    got = fullsize.index_digest(host_u64(ix.keys), host_vals(ix.vals))
+    assert_digest(got, exp["index"], "index")
+    # a small grid: every candidate's anchors are compared by the tuner itself
+    grid = {"long_records": [64, 192], "lookup_blocks": [8192], "long_blocks": [1024]}
+    tuning, report = autotune.tune(ix, uneven["reads"], pattern, K, W, grid=grid, reps=1,
+                                   cache=str(tmp_path / "tune.json"))
+    assert len(report) == 2
+    plan = SeedPlan(ix, uneven["reads"], pattern, K, W, tuning=tuning)
+    plan.capture()
+    plan.status.zero_()
+    plan.replay()
+    plan.check()
+    a, off, sh = plan.outputs()
+    got = fullsize.anchors_digest(a.cpu().numpy().view(np.uint32), host_u64(off),
+                                  sh.cpu().numpy())
+    assert_digest(got, exp["anchors"], "anchors")
+
+
+@pytest.mark.timeout(900)
+def test_learned_index_500m_lookups_1gbp(gpu, golden, uneven):
+    exp = want(golden, "lookups-1Gbp/10")["lookups"]
+    ix = gpu.index_build(uneven["ref"], "10", K, W)
+    rk, _, _ = gpu.sketch(uneven["reads"], "10", K, W)
+    q = fullsize.lookup_queries(host_u64(rk))
+    del rk
+    qd = torch.from_numpy(q.view(np.int64)).cuda()
+    del q
+    lb0, occ0 = gpu.lookup(ix, qd)
+    for root in ("mlp", "linear"):
+        lb1, occ1 = gpu.lookup(gpu.rmi_train(ix, root=root, log2_leaves=18), qd)
+        assert torch.equal(lb0, lb1) and torch.equal(occ0, occ1), root
+        del lb1, occ1
+    # lower-bound property of every result: keys[lb-1] < q <= keys[lb], and the run
+    # [lb, lb+occ) holds exactly the keys equal to q (keys compared as unsigned)
+    keys = ix.keys
+    n = ix.n
+    flip = torch.tensor(-2**63, dtype=torch.int64, device=qd.device)
+    ks = keys ^ flip
+    qs = qd ^ flip
+    lb = lb0.to(torch.int64)
+    occ = occ0.to(torch.int64)
+    assert bool(((lb >= 0) & (lb + occ <= n)).all())
+    prev = ks[(lb - 1).clamp(min=0)]
+    assert bool(((lb == 0) | (prev < qs)).all())
+    at = ks[lb.clamp(max=n - 1)]
+    assert bool(((lb == n) | (at >= qs)).all())
+    assert bool(((occ == 0) | (at == qs)).all())
+    last = ks[(lb + occ - 1).clamp(min=0, max=n - 1)]
+    assert bool(((occ == 0) | (last == qs)).all())
+    after = ks[(lb + occ).clamp(max=n - 1)]
+    assert bool(((lb + occ == n) | (after != qs)).all())
+    del prev, at, last, after, lb, occ, ks, qs
+    got = fullsize.lookup_digest(lb0.cpu().numpy().view(np.uint32),
+                                 occ0.cpu().numpy().view(np.uint32))
+    assert got["n"] == 500_000_000
+    assert got["found"] == exp["found"] and got["occ_sum"] == exp["occ_sum"]
+    assert_digest(got, exp, "lookups")
+
+
+@pytest.mark.timeout(900)
+def test_containment_1000_genomes(gpu, golden):
+    exp = want(golden, "containment-1000/10")
+    d = datagen.workload_containment()
+    ng = d["ref_offsets"].size - 1
+    ref = gpu.to_device(d["ref"], d["ref_offsets"])
+    reads = gpu.to_device(d["reads"], d["read_offsets"])
+    del d
+    ix = gpu.index_build(ref, "10", K, W, val_bits=64)
+    del ref
+    got = fullsize.index_digest(host_u64(ix.keys), host_vals(ix.vals))
+    assert_digest(got, exp["index"], "index")
+    want_counts = np.array(exp["counts"], np.uint32)
+    want_sizes = np.array(exp["sizes"], np.uint32)
+    for index in (ix, gpu.rmi_train(ix, root="mlp", log2_leaves=18)):
+        counts, sizes = gpu.contain(index, reads, "10", K, W, ng)
+        c = counts.cpu().numpy().view(np.uint32)
+        s = sizes.cpu().numpy().view(np.uint32)
+        assert np.array_equal(s, want_sizes)
+        assert np.array_equal(c, want_counts), np.nonzero(c != want_counts)[0][:10]
