@@ -59,6 +59,7 @@ struct SketchWs {
     uint32_t *psw;
     uint64_t *tiles;
     uint32_t *counter;
+    uint32_t *lohi;       // per-window sequence ranges (sparsify blocks, then sketch tiles)
 };
 
 void plan_sketch_ws(Bump &b, uint32_t n_seq, uint64_t npb, int w, SketchWs *o)
@@ -69,6 +70,8 @@ void plan_sketch_ws(Bump &b, uint32_t n_seq, uint64_t npb, int w, SketchWs *o)
     o->psw = b.take<uint32_t>(psw_words(npb));
     o->tiles = b.take<uint64_t>(sketch_tiles_bound(npb, w));
     o->counter = b.take<uint32_t>(1);
+    const size_t a = sparsify_lohi(psw_words(npb)), t = 2 * sketch_tiles_bound(npb, w);
+    o->lohi = b.take<uint32_t>(a > t ? a : t);
 }
 
 // kept counts -> pofs -> patterned stream, for a per-sequence or uniform shift
@@ -81,7 +84,7 @@ hipError_t sparsify_to_stream(const godiet_seqs *in, const Pattern &P, const uin
     if (e != hipSuccess) return e;
     e = exclusive_scan_u64(W.kept, W.pofs, in->n_seq, W.scan, s);
     if (e != hipSuccess) return e;
-    return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, psw_words(npb), s);
+    return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, psw_words(npb), W.lohi, s);
 }
 
 struct IndexWs {
@@ -166,7 +169,7 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         uint32_t *qv = W.qvals + si * W.stride;
         SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
-                             prm->w, o, W.sk.tiles, W.sk.counter, status, stream));
+                             prm->w, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
                              W.occ + si * W.stride, index->rmi, opts->lookup_blocks, stream));
     }
@@ -229,6 +232,7 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
         if (!prm || !parse_pattern(prm->pattern, &P)) return 0;
         b.take<uint64_t>((size_t)seqs->n_seq + 1);
         b.take<uint64_t>(scan_scratch((size_t)seqs->n_seq + 1));
+        b.take<uint32_t>(sparsify_lohi(psw_words(kept_bound(seqs, P))));
         return b.off;
     }
     case GODIET_OP_SKETCH: {
@@ -266,14 +270,15 @@ godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const 
     Bump b(ws);
     uint64_t *kept = b.take<uint64_t>((size_t)in->n_seq + 1);
     uint64_t *scan = b.take<uint64_t>(scan_scratch((size_t)in->n_seq + 1));
+    const uint64_t npb = kept_bound(in, P);
+    uint32_t *lohi = b.take<uint32_t>(sparsify_lohi(psw_words(npb)));
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     const Batch bt = batch_of(in);
-    const uint64_t npb = kept_bound(in, P);
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(launch_kept(bt, P, shift, 0, kept, status, stream));
     GD_TRY(exclusive_scan_u64(kept, out_offsets, in->n_seq, scan, stream));
     GD_TRY(launch_sparsify(bt, P, shift, 0, out_offsets, (uint32_t *)out_bases, psw_words(npb),
-                           stream));
+                           lohi, stream));
     return GODIET_OK;
 }
 
@@ -294,7 +299,7 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
     GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, status, stream));
     SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
     GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, npb, prm->k, prm->w, o, W.tiles,
-                         W.counter, status, stream));
+                         W.counter, W.lohi, status, stream));
     return GODIET_OK;
 }
 
@@ -319,7 +324,7 @@ godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_par
     GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));
     SketchOut o{keys, vals, val_bits == 32 ? VAL_GLOBAL32 : VAL_SEQ64, nullptr, capacity, n_out};
     GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, npb, prm->k, prm->w, o,
-                         W.sk.tiles, W.sk.counter, status, stream));
+                         W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
     if (capacity > 0) GD_TRY(launch_sort(W.sp, W.so, keys, vals, vb, n_out, capacity, stream));
     return GODIET_OK;
 }

@@ -83,7 +83,9 @@ hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
 // Patterned stream (uint32 words, 16 bases each) of `words` words from pofs.
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           size_t words, hipStream_t s);
+                           size_t words, uint32_t *lohi, hipStream_t s);
+// Entries of the lohi scratch a sparsify of `words` output words needs.
+inline size_t sparsify_lohi(size_t words) { return 2 * ((words + 255) / 256) + 2; }
 
 struct SketchOut {
     uint64_t *keys;
@@ -98,8 +100,8 @@ size_t sketch_tiles_bound(uint64_t np_bound, int w);
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
                          uint64_t np_bound, int k, int w, const SketchOut &o,
-                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *status,
-                         hipStream_t s);
+                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
+                         uint32_t *status, hipStream_t s);
 
 // Words of the patterned stream buffer for an upper bound on kept bases.
 inline size_t psw_words(uint64_t np_bound) { return (size_t)(np_bound / 16) + 8; }

@@ -72,30 +72,46 @@ struct SeqCache {
     }
 };
 
-// Fill the cache for positions [jlo, jhi] (all threads of the workgroup call this).
-__device__ __forceinline__ SeqCache seq_cache(const uint64_t *pofs, uint32_t n_seq, uint64_t jlo,
-                                              uint64_t jhi, uint64_t *sh, uint32_t *sh_lohi)
+// Sequences holding the first and last position of window i of the patterned stream,
+// for all windows at once (one thread each), so that no workgroup starts with a serial
+// search over the batch's offsets.  Window i covers [max(i*stride - before, 0),
+// i*stride - before + span] clamped to the stream; lohi[2i] and lohi[2i+1] are the first and
+// last sequence (both n_seq when the window lies past the stream's end).
+__global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, uint32_t n_seq,
+                                                        uint64_t stride, uint64_t before,
+                                                        uint64_t span, uint64_t count,
+                                                        uint32_t *lohi)
 {
-    if (threadIdx.x == 0) {
-        const uint64_t np = pofs[n_seq];
-        uint32_t lo = 0, n = 0;
-        if (np > 0 && jlo < np) {
-            if (jhi >= np) jhi = np - 1;
-            lo = last_le(pofs, n_seq, jlo);
-            const uint32_t hi = last_le(pofs, n_seq, jhi);
-            n = hi - lo + 1;                 // sequences lo..hi, boundaries lo..hi+1
-            if (n + 1 > (uint32_t)kSeqCache) n = 0;
-        }
-        sh_lohi[0] = lo;
-        sh_lohi[1] = n;
+    const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t np = pofs[n_seq];
+    const int64_t a0 = (int64_t)(i * stride) - (int64_t)before;
+    const uint64_t a = a0 > 0 ? (uint64_t)a0 : 0;
+    const int64_t b0 = a0 + (int64_t)span;
+    uint64_t b = b0 > 0 ? (uint64_t)b0 : 0;
+    uint32_t lo = n_seq, hi = n_seq;
+    if (a < np) {
+        if (b >= np) b = np - 1;
+        lo = last_le(pofs, n_seq, a);
+        hi = last_le(pofs, n_seq, b);
     }
-    __syncthreads();
+    lohi[2 * i] = lo;
+    lohi[2 * i + 1] = hi;
+}
+
+// Fill the cache with the boundaries of sequences lo..hi from k_window_seqs (all threads
+// of the workgroup call this).
+__device__ __forceinline__ SeqCache seq_cache(const uint64_t *pofs, uint32_t n_seq,
+                                              const uint32_t *lohi, uint64_t win, uint64_t *sh)
+{
     SeqCache c;
     c.pofs = pofs;
     c.n_seq = n_seq;
     c.sh = sh;
-    c.lo = sh_lohi[0];
-    c.n = sh_lohi[1];
+    const uint32_t lo = lohi[2 * win], hi = lohi[2 * win + 1];
+    c.lo = lo;
+    c.n = lo < n_seq ? hi - lo + 1 : 0;      // sequences lo..hi, boundaries lo..hi+1
+    if (c.n + 1 > (uint32_t)kSeqCache) c.n = 0;
     for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += kBlock) sh[i] = pofs[c.lo + i];
     __syncthreads();
     return c;
@@ -146,12 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                                                      uint32_t n_seq, Pattern P,
                                                      const uint32_t *shift, uint32_t uniform,
                                                      const uint64_t *pofs, uint32_t *psw,
-                                                     size_t words, uint64_t nbytes, int compact)
+                                                     size_t words, uint64_t nbytes, int compact,
+                                                     const uint32_t *lohi)
 {
     __shared__ uint64_t sh_pofs[kSeqCache];
-    __shared__ uint32_t sh_lohi[2];
-    const uint64_t blk0 = (uint64_t)blockIdx.x * kBlock * 16;
-    const SeqCache C = seq_cache(pofs, n_seq, blk0, blk0 + kBlock * 16 - 1, sh_pofs, sh_lohi);
+    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs);
     const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
     if (q >= words) return;
     const uint64_t np = pofs[n_seq];
@@ -245,6 +260,7 @@ struct SketchArgs {
     uint64_t capacity;
     uint64_t *n_out;
     uint64_t *tile_state;
+    const uint32_t *lohi;           // per-tile sequence range (k_window_seqs)
     uint32_t *tile_counter;
     uint32_t *status;
 };
@@ -675,7 +691,6 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     __shared__ uint64_t sh_base;
     __shared__ uint32_t sh_tile;
     __shared__ uint64_t sh_pofs[kSeqCache];
-    __shared__ uint32_t sh_lohi[2];
 
     const uint64_t np = A.pofs[A.n_seq];
     const uint64_t n_tiles = np / (uint64_t)A.T + 1;    // the last tile covers position np
@@ -685,10 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     __syncthreads();
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
-    const int64_t j0 = (int64_t)(tile * (uint64_t)A.T);
-    const uint64_t jlo = j0 > A.H ? (uint64_t)(j0 - A.H) : 0;
-    const SeqCache C = seq_cache(A.pofs, A.n_seq, jlo, (uint64_t)(j0 + A.T + A.H + 48), sh_pofs,
-                                 sh_lohi);
+    const SeqCache C = seq_cache(A.pofs, A.n_seq, A.lohi, tile, sh_pofs);
     sketch_tile<W>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C);
 }
 
@@ -706,28 +718,37 @@ hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
 
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           size_t words, hipStream_t s)
+                           size_t words, uint32_t *lohi, hipStream_t s)
 {
     const size_t blocks = (words + kBlock - 1) / kBlock;
+    if (blocks == 0) return hipSuccess;
+    GD_LAUNCH(k_window_seqs, dim3((unsigned)((blocks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+              pofs, b.n_seq, (uint64_t)kBlock * 16, (uint64_t)0, (uint64_t)kBlock * 16 - 1,
+              (uint64_t)blocks, lohi);
     // 16 consecutive kept bases lie in at most ceil(15/x) + 1 periods; with that span
     // <= 48 bases every base of a word's segment is inside a 64-base window that starts
     // at most 15 bases before the segment's first kept base
     const int compact = (int)(((15 + P.x - 1) / P.x + 1) * P.p <= 48);
     GD_LAUNCH(k_sparsify, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.bases, b.offsets,
-              b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4, compact);
+              b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4, compact,
+              (const uint32_t *)lohi);
     return hipGetLastError();
 }
 
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
                          uint64_t np_bound, int k, int w, const SketchOut &o,
-                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *status,
-                         hipStream_t s)
+                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
+                         uint32_t *status, hipStream_t s)
 {
     const TileGeom g = tile_geom(w);
     const size_t tiles = sketch_tiles_bound(np_bound, w);
     hipError_t e = fill_u64(tile_state, 0, tiles, s);
     if (e != hipSuccess) return e;
+    // tile t covers [t*T - H, t*T + T + H + 48] (the last 48 for the record loop's lookups)
+    GD_LAUNCH(k_window_seqs, dim3((unsigned)((tiles + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+              pofs, b.n_seq, (uint64_t)g.T, (uint64_t)g.H, (uint64_t)(g.T + 2 * g.H + 48),
+              (uint64_t)tiles, lohi);
     e = fill_u32(tile_counter, 0, 1, s);
     if (e != hipSuccess) return e;
     SketchArgs A;
@@ -750,6 +771,7 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     A.capacity = o.capacity;
     A.n_out = o.n_out;
     A.tile_state = tile_state;
+    A.lohi = lohi;
     A.tile_counter = tile_counter;
     A.status = status;
     A.inv_x = 1.0 / (double)P.x;
