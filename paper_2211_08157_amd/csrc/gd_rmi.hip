@@ -6,11 +6,12 @@
 //   root parameters                linear: leaf = a*x + b;  MLP: 1 -> 32 ReLU -> 1 with
 //                                  hidden unit i = relu(x - t_i), out = c0 + sum c_i h_i,
 //                                  x = key * 2^-64 (FP32), out = predicted rank / n
-//   RmiLeaf[L]                     first key, base position, slope, intercept, errors
+//   RmiLeaf[L]                     16 bytes: high half of the first key, base
+//                                  position, slope, FP16 intercept, 8-bit errors
 //
 // Routing is monotone in the key (FP32 conversion, non-negative slopes, floor), so each
 // leaf owns a contiguous run of the sorted keys.  A leaf predicts
-//     p = base + floor(icpt + slope * float(q - kmin))
+//     p = base + floor(icpt + slope * float((q >> 32) - khi))
 // and the answer is searched in [p - err_lo, p + err_hi + 1].  The window is accepted
 // only if keys[lo-1] < q <= keys[hi] (with the array ends as sentinels); otherwise the
 // lookup falls back to a full binary search, so results never depend on the model or on
@@ -79,9 +80,11 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
     }
 }
 
-// One thread per leaf: least-squares line through (key - kmin, position) in FP64, then
-// the largest under- and over-prediction over the leaf's keys with the lookup's own
-// prediction function.
+// One thread per leaf: least-squares line through ((key >> 32) - khi, position) in FP64,
+// then the largest under- and over-prediction over the leaf's keys with the lookup's own
+// prediction function (saturated at 255: a larger miss only sends those lookups to the
+// binary-search fallback).  The key loops take 8 keys per step so that 8 loads are in
+// flight per thread.
 __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64_t n,
                                                     const RmiHeader *Hp, RmiLeaf *leaves)
 {
@@ -92,14 +95,12 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     const uint64_t hi = l + 1 < L ? leaves[l + 1].base : n;
     RmiLeaf lf;
     lf.base = (uint32_t)lo;
-    lf.kmin = lo < n ? keys[lo] : kMax64;
+    lf.khi = lo < n ? (uint32_t)(keys[lo] >> 32) : 0xffffffffu;
     lf.slope = 0.f;
-    lf.icpt = 0.f;
+    lf.icpt = (_Float16)0.f;
     lf.err_lo = 0;
     lf.err_hi = 0;
-    lf.pad = 0;
     const uint64_t m = hi > lo ? hi - lo : 0;
-    // (the key loops take 8 keys per step so that 8 loads are in flight per thread)
     if (m >= 2) {
         double sx = 0, sy = 0, sxx = 0, sxy = 0;
         uint64_t i = lo;
@@ -109,18 +110,20 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
             for (int u = 0; u < 8; u++) kk[u] = keys[i + u];
 #pragma unroll
             for (int u = 0; u < 8; u++) {
-                const double x = (double)(kk[u] - lf.kmin), y = (double)(i + u - lo);
+                const double x = (double)((uint32_t)(kk[u] >> 32) - lf.khi), y = (double)(i + u - lo);
                 sx += x; sy += y; sxx += x * x; sxy += x * y;
             }
         }
         for (; i < hi; i++) {
-            const double x = (double)(keys[i] - lf.kmin), y = (double)(i - lo);
+            const double x = (double)((uint32_t)(keys[i] >> 32) - lf.khi), y = (double)(i - lo);
             sx += x; sy += y; sxx += x * x; sxy += x * y;
         }
         const double var = sxx - sx * sx / (double)m;
         const double sl = var > 0 ? (sxy - sx * sy / (double)m) / var : 0.0;
+        double ic = (sy - sl * sx) / (double)m;
+        ic = ic > 60000.0 ? 60000.0 : (ic < -60000.0 ? -60000.0 : ic);
         lf.slope = (float)(sl > 0 ? sl : 0.0);
-        lf.icpt = (float)((sy - sl * sx) / (double)m);
+        lf.icpt = (_Float16)(float)ic;
     }
     // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]
     int64_t elo = 0, ehi = 0;
@@ -140,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
             prev = kk[u];
         }
     }
-    lf.err_lo = (int32_t)(elo < 0x7fffffff ? elo : 0x7fffffff);
-    lf.err_hi = (int32_t)(ehi < 0x7fffffff ? ehi : 0x7fffffff);
+    lf.err_lo = (uint8_t)(elo < 255 ? elo : 255);
+    lf.err_hi = (uint8_t)(ehi < 255 ? ehi : 255);
     leaves[l] = lf;
 }
 

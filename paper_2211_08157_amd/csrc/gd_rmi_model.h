@@ -17,14 +17,17 @@ struct RmiHeader {
     float pad2[7];
 };
 
+// 16 bytes, so that a leaf is one load.  The prediction works on the key's high 32 bits:
+// a leaf spans about 2^64 / 2^log2_leaves of key space, so dropping the low half costs
+// far less than one position.
 struct RmiLeaf {
-    uint64_t kmin;
-    uint32_t base;
-    float slope, icpt;
-    int32_t err_lo, err_hi;
-    uint32_t pad;
+    uint32_t khi;              // high 32 bits of the leaf's first key
+    uint32_t base;             // index of the leaf's first key
+    float slope;               // positions per unit of (key >> 32)
+    _Float16 icpt;             // intercept in positions
+    uint8_t err_lo, err_hi;    // largest under- and over-prediction, saturated at 255
 };
-static_assert(sizeof(RmiLeaf) == 32, "leaf record is 32 bytes");
+static_assert(sizeof(RmiLeaf) == 16, "leaf record is 16 bytes");
 static_assert(sizeof(RmiHeader) == 320, "header keeps the leaves 64-byte aligned");
 
 __device__ __forceinline__ float key_x(uint64_t k)
@@ -53,8 +56,9 @@ __device__ __forceinline__ uint32_t route(const RmiHeader &H, uint64_t k)
 
 __device__ __forceinline__ int64_t predict(const RmiLeaf &lf, uint64_t k)
 {
-    const float d = k >= lf.kmin ? __ull2float_rn(k - lf.kmin) : 0.f;
-    const float f = __fadd_rn(lf.icpt, __fmul_rn(lf.slope, d));
+    const uint32_t kh = (uint32_t)(k >> 32);
+    const float d = kh >= lf.khi ? __uint2float_rn(kh - lf.khi) : 0.f;
+    const float f = __fadd_rn((float)lf.icpt, __fmul_rn(lf.slope, d));
     return (int64_t)lf.base + (int64_t)floorf(f);
 }
 

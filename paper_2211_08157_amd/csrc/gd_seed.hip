@@ -41,8 +41,72 @@ __device__ __forceinline__ uint64_t run_end(const uint64_t *keys, uint64_t n, ui
     return a;
 }
 
-// One lane per query; `rmi` (nullable) switches the lower bound to the learned index.
-template <bool kModel>
+// Lower bound l and run end u of q through the learned index when the keys are 16-byte
+// aligned.  The lookup is bound by the number of random memory requests, so the leaf is
+// one 16-byte load and the key window [lo - 1, hi] (both brackets included) is read as
+// up to kPairs independent 16-byte loads; both ends come from those keys.  The bracket
+// check keeps the result exact whatever the model holds; a window too wide or a failed
+// check takes the plain searches.
+constexpr int kPairs = 8;
+
+__device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, uint64_t n,
+                                         uint64_t q, uint64_t &l, uint64_t &u)
+{
+    const RmiHeader &H = *(const RmiHeader *)rmi;
+    const RmiLeaf *leaves = (const RmiLeaf *)((const char *)rmi + sizeof(RmiHeader));
+    if (H.magic == kRmiMagic && H.n_keys == n && n > 0) {
+        const RmiLeaf lf = leaves[route(H, q)];
+        const int64_t p = predict(lf, q);
+        int64_t lo = p - lf.err_lo, hi = p + lf.err_hi + 1;
+        if (lo < 0) lo = 0;
+        if (hi > (int64_t)n) hi = (int64_t)n;
+        const int64_t s0 = lo > 0 ? lo - 1 : 0;                     // first key read
+        const int64_t s1 = hi < (int64_t)n ? hi : (int64_t)n - 1;   // last key read
+        const int64_t e0 = s0 & ~(int64_t)1;                        // 16-byte aligned
+        if (lo <= hi && s1 - e0 < 2 * kPairs) {
+            ulonglong2 v[kPairs];
+#pragma unroll
+            for (int c = 0; c < kPairs; c++) {
+                const int64_t e = e0 + 2 * c;
+                if (e <= s1 && e + 1 < (int64_t)n) v[c] = *(const ulonglong2 *)(keys + e);
+                else if (e <= s1) v[c] = make_ulonglong2(keys[e], kMax64);
+                else v[c] = make_ulonglong2(kMax64, kMax64);
+            }
+            bool ok = true, hi_eq = false;
+            uint32_t lt = 0, eq = 0;
+#pragma unroll
+            for (int c = 0; c < kPairs; c++) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int64_t idx = e0 + 2 * c + h;
+                    const uint64_t kv = h ? v[c].y : v[c].x;
+                    if (idx < s0 || idx > s1) continue;
+                    if (idx == lo - 1) {
+                        ok = ok && kv < q;                  // left bracket
+                    } else if (idx == hi) {                 // right bracket (hi < n)
+                        ok = ok && kv >= q;
+                        hi_eq = kv == q;
+                        eq += hi_eq ? 1u : 0u;
+                    } else {                                // window [lo, hi)
+                        lt += kv < q ? 1u : 0u;
+                        eq += kv == q ? 1u : 0u;
+                    }
+                }
+            }
+            if (ok) {
+                l = (uint64_t)lo + lt;
+                u = hi_eq ? run_end(keys, n, (uint64_t)hi, q) : l + eq;
+                return;
+            }
+        }
+    }
+    l = lower_bound_u64(keys, n, q);
+    u = run_end(keys, n, l, q);
+}
+
+// One lane per query; `rmi` (nullable) switches the lower bound to the learned index
+// (kWide: keys 16-byte aligned, windowed loads).
+template <bool kModel, bool kWide>
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64_t in,
                                                    const uint64_t *q, const uint64_t *n_q,
                                                    uint64_t q_cap, uint32_t *lb, uint32_t *occ,
@@ -53,8 +117,13 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t x = q[i];
-        const uint64_t l = kModel ? rmi_lower_bound(rmi, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
-        const uint64_t u = run_end(ikeys, in, l, x);
+        uint64_t l, u;
+        if (kModel && kWide) {
+            rmi_find(rmi, ikeys, in, x, l, u);
+        } else {
+            l = kModel ? rmi_lower_bound(rmi, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
+            u = run_end(ikeys, in, l, x);
+        }
         lb[i] = (uint32_t)l;
         occ[i] = (uint32_t)(u - l);
     }
@@ -290,12 +359,15 @@ hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
     const uint64_t cap = max_blocks ? max_blocks : 8192;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
-    if (rmi)
-        GD_LAUNCH(k_lookup<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, rmi);
+    if (rmi && ((uintptr_t)ikeys & 15) == 0)
+        GD_LAUNCH((k_lookup<true, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in,
+                  q, n_q, q_cap, lb, occ, rmi);
+    else if (rmi)
+        GD_LAUNCH((k_lookup<true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in,
+                  q, n_q, q_cap, lb, occ, rmi);
     else
-        GD_LAUNCH(k_lookup<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, rmi);
+        GD_LAUNCH((k_lookup<false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys,
+                  in, q, n_q, q_cap, lb, occ, rmi);
     return hipGetLastError();
 }
 

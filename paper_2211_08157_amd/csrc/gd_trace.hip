@@ -62,7 +62,13 @@ size_t godiet_trace_dump(char *buf, size_t len)
         for (auto &r : g_recs) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = -1.f;
-            auto &e = agg[r.name];
+            // launch sites wrap multi-argument templates in parentheses; report the bare
+            // kernel name without spaces
+            std::string nm;
+            for (const char *c = r.name; *c; c++)
+                if (*c != ' ') nm += *c;
+            if (nm.size() >= 2 && nm.front() == '(' && nm.back() == ')') nm = nm.substr(1, nm.size() - 2);
+            auto &e = agg[nm];
             e.first += 1;
             e.second += ms;
             if (consume) {

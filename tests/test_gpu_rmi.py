@@ -57,11 +57,11 @@ def test_rmi_corrupted_model_falls_back(gpu, ref_index):
     q = queries_from(ek)
     qt = torch.from_numpy(q.view(np.int64)).cuda()
     m = gpu.rmi_train(ix, root="mlp", log2_leaves=12)
-    words = m.rmi.view(torch.int32)                 # header 320 B, then 32-B leaves
-    leaves = words[80:].view(-1, 8)
-    leaves[:, 5] = 0                               # err_lo
-    leaves[:, 6] = 0                               # err_hi
-    leaves[::3, 3] = 0x3f800000                    # slope = 1.0: wild predictions
+    words = m.rmi.view(torch.int32)                 # header 320 B, then 16-B leaves
+    leaves = words[80:].view(-1, 4)                 # khi, base, slope, icpt|err_lo|err_hi
+    leaves[:, 3] = leaves[:, 3] & 0xFFFF            # both errors 0
+    leaves[::3, 2] = 0x3f800000                     # slope = 1.0: wild predictions
+    leaves[1::5, 1] = 0x7FFFFFFF                    # base far past the end
     lb_r, occ_r = gpu.lookup(m, qt)
     elb, eocc = oracle.lookup(ek, q)
     assert np.array_equal(u32(lb_r).astype(np.uint64), elb)
