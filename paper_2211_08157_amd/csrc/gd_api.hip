@@ -101,9 +101,10 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     uint64_t expected = npb * 2 / (uint64_t)(w + 1) + 1;
     if (expected > capacity) expected = capacity;
     o->sp = sort_plan(expected, capacity, val_bytes);
-    o->so.hist = b.take<uint32_t>(o->sp.nfine);
+    o->so.hist = b.take<uint32_t>(o->sp.digits ? o->sp.nchunks * o->sp.nfine : o->sp.nfine);
+    o->so.tot = o->sp.digits ? b.take<uint32_t>(o->sp.nfine) : nullptr;
     o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
-    o->so.rank = b.take<uint32_t>(capacity);
+    o->so.rank = o->sp.digits ? nullptr : b.take<uint32_t>(capacity);
     o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
     o->so.trec = b.take<ulonglong2>(capacity);
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);

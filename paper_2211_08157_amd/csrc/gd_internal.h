@@ -112,11 +112,14 @@ struct SortPlan {
     size_t nfine;          // 2^Bf fine bins
     size_t target;         // records per coarse bucket
     size_t ncoarse;        // coarse buckets launched
+    bool digits;           // counting pass by top Bf bits with workgroup-local counters
+    size_t nchunks;        // digits mode: record chunks (one workgroup each)
 };
 SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes);
 // Scratch pieces the sort needs.
 struct SortWs {
-    uint32_t *hist;        // nfine
+    uint32_t *hist;        // nfine (digits mode: nchunks * nfine per-chunk digit counts)
+    uint32_t *tot;         // digits mode: nfine digit totals
     uint64_t *fofs;        // nfine + 1
     uint32_t *rank;        // capacity: rank of each record inside its fine bin
     uint64_t *scan_tmp;    // scan_scratch(nfine)

@@ -21,6 +21,14 @@
 // thousands of records) is listed and sorted by a fallback kernel in global memory.
 // (hash, val) pairs are unique, so the result does not depend on the order in which the
 // scatter's atomics land.
+//
+// Indexes of up to ~10M records take a cheaper partition ("digits" mode): 2^14 digits of
+// the top key bits, counted per chunk of 32K records in LDS, turned into per-chunk digit
+// offsets by one thread per digit, and scattered with LDS atomics, so no record touches
+// a global atomic or a random global read.  The densest digit then holds about six times
+// the mean (~3.2K records at 8M), so coarse buckets target 512 records (at most 512 plus
+// one digit, within the LDS capacity); each is binned again in LDS by the next key bits
+// and its records placed by rank (k_digit_bucket_sort).
 #include "gd_internal.h"
 
 namespace gd {
@@ -60,6 +68,77 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const 
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t key = keys[i];
         trec[fofs[key >> (64 - Bf)] + rank[i]] = make_ulonglong2(key, (uint64_t)vals[i]);
+    }
+}
+
+// ---- digits mode
+constexpr int kDigitBits = 14;
+constexpr int kChunk = 32768;       // records per counting / scatter workgroup
+constexpr int kBigBlock = 1024;
+
+__global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
+                                                           const uint64_t *n_ptr,
+                                                           uint64_t capacity, int Bd,
+                                                           uint32_t *mat)
+{
+    __shared__ uint32_t cnt[1 << kDigitBits];
+    const uint32_t D = 1u << Bd;
+    for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) cnt[d] = 0;
+    __syncthreads();
+    uint64_t n = *n_ptr;
+    if (n > capacity) n = capacity;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) atomicAdd(&cnt[keys[i] >> (64 - Bd)], 1u);
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) mat[(size_t)blockIdx.x * D + d] = cnt[d];
+}
+
+// One thread per digit: its total over all chunks.
+__global__ __launch_bounds__(kBlock) void k_digit_totals(const uint32_t *mat, uint32_t nchunks,
+                                                         uint32_t D, uint32_t *tot)
+{
+    const uint32_t d = blockIdx.x * kBlock + threadIdx.x;
+    if (d >= D) return;
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (uint32_t b = 0; b < nchunks; b++) sum += mat[(size_t)b * D + d];
+    tot[d] = sum;
+}
+
+// One thread per digit: per-chunk counts -> each chunk's first output slot of the digit.
+__global__ __launch_bounds__(kBlock) void k_digit_offsets(uint32_t *mat, uint32_t nchunks,
+                                                          uint32_t D, const uint64_t *start)
+{
+    const uint32_t d = blockIdx.x * kBlock + threadIdx.x;
+    if (d >= D) return;
+    uint32_t run = (uint32_t)start[d];
+#pragma unroll 8
+    for (uint32_t b = 0; b < nchunks; b++) {
+        const uint32_t v = mat[(size_t)b * D + d];
+        mat[(size_t)b * D + d] = run;
+        run += v;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBigBlock) void k_digit_scatter(const uint64_t *keys, const V *vals,
+                                                             const uint64_t *n_ptr,
+                                                             uint64_t capacity, int Bd,
+                                                             const uint32_t *mat, ulonglong2 *trec)
+{
+    __shared__ uint32_t off[1 << kDigitBits];
+    const uint32_t D = 1u << Bd;
+    for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) off[d] = mat[(size_t)blockIdx.x * D + d];
+    __syncthreads();
+    uint64_t n = *n_ptr;
+    if (n > capacity) n = capacity;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) {
+        const uint64_t key = keys[i];
+        const uint32_t pos = atomicAdd(&off[key >> (64 - Bd)], 1u);
+        trec[pos] = make_ulonglong2(key, (uint64_t)vals[i]);
     }
 }
 
@@ -177,6 +256,125 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
     }
 }
 
+// Digits mode: a coarse bucket is a run of nd whole digits.  Its records are binned in
+// LDS by the key bits just below the digit (S of them, nd << S <= kSub sub-bins, about
+// two records each on average), the sub-bins are scanned and filled from registers, and
+// every record is then placed by its rank inside its sub-bin, as in k_bucket_sort.
+// Buckets spanning too many digits, or holding a long sub-bin, are bitonic-sorted.
+constexpr int kSub = 4096;
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_digit_bucket_sort(const ulonglong2 *trec,
+                                                              const uint64_t *fofs,
+                                                              const uint32_t *cstart, int Bd,
+                                                              uint64_t *okeys, V *ovals,
+                                                              uint32_t *overflow,
+                                                              uint32_t *overflow_n)
+{
+    constexpr int kCap = Cap<V>::value;
+    constexpr int kPer = kCap / kBlock;
+    __shared__ uint64_t K[kCap];
+    __shared__ V Vv[kCap];
+    __shared__ uint32_t sub[kSub + 1];
+    __shared__ uint32_t sh_scan[kBlock / kWave];
+
+    const uint32_t d0 = cstart[blockIdx.x], d1 = cstart[blockIdx.x + 1];
+    const uint64_t base = fofs[d0];
+    const uint64_t n64 = fofs[d1] - base;
+    if (n64 == 0) return;
+    if (n64 > (uint64_t)kCap) {
+        if (threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
+        return;
+    }
+    const int n = (int)n64;
+    const int t = threadIdx.x;
+    const uint32_t nd = d1 - d0;
+    int S = 0;
+    while (S < 16 && ((uint64_t)nd << (S + 1)) <= (uint64_t)kSub) S++;
+    const bool binned = ((uint64_t)nd << S) <= (uint64_t)kSub;
+    const uint32_t NS = binned ? nd << S : 0;
+    const int shs = 64 - Bd - S;
+
+    ulonglong2 r[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * kBlock;
+        if (i < n) r[m] = trec[base + i];
+    }
+    int big = binned ? 0 : 1;
+    if (binned) {
+        for (uint32_t b = t; b <= NS; b += kBlock) sub[b] = 0;
+        __syncthreads();
+        uint32_t slot[kPer];
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            if (i < n) slot[m] = atomicAdd(&sub[(uint32_t)(r[m].x >> shs) - (d0 << S)], 1u);
+        }
+        __syncthreads();
+        // exclusive scan of sub[0, NS): each thread takes a run of consecutive entries
+        const uint32_t per = (NS + kBlock - 1) / kBlock;
+        const uint32_t b0 = t * per, b1 = b0 + per < NS ? b0 + per : NS;
+        uint32_t run = 0;
+        for (uint32_t b = b0; b < b1; b++) run += sub[b];
+        uint32_t total;
+        uint32_t acc = block_excl_scan<uint32_t>(run, sh_scan, &total);
+        for (uint32_t b = b0; b < b1; b++) {
+            const uint32_t c = sub[b];
+            sub[b] = acc;
+            acc += c;
+        }
+        if (t == 0) sub[NS] = (uint32_t)n;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            if (i < n) {
+                const uint32_t at = sub[(uint32_t)(r[m].x >> shs) - (d0 << S)] + slot[m];
+                K[at] = r[m].x;
+                Vv[at] = (V)r[m].y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            if (i < n) { K[i] = r[m].x; Vv[i] = (V)r[m].y; }
+        }
+    }
+    __syncthreads();
+    int pos[kPer];
+    if (binned) {
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            const int i = t + m * kBlock;
+            pos[m] = i;
+            if (i >= n) continue;
+            const uint64_t k = K[i];
+            const V v = Vv[i];
+            const uint32_t b = (uint32_t)(k >> shs) - (d0 << S);
+            const int lo = (int)sub[b], hi = (int)sub[b + 1];
+            if (hi - lo > kSmall) {
+                big = 1;
+                continue;
+            }
+            int rank = 0;
+            for (int j = lo; j < hi; j++) rank += rec_less<V>(K[j], Vv[j], k, v) ? 1 : 0;
+            pos[m] = lo + rank;
+        }
+    }
+    if (__syncthreads_or(big)) {
+        lds_bitonic<V>(K, Vv, n);
+        for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
+        return;
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * kBlock;
+        if (i < n) { okeys[base + pos[m]] = K[i]; ovals[base + pos[m]] = Vv[i]; }
+    }
+}
+
 // Fallback for coarse buckets larger than the LDS capacity: sort runs of kCap records in
 // LDS into the output, then merge pairs of runs by ranking (an element's output index is
 // its index in its own run plus the number of smaller elements in the other run),
@@ -258,21 +456,41 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
                      const uint64_t *n_ptr, uint64_t capacity, hipStream_t s)
 {
     hipError_t e;
-    if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
     if ((e = fill_u32(w.overflow_n, 0, 1, s)) != hipSuccess) return e;
-    const unsigned grid = 4096;
-    GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.Bf, w.hist,
-              w.rank);
-    if ((e = exclusive_scan_u32(w.hist, w.fofs, sp.nfine, w.scan_tmp, s)) != hipSuccess) return e;
-    GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity, sp.Bf,
-              (const uint64_t *)w.fofs, (const uint32_t *)w.rank, w.trec);
+    if (sp.digits) {
+        const uint32_t D = (uint32_t)sp.nfine, nc = (uint32_t)sp.nchunks;
+        const unsigned dg = (D + kBlock - 1) / kBlock;
+        GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, sp.Bf,
+                  w.hist);
+        GD_LAUNCH(k_digit_totals, dim3(dg), dim3(kBlock), 0, s, (const uint32_t *)w.hist, nc, D,
+                  w.tot);
+        if ((e = exclusive_scan_u32(w.tot, w.fofs, D, w.scan_tmp, s)) != hipSuccess) return e;
+        GD_LAUNCH(k_digit_offsets, dim3(dg), dim3(kBlock), 0, s, w.hist, nc, D,
+                  (const uint64_t *)w.fofs);
+        GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), 0, s, keys, vals, n_ptr, capacity,
+                  sp.Bf, (const uint32_t *)w.hist, w.trec);
+    } else {
+        if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
+        const unsigned grid = 4096;
+        GD_LAUNCH(k_hist, dim3(grid), dim3(kBlock), 0, s, keys, n_ptr, capacity, sp.Bf, w.hist,
+                  w.rank);
+        if ((e = exclusive_scan_u32(w.hist, w.fofs, sp.nfine, w.scan_tmp, s)) != hipSuccess)
+            return e;
+        GD_LAUNCH(k_scatter<V>, dim3(grid), dim3(kBlock), 0, s, keys, vals, n_ptr, capacity,
+                  sp.Bf, (const uint64_t *)w.fofs, (const uint32_t *)w.rank, w.trec);
+    }
     if ((e = fill_u32(w.cstart, (uint32_t)sp.nfine, sp.ncoarse + 1, s)) != hipSuccess) return e;
     GD_LAUNCH(k_coarse_starts, dim3((unsigned)((sp.nfine + kBlock) / kBlock)), dim3(kBlock), 0, s,
               (const uint64_t *)w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, w.cstart,
               (uint64_t)sp.ncoarse + 1);
-    GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
-              (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs, (const uint32_t *)w.cstart,
-              sp.Bf, keys, vals, w.overflow, w.overflow_n);
+    if (sp.digits)
+        GD_LAUNCH(k_digit_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
+                  (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
+                  (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
+    else
+        GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
+                  (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
+                  (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
     GD_LAUNCH(k_bucket_sort_big<V>, dim3(64), dim3(kBlock), 0, s, w.trec,
               (const uint64_t *)w.fofs, (const uint32_t *)w.cstart,
               (const uint32_t *)w.overflow, (const uint32_t *)w.overflow_n, keys, vals);
@@ -284,8 +502,23 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
 SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
 {
     SortPlan sp;
+    // digits mode while the densest of 2^14 digits (about 6x the mean) plus a 512-record
+    // target stays within the LDS capacity of a bucket
+    if (val_bytes == 4 && capacity <= ((uint64_t)640 << kDigitBits) && capacity > 0) {
+        int Bd = 4;                          // about 512 records per digit, at most 2^14 digits
+        while (Bd < kDigitBits && (capacity >> Bd) > 512) Bd++;
+        sp.digits = true;
+        sp.Bf = Bd;
+        sp.nfine = (size_t)1 << Bd;
+        sp.nchunks = (size_t)((capacity + kChunk - 1) / kChunk);
+        sp.target = 512;
+        sp.ncoarse = (size_t)(capacity / sp.target) + 2;
+        return sp;
+    }
     int Bf = 4;
     while (Bf < 26 && (expected_records >> Bf) > 2) Bf++;
+    sp.digits = false;
+    sp.nchunks = 0;
     sp.Bf = Bf;
     sp.nfine = (size_t)1 << Bf;
     sp.target = val_bytes == 4 ? 2048 : 1024;
