@@ -316,7 +316,7 @@ __device__ __forceinline__ void div_x(uint64_t li, uint32_t x, double inv_x, uin
 // containing a position) is built the same way from the previous chunk's suffix maxima.
 // ex is an LDS array of kE words used for the two neighbour exchanges.
 template <int W>
-__device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], const uint32_t (&fv)[16],
+__device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t selm, uint32_t winm,
                                                uint64_t *ex, bool owner)
 {
     const int t = threadIdx.x;
@@ -359,7 +359,7 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], const ui
         }
     }
 #pragma unroll
-    for (int s = 0; s < 16; s++) mw[s] = (fv[s] & 2u) ? mw[s] : 0;
+    for (int s = 0; s < 16; s++) mw[s] = ((winm >> s) & 1u) ? mw[s] : 0;
 
     // opening
     uint64_t SM[16], PM[16], op[16];
@@ -403,12 +403,12 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], const ui
     uint32_t sel = 0;
 #pragma unroll
     for (int u = 0; u < 16; u++)
-        if (owner && (fv[u] & 1u) && v[u] == op[u]) sel |= 1u << u;
+        if (owner && ((selm >> u) & 1u) && v[u] == op[u]) sel |= 1u << u;
     return sel;
 }
 
 // Any w: window minima and the opening by doubling in LDS (ex holds kE words).
-__device__ uint32_t select_lds(const uint64_t (&v)[16], const uint32_t (&fv)[16], uint64_t *ex,
+__device__ uint32_t select_lds(const uint64_t (&v)[16], uint32_t selm, uint32_t winm, uint64_t *ex,
                                int w, bool owner)
 {
     const int t = threadIdx.x;
@@ -435,7 +435,7 @@ __device__ uint32_t select_lds(const uint64_t (&v)[16], const uint32_t (&fv)[16]
 #pragma unroll
         for (int u = 0; u < 16; u++) {
             const int i = 16 * t + u;
-            x[u] = (fv[u] & 2u) ? min(ex[i], i + r2 < kE ? ex[i + r2] : kMax64) : 0;
+            x[u] = ((winm >> u) & 1u) ? min(ex[i], i + r2 < kE ? ex[i + r2] : kMax64) : 0;
         }
         __syncthreads();
 #pragma unroll
@@ -459,7 +459,7 @@ __device__ uint32_t select_lds(const uint64_t (&v)[16], const uint32_t (&fv)[16]
     for (int u = 0; u < 16; u++) {
         const int i = 16 * t + u;
         const uint64_t opened = max(ex[i], i - r2 >= 0 ? ex[i - r2] : 0);
-        if (owner && (fv[u] & 1u) && v[u] == opened) sel |= 1u << u;
+        if (owner && ((selm >> u) & 1u) && v[u] == opened) sel |= 1u << u;
     }
     return sel;
 }
@@ -477,12 +477,12 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
     const int64_t jc = j0 - H + 16 * t;                  // first position of this chunk
 
     // ---- stage 1: canonical k-mer hashes and flags of the 16 positions of the chunk.
-    // hv = hash (kMax64 where there is no k-mer or it is a palindrome);
-    // fv bit0 = may be selected, bit1 = a valid window starts here, bit2 = strand.
+    // hv = hash (kMax64 where there is no k-mer or it is a palindrome); bit u of selm:
+    // position u may be selected, of winm: a valid window starts there, of smask: strand.
     uint64_t hv[16];
-    uint32_t fv[16];
+    uint32_t selm = 0, winm = 0, smask = 0;   // bit u: may be selected / window starts / strand
 #pragma unroll
-    for (int u = 0; u < 16; u++) { hv[u] = kMax64; fv[u] = 0; }
+    for (int u = 0; u < 16; u++) hv[u] = kMax64;
     uint32_t seq0 = 0;
     uint64_t beg0 = 0, end0 = 0;
     if (jc >= 0 && (uint64_t)jc < np) {
@@ -499,6 +499,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                               seq_end - seq_beg >= (uint64_t)(k + w - 1);
         if (interior && (k & 1)) {
             // odd k: a k-mer never equals its reverse complement
+            selm = winm = 0xFFFFu;
 #pragma unroll
             for (int u = 0; u < 16; u++) {
                 const uint64_t X = kmer_lsb(w0, w1, w2, u);
@@ -507,9 +508,10 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t fwd = F >> fsh;
                 const bool strand = rc < fwd;
                 hv[u] = mix64(strand ? rc : fwd);
-                fv[u] = 3u | (strand ? 4u : 0u);
+                smask |= (strand ? 1u : 0u) << u;
             }
         } else if (interior) {
+            winm = 0xFFFFu;
 #pragma unroll
             for (int u = 0; u < 16; u++) {
                 const uint64_t X = kmer_lsb(w0, w1, w2, u);
@@ -520,7 +522,8 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t h = mix64(strand ? rc : fwd);
                 const bool pal = fwd == rc;
                 hv[u] = pal ? kMax64 : h;
-                fv[u] = (pal ? 0u : 1u) | 2u | (strand ? 4u : 0u);
+                selm |= (pal ? 0u : 1u) << u;
+                smask |= (strand ? 1u : 0u) << u;
             }
         } else {
             // The chunk meets a sequence end (reads put one into most chunks): bit masks of
@@ -556,20 +559,19 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t h = mix64(strand ? rc : fwd);
                 const bool use = ((kv >> u) & 1u) && !((k & 1) == 0 && fwd == rc);
                 hv[u] = use ? h : kMax64;
-                fv[u] = (use && ((okm >> u) & 1u) ? 1u : 0u) | (((wv >> u) & 1u) << 1) |
-                        (strand ? 4u : 0u);
+                selm |= (use ? 1u : 0u) << u;
+                smask |= (strand ? 1u : 0u) << u;
             }
+            selm &= okm;
+            winm = wv;
         }
     }
 
     // ---- stage 2: minimizer selection (window minima, then the opening)
     const bool owner = 16 * t >= H && 16 * t < H + T;
     uint32_t sel;
-    if constexpr (W > 0) sel = select_reg<W>(hv, fv, ex, owner);
-    else sel = select_lds(hv, fv, ex, w, owner);
-    uint32_t smask = 0;              // strand of each position
-#pragma unroll
-    for (int u = 0; u < 16; u++) smask |= ((fv[u] >> 2) & 1u) << u;
+    if constexpr (W > 0) sel = select_reg<W>(hv, selm, winm, ex, owner);
+    else sel = select_lds(hv, selm, winm, ex, w, owner);
 
     // ---- stage 3: position-ordered compaction across tiles (decoupled look-back)
     uint64_t total;
