@@ -229,6 +229,9 @@ godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uin
  * including the NUL. */
 void godiet_trace_enable(int on);
 size_t godiet_trace_dump(char *buf, size_t len);
+/* Restricts tracing to kernels whose name (as reported by godiet_trace_dump) begins with
+ * prefix; NULL or "" traces every kernel again.  The string is copied. */
+void godiet_trace_filter(const char *prefix);
 
 #ifdef __cplusplus
 }

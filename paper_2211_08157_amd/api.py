@@ -83,12 +83,19 @@ def lib():
         L.godiet_trace_enable.restype = None
         L.godiet_trace_dump.argtypes = [ctypes.c_char_p, sz]
         L.godiet_trace_dump.restype = sz
+        L.godiet_trace_filter.argtypes = [ctypes.c_char_p]
+        L.godiet_trace_filter.restype = None
         _lib = L
     return _lib
 
 
 def trace_enable(on=True):
     lib().godiet_trace_enable(1 if on else 0)
+
+
+def trace_filter(prefix=None):
+    """Trace only kernels whose name starts with prefix (None: all)."""
+    lib().godiet_trace_filter(prefix.encode() if prefix else None)
 
 
 def trace_dump():

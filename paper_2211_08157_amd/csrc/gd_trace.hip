@@ -23,6 +23,18 @@ struct Rec {
     hipEvent_t a, b;
 };
 std::vector<Rec> g_recs;
+std::string g_filter;            // guarded by g_mu
+
+// Launch sites wrap multi-argument templates in parentheses; the reported name is the
+// bare kernel name without spaces.
+std::string normalize(const char *name)
+{
+    std::string nm;
+    for (const char *c = name; *c; c++)
+        if (*c != ' ') nm += *c;
+    if (nm.size() >= 2 && nm.front() == '(' && nm.back() == ')') nm = nm.substr(1, nm.size() - 2);
+    return nm;
+}
 }  // namespace
 
 bool enabled() { return g_on.load(std::memory_order_relaxed); }
@@ -30,6 +42,10 @@ bool enabled() { return g_on.load(std::memory_order_relaxed); }
 Scope::Scope(const char *name, hipStream_t s) : name_(name), s_(s), a_(nullptr), b_(nullptr)
 {
     if (!enabled()) return;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        if (!g_filter.empty() && normalize(name).compare(0, g_filter.size(), g_filter) != 0) return;
+    }
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
         a_ = b_ = nullptr;
         return;
@@ -52,6 +68,12 @@ extern "C" {
 
 void godiet_trace_enable(int on) { gd::trace::g_on.store(on != 0); }
 
+void godiet_trace_filter(const char *prefix)
+{
+    std::lock_guard<std::mutex> g(gd::trace::g_mu);
+    gd::trace::g_filter = prefix ? prefix : "";
+}
+
 size_t godiet_trace_dump(char *buf, size_t len)
 {
     using namespace gd::trace;
@@ -62,13 +84,7 @@ size_t godiet_trace_dump(char *buf, size_t len)
         for (auto &r : g_recs) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = -1.f;
-            // launch sites wrap multi-argument templates in parentheses; report the bare
-            // kernel name without spaces
-            std::string nm;
-            for (const char *c = r.name; *c; c++)
-                if (*c != ' ') nm += *c;
-            if (nm.size() >= 2 && nm.front() == '(' && nm.back() == ')') nm = nm.substr(1, nm.size() - 2);
-            auto &e = agg[nm];
+            auto &e = agg[normalize(r.name)];
             e.first += 1;
             e.second += ms;
             if (consume) {
