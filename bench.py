@@ -37,8 +37,8 @@ OPS_PER_KMER = 4 + 3 + 17 + 18
 # HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
 # kernel source; reported only while that source is unchanged.
 MEASURED_TRAFFIC = {
-    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="df3ccb0881a9fea7",
-                         bytes_per_step=427.3e6,
+    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="f9d3abf5f521625e",
+                         bytes_per_step=428.3e6,
                          summary="profiles/k_sketch_illumina-100Mbp_hbm_bytes.md"),
 }
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
