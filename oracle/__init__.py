@@ -68,6 +68,8 @@ def lib():
         L.gdo_contain.argtypes = [P, P, u64, P, P, u32, ctypes.c_char_p, i32, i32, i32, u32, u32,
                                   u32, P, P]
         L.gdo_contain.restype = i64
+        L.gdo_vote.argtypes = [P, P, u32, u32, u32, u32, P, P]
+        L.gdo_vote.restype = i64
         _lib = L
     return _lib
 
@@ -182,3 +184,17 @@ def contain(ikeys, ivals, codes, offsets, pattern, k, w, n_genomes, shift_mode=-
                              offsets.size - 1, pattern.encode(), k, w, shift_mode, align_t,
                              max_occ, n_genomes, _ptr(counts), _ptr(sizes)), "contain")
     return counts, sizes
+
+
+def vote(anchors, read_off, max_dist, min_votes, max_win):
+    """Location voting (Illumina form) with rescue.  anchors: (n, 4) uint32 rows of
+    (read_id, qpos, rpos, strand) grouped by read; read_off[n_reads+1].  Returns (rows
+    (n_reads, max_win, 4) int64 of (strand, votes, flags, loc), n_win[n_reads])."""
+    a = np.ascontiguousarray(anchors, dtype=np.uint32).reshape(-1, 4)
+    off = np.ascontiguousarray(read_off, dtype=np.uint64)
+    n_reads = off.size - 1
+    out = np.zeros((max(n_reads, 1), max_win, 4), np.int64)
+    nw = np.zeros(max(n_reads, 1), np.uint32)
+    _check(lib().gdo_vote(_ptr(a), _ptr(off), n_reads, int(max_dist), int(min_votes),
+                          int(max_win), _ptr(out), _ptr(nw)), "vote")
+    return out[:n_reads], nw[:n_reads]

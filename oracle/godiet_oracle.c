@@ -26,7 +26,11 @@
  *     minimizers and never lower a window minimum;
  *   - pattern alignment scores the first n* = min_s |M_s| minimizers of every shift
  *     (capped by t when t > 0), skips occurrences >= max_occ when max_occ > 0, and picks
- *     the smallest shift of maximal score (0 when p == 1).
+ *     the smallest shift of maximal score (0 when p == 1);
+ *   - location voting: the adjusted location of an anchor is its diagonal rpos - qpos
+ *     on the forward strand and its anti-diagonal rpos + qpos on the reverse strand;
+ *     locations vote only within their strand; every anchor is one vote; winners are
+ *     ordered by votes (descending), then strand and location (ascending).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -421,4 +425,85 @@ int64_t gdo_contain(const uint64_t *ikeys, const uint64_t *ivals, uint64_t in,
     free(gh);
     free(sample);
     return (int64_t)nu;
+}
+
+/* Location voting for short reads (Section 3.4 steps 1-4, Illumina form) with the rescue
+ * location of Section 3.6.3.  For read r, its anchors [read_off[r], read_off[r+1]) of
+ * rows (read_id, qpos, rpos, strand):
+ *   1. adjusted location: strand 0: rpos - qpos; strand 1: rpos + qpos;
+ *   2. the (strand, location) pairs are sorted into one list;
+ *   3. the first entry is the temporary mapping location L0; its votes are the entries of
+ *      the same strand with location <= L0 + D;
+ *   4. if votes >= V, (strand, L0, votes) is a winner; the first entry beyond L0 + D (or
+ *      of the other strand) becomes the next temporary location, until the list ends.
+ * Winners are ordered by votes descending (ties: strand, then location ascending) and the
+ * first max_win are kept.  The rescue location is the candidate with the most votes (the
+ * first such in list order); when there is no winner it is the output, flagged 1.
+ * Output per read in out[r*max_win + i], i < n_win[r], rows (strand, votes, flags, loc)
+ * as four int64 values.  Returns the total number of rows written. */
+typedef struct { int64_t loc; uint32_t strand; uint32_t votes; } gdo_cand;
+
+static int loc_cmp(const void *pa, const void *pb)
+{
+    const gdo_cand *a = (const gdo_cand *)pa, *b = (const gdo_cand *)pb;
+    if (a->strand != b->strand) return a->strand < b->strand ? -1 : 1;
+    return a->loc < b->loc ? -1 : (a->loc > b->loc ? 1 : 0);
+}
+
+static int win_cmp(const void *pa, const void *pb)
+{
+    const gdo_cand *a = (const gdo_cand *)pa, *b = (const gdo_cand *)pb;
+    if (a->votes != b->votes) return a->votes > b->votes ? -1 : 1;
+    return loc_cmp(pa, pb);
+}
+
+int64_t gdo_vote(const uint32_t *anchors, const uint64_t *read_off, uint32_t n_reads,
+                 uint32_t D, uint32_t V, uint32_t max_win, int64_t *out, uint32_t *n_win)
+{
+    if (max_win == 0) return GDO_EINVAL;
+    int64_t total = 0;
+    for (uint32_t r = 0; r < n_reads; r++) {
+        const uint64_t b = read_off[r], m = read_off[r + 1] - b;
+        n_win[r] = 0;
+        if (m == 0) continue;
+        gdo_cand *list = (gdo_cand *)malloc(m * sizeof(gdo_cand));
+        gdo_cand *win = (gdo_cand *)malloc(m * sizeof(gdo_cand));
+        if (!list || !win) { free(list); free(win); return GDO_ENOMEM; }
+        for (uint64_t i = 0; i < m; i++) {
+            const uint32_t *a = anchors + 4 * (b + i);
+            list[i].strand = a[3];
+            list[i].loc = a[3] ? (int64_t)a[2] + (int64_t)a[1] : (int64_t)a[2] - (int64_t)a[1];
+            list[i].votes = 0;
+        }
+        qsort(list, (size_t)m, sizeof(gdo_cand), loc_cmp);
+        uint64_t nw = 0, i = 0;
+        gdo_cand rescue = list[0];
+        rescue.votes = 0;
+        while (i < m) {
+            gdo_cand c = list[i];
+            uint64_t j = i;
+            while (j < m && list[j].strand == c.strand && list[j].loc <= c.loc + (int64_t)D) j++;
+            c.votes = (uint32_t)(j - i);
+            if (c.votes >= V) win[nw++] = c;
+            if (c.votes > rescue.votes) rescue = c;
+            i = j;
+        }
+        if (nw > 0) {
+            qsort(win, (size_t)nw, sizeof(gdo_cand), win_cmp);
+            if (nw > max_win) nw = max_win;
+            for (uint64_t t = 0; t < nw; t++) {
+                int64_t *o = out + 4 * ((uint64_t)r * max_win + t);
+                o[0] = win[t].strand; o[1] = win[t].votes; o[2] = 0; o[3] = win[t].loc;
+            }
+            n_win[r] = (uint32_t)nw;
+        } else {
+            int64_t *o = out + 4 * ((uint64_t)r * max_win);
+            o[0] = rescue.strand; o[1] = rescue.votes; o[2] = 1; o[3] = rescue.loc;
+            n_win[r] = 1;
+        }
+        total += n_win[r];
+        free(list);
+        free(win);
+    }
+    return total;
 }

@@ -50,6 +50,16 @@ MUTANTS = [
     ("anchor strand without the index strand",
      "anchors[4 * n + 3] = (uint32_t)((mv[j] ^ ivals[e]) & 1);",
      "anchors[4 * n + 3] = (uint32_t)(mv[j] & 1);"),
+    ("reverse-strand location as a diagonal",
+     "list[i].loc = a[3] ? (int64_t)a[2] + (int64_t)a[1] : (int64_t)a[2] - (int64_t)a[1];",
+     "list[i].loc = (int64_t)a[2] - (int64_t)a[1];"),
+    ("voting distance exclusive",
+     "list[j].loc <= c.loc + (int64_t)D) j++;", "list[j].loc < c.loc + (int64_t)D) j++;"),
+    ("vote threshold strict", "if (c.votes >= V) win[nw++] = c;", "if (c.votes > V) win[nw++] = c;"),
+    ("rescue keeps the last best", "if (c.votes > rescue.votes) rescue = c;",
+     "if (c.votes >= rescue.votes) rescue = c;"),
+    ("winners by ascending votes", "if (a->votes != b->votes) return a->votes > b->votes ? -1 : 1;",
+     "if (a->votes != b->votes) return a->votes < b->votes ? -1 : 1;"),
     ("containment counts every genome hash",
      "if (bsearch(&gh[i].val, sample, (size_t)nu, sizeof(uint64_t), u64_cmp)) counts[g]++;",
      "if (1) counts[g]++;"),
@@ -71,11 +81,16 @@ def main():
                 f.write(src.replace(old, new))
             subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", so, c])
             env = dict(os.environ, GODIET_ORACLE_LIB=so)
-            r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p",
-                                "no:cacheprovider", os.path.join(ROOT, "tests", "test_oracle.py")],
-                               cwd=ROOT, env=env, capture_output=True, text=True)
-            last = (r.stdout.strip().splitlines() or ["?"])[-1]
-            killed = r.returncode != 0
+            try:
+                r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p",
+                                    "no:cacheprovider",
+                                    os.path.join(ROOT, "tests", "test_oracle.py")],
+                                   cwd=ROOT, env=env, capture_output=True, text=True,
+                                   timeout=120)
+                last = (r.stdout.strip().splitlines() or ["?"])[-1]
+                killed = r.returncode != 0
+            except subprocess.TimeoutExpired:     # a mutant that never ends fails too
+                last, killed = "timed out", True
             survived += 0 if killed else 1
             print("%-8s %-45s %s" % ("killed" if killed else "SURVIVED", what, last))
     print("%d of %d mutants killed" % (len(MUTANTS) - survived, len(MUTANTS)))

@@ -365,3 +365,107 @@ def test_contain_matches_python_sets():
         hg = {int(kk) for kk, vv in zip(ik, iv) if int(vv) >> 32 == g}
         assert sizes[g] == len(hg)
         assert counts[g] == len(hg & sample)
+
+
+# ---------------------------------------------------------------- location voting
+
+def hand_vote_cases():
+    cases, cur = [], None
+    with open(os.path.join(GOLD, "hand_votes.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if not line:
+                continue
+            if line[0] == "case":
+                cur = dict(D=int(line[1]), V=int(line[2]), cap=int(line[3]), anchors=[], expect=[])
+                cases.append(cur)
+            elif line[0] == "reads":
+                cur["reads"] = int(line[1])
+            elif line[0] == "anchor":
+                cur["anchors"].append([int(v) for v in line[1:]])
+            elif line[0] == "expect":
+                cur["expect"].append([int(v) for v in line[1:]])
+    return cases
+
+
+def anchors_and_offsets(rows, n_reads):
+    a = np.array(rows, np.uint32).reshape(-1, 4)
+    counts = np.bincount(a[:, 0], minlength=n_reads) if a.size else np.zeros(n_reads, int)
+    off = np.zeros(n_reads + 1, np.uint64)
+    off[1:] = np.cumsum(counts)
+    return a, off
+
+
+def test_vote_hand_worked_cases():
+    for c in hand_vote_cases():
+        a, off = anchors_and_offsets(c["anchors"], c["reads"])
+        rows, nw = oracle.vote(a, off, c["D"], c["V"], c["cap"])
+        got = [[r] + list(rows[r, i]) for r in range(c["reads"]) for i in range(nw[r])]
+        want = [[e[0], e[1], e[2], e[3], e[4]] for e in c["expect"]]
+        assert got == want
+
+
+def brute_votes(rows, D, V, cap):
+    """Candidates by repeated minimum over the unsorted anchors of one read (no sort):
+    the next temporary location is the smallest location beyond the previous one + D;
+    its votes are counted over all anchors of its strand."""
+    locs = {0: [], 1: []}
+    for q, r, st in rows:
+        locs[st].append(r + q if st else r - q)
+    cands = []
+    for st in (0, 1):
+        rest = list(locs[st])
+        lo = None
+        while True:
+            left = [x for x in rest if lo is None or x > lo + D]
+            if not left:
+                break
+            lo = min(left)
+            votes = sum(1 for x in locs[st] if lo <= x <= lo + D)
+            cands.append((st, lo, votes))
+    wins = sorted([c for c in cands if c[2] >= V], key=lambda c: (-c[2], c[0], c[1]))[:cap]
+    if wins:
+        return [(st, v, 0, lo) for st, lo, v in wins]
+    if not cands:
+        return []
+    best = max(c[2] for c in cands)
+    st, lo, v = min(c for c in cands if c[2] == best)
+    return [(st, v, 1, lo)]
+
+
+@pytest.mark.parametrize("D,V,cap", [(0, 1, 4), (3, 2, 2), (10, 3, 8), (50, 1, 1), (5, 100, 3)])
+def test_vote_matches_repeated_minimum_brute_force(D, V, cap):
+    rng = np.random.default_rng(7 + D + V)
+    reads = []
+    for r in range(300):
+        m = int(rng.integers(0, 25))
+        base = int(rng.integers(100, 10_000))
+        rows = []
+        for _ in range(m):
+            q = int(rng.integers(0, 150))
+            st = int(rng.integers(0, 2))
+            if rng.random() < 0.6:          # on a true diagonal, with small indel drift
+                r_ = (base + q if st == 0 else base - q) + int(rng.integers(-2, 3))
+            else:
+                r_ = int(rng.integers(200, 20_000))
+            rows.append((q, max(r_, 0), st))
+        rows.sort()                          # (qpos, rpos) order, as the seeder emits them
+        reads.append(rows)
+    flat = [[i, q, r_, st] for i, rows in enumerate(reads) for q, r_, st in rows]
+    a, off = anchors_and_offsets(flat, len(reads))
+    out, nw = oracle.vote(a, off, D, V, cap)
+    for i, rows in enumerate(reads):
+        want = brute_votes(rows, D, V, cap)
+        got = [tuple(int(v) for v in out[i, j]) for j in range(nw[i])]
+        assert got == want, (i, rows)
+
+
+def test_vote_ignores_anchor_order_and_counts_exact_reads():
+    rng = np.random.default_rng(11)
+    rows = [[0, q, 5000 + q, 0] for q in range(0, 150, 7)] + [[0, 3, 90_000, 1]]
+    a, off = anchors_and_offsets(rows, 1)
+    out, nw = oracle.vote(a, off, 8, 3, 4)
+    assert nw[0] == 1 and list(out[0, 0]) == [0, len(rows) - 1, 0, 5000]
+    perm = a[rng.permutation(len(rows))]
+    out2, nw2 = oracle.vote(perm, off, 8, 3, 4)
+    assert np.array_equal(out, out2) and np.array_equal(nw, nw2)
