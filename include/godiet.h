@@ -76,6 +76,7 @@ typedef int32_t godiet_status;
 #define GODIET_OP_SEED        4
 #define GODIET_OP_RMI_TRAIN   5
 #define GODIET_OP_CONTAIN     6
+#define GODIET_OP_VOTE        7
 
 typedef struct {
     const uint8_t *bases;     /* 2-bit packed bases (layout above) */
@@ -119,6 +120,22 @@ typedef struct {
 typedef struct {
     uint32_t read_id, qpos, rpos, strand;   /* 16 bytes */
 } godiet_anchor;
+
+/* Location voting parameters (Section 3.4): D, V and the cap on the winning list. */
+typedef struct {
+    uint32_t max_dist;        /* D: votes of L0 are the locations in [L0, L0 + D] */
+    uint32_t min_votes;       /* V: a location wins with >= V votes */
+    uint32_t max_winners;     /* 1..16: winners kept per read */
+} godiet_vote_opts;
+
+/* One winning (or rescue) mapping location, 24 bytes.  loc is the adjusted location:
+ * rpos - qpos for strand 0 (may be negative), rpos + qpos for strand 1. */
+typedef struct {
+    int64_t loc;
+    uint32_t read_id, strand, votes;
+    uint32_t flags;           /* GODIET_VOTE_RESCUE: below V, the read's best candidate */
+} godiet_winner;
+#define GODIET_VOTE_RESCUE 1u
 
 /* Human-readable text of a status code. */
 const char *godiet_status_string(godiet_status s);
@@ -199,6 +216,26 @@ godiet_status godiet_contain(const godiet_index *index, const godiet_seqs *reads
                              const godiet_sketch_params *prm, const godiet_seed_opts *opts,
                              uint32_t n_genomes, uint32_t *counts, uint32_t *genome_sizes,
                              void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
+/* Location voting (Section 3.4 steps 1-4, the short-read form, with the rescue location
+ * of Section 3.6.3) over the anchors of godiet_seed: for each read r, its anchors
+ * [read_anchor_off[r], read_anchor_off[r+1]) (all with read_id r) get the adjusted
+ * location rpos - qpos (strand 0) or rpos + qpos (strand 1) and are sorted by (strand,
+ * location).  The first entry is the temporary location L0; its votes are the entries of
+ * its strand in [L0, L0 + D]; it wins with >= V votes; the first entry beyond L0 + D
+ * becomes the next L0.  out[r * max_winners + i], i < n_win[r], receives the winners by
+ * votes descending, then strand and location ascending, at most max_winners of them;
+ * with no winner it receives the candidate with the most votes (the first such),
+ * flagged GODIET_VOTE_RESCUE; a read without anchors gets n_win[r] = 0.
+ * anchor_capacity [host] bounds read_anchor_off[n_reads] (GODIET_ST_CAPACITY if
+ * exceeded); anchors not grouped by read raise GODIET_ST_RANGE.  Needs n_reads < 2^31
+ * and positions < 2^31.  ws: godiet_workspace_size(GODIET_OP_VOTE, reads, NULL,
+ * anchor_capacity), where only reads->n_seq (= n_reads) is read.  Device arrays:
+ * anchors, read_anchor_off, out (n_reads * max_winners), n_win (n_reads). */
+godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anchor_off,
+                          uint32_t n_reads, uint64_t anchor_capacity,
+                          const godiet_vote_opts *opts, godiet_winner *out, uint32_t *n_win,
+                          void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
 
 /* Exact-match lookups in a sorted index (Section 3.3: each read minimizer is matched
  * exactly against the seed index): for every query q[i], lb[i] = first index e with

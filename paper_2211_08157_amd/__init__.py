@@ -10,10 +10,10 @@ If the shared library is missing the import of the binding raises; there is no C
 fallback.
 """
 from .api import (GodietError, DeviceSeqs, DeviceIndex, pack, to_device, sparsify, sketch,
-                  index_build, seed, rmi_train, lookup, contain, lib, lib_path, workspace_size, kept_bound, trace_enable, trace_dump, trace_filter,
+                  index_build, seed, rmi_train, lookup, contain, lib, lib_path, workspace_size, kept_bound, trace_enable, trace_dump, trace_filter, vote, winners_rows,
                   STATUS_CAPACITY,
                   STATUS_RANGE, STATUS_SHIFT)
 
 __all__ = ["GodietError", "DeviceSeqs", "DeviceIndex", "pack", "to_device", "sparsify", "sketch",
-           "index_build", "seed", "rmi_train", "lookup", "contain", "lib", "lib_path", "workspace_size", "kept_bound", "trace_enable", "trace_dump", "trace_filter",
+           "index_build", "seed", "rmi_train", "lookup", "contain", "lib", "lib_path", "workspace_size", "kept_bound", "trace_enable", "trace_dump", "trace_filter", "vote", "winners_rows",
            "STATUS_CAPACITY", "STATUS_RANGE", "STATUS_SHIFT"]

@@ -9,7 +9,8 @@ lib_path = os.path.join(_HERE, "libgodiet.so")
 
 OK, E_INVAL, E_RANGE, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_CAPACITY, STATUS_RANGE, STATUS_SHIFT = 1, 2, 4
-OP_SPARSIFY, OP_SKETCH, OP_INDEX_BUILD, OP_SEED, OP_RMI_TRAIN, OP_CONTAIN = 1, 2, 3, 4, 5, 6
+OP_SPARSIFY, OP_SKETCH, OP_INDEX_BUILD, OP_SEED, OP_RMI_TRAIN, OP_CONTAIN, OP_VOTE = 1, 2, 3, 4, 5, 6, 7
+VOTE_RESCUE = 1
 
 
 class GodietError(RuntimeError):
@@ -38,6 +39,11 @@ class SeedOpts(ctypes.Structure):
     _fields_ = [("shift_mode", ctypes.c_int32), ("align_t", ctypes.c_uint32),
                 ("max_occ", ctypes.c_uint32), ("long_records", ctypes.c_uint32),
                 ("lookup_blocks", ctypes.c_uint32), ("long_blocks", ctypes.c_uint32)]
+
+
+class VoteOpts(ctypes.Structure):
+    _fields_ = [("max_dist", ctypes.c_uint32), ("min_votes", ctypes.c_uint32),
+                ("max_winners", ctypes.c_uint32)]
 
 
 _lib = None
@@ -73,6 +79,8 @@ def lib():
         L.godiet_contain.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), u32, P, P, P, sz,
                                      P, P]
         L.godiet_contain.restype = i32
+        L.godiet_vote.argtypes = [P, P, u32, u64, S(VoteOpts), P, P, P, sz, P, P]
+        L.godiet_vote.restype = i32
         L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
         L.godiet_lookup.restype = i32
         L.godiet_rmi_size.argtypes = [u32]
@@ -364,3 +372,47 @@ def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, ma
     if _status_value(st) & STATUS_RANGE:
         raise ValueError("an index record names a genome id >= n_genomes")
     return counts[:n_genomes], sizes[:n_genomes]
+
+
+def vote(anchors, read_off, max_dist, min_votes, max_winners, capacity=None):
+    """Location voting over seeding anchors (int32 tensor (n, 4), read_off int64 tensor
+    [n_reads+1]).  Returns (winners int32 tensor (n_reads, max_winners, 6): the 24-byte
+    records loc (two words), read_id, strand, votes, flags; n_win int32 tensor)."""
+    torch = _torch()
+    n_reads = read_off.numel() - 1
+    if capacity is None:
+        capacity = anchors.numel() // 4
+    L = lib()
+    rs = Seqs(None, None, n_reads, 0)           # workspace sizing reads only n_seq
+    need = L.godiet_workspace_size(OP_VOTE, ctypes.byref(rs), None, int(capacity))
+    if need == 0:
+        raise ValueError("sizes out of range for location voting")
+    ws = _empty(need, torch.uint8)
+    out = _empty(max(n_reads, 1) * max_winners * 6, torch.int32)
+    nw = _empty(max(n_reads, 1), torch.int32)
+    st = _empty(1, torch.int32)
+    opts = VoteOpts(int(max_dist), int(min_votes), int(max_winners))
+    _check(L.godiet_vote(_ptr(anchors) if anchors.numel() else None, _ptr(read_off), n_reads,
+                         int(capacity), ctypes.byref(opts), _ptr(out), _ptr(nw), _ptr(ws),
+                         ws.numel(), _ptr(st), _stream()), "godiet_vote")
+    status = _status_value(st)
+    if status & STATUS_CAPACITY:
+        raise ValueError("more anchors than the capacity given")
+    if status & STATUS_RANGE:
+        raise ValueError("anchors are not grouped by read as read_off says")
+    return out[:n_reads * max_winners * 6].view(n_reads, max_winners, 6), nw[:n_reads]
+
+
+def winners_rows(winners, n_win):
+    """Host rows (read, strand, votes, flags, loc) of every output winner, in order."""
+    import numpy as np
+    w = winners.cpu().numpy()
+    nw = n_win.cpu().numpy()
+    rows = []
+    if w.size == 0:
+        return np.zeros((0, 5), np.int64)
+    loc = w[:, :, 0].astype(np.int64) & 0xFFFFFFFF | (w[:, :, 1].astype(np.int64) << 32)
+    idx = np.arange(w.shape[1])[None, :] < nw[:, None]
+    r, j = np.nonzero(idx)
+    return np.stack([w[r, j, 2].astype(np.int64), w[r, j, 3].astype(np.int64),
+                     w[r, j, 4].astype(np.int64), w[r, j, 5].astype(np.int64), loc[r, j]], 1)

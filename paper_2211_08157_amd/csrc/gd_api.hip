@@ -112,6 +112,32 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->so.overflow_n = b.take<uint32_t>(1);
 }
 
+struct VoteWs {
+    uint64_t *keys;
+    uint32_t *vals;
+    uint32_t *long_ids, *long_n;
+    SortWs so;
+    SortPlan sp;
+};
+
+void plan_vote_ws(Bump &b, uint32_t n_reads, uint64_t capacity, VoteWs *o)
+{
+    o->keys = b.take<uint64_t>(capacity);
+    o->vals = b.take<uint32_t>(capacity);
+    o->long_ids = b.take<uint32_t>(n_reads);
+    o->long_n = b.take<uint32_t>(1);
+    o->sp = sort_plan(capacity, capacity > 0 ? capacity : 1, 4);
+    o->so.hist = b.take<uint32_t>(o->sp.digits ? o->sp.nchunks * o->sp.nfine : o->sp.nfine);
+    o->so.tot = o->sp.digits ? b.take<uint32_t>(o->sp.nfine) : nullptr;
+    o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
+    o->so.rank = o->sp.digits ? nullptr : b.take<uint32_t>(capacity);
+    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
+    o->so.trec = b.take<ulonglong2>(capacity);
+    o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
+    o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
+    o->so.overflow_n = b.take<uint32_t>(1);
+}
+
 struct SeedWs {
     SketchWs sk;
     uint64_t *mzofs;      // n_shift * (n_reads + 1)
@@ -256,6 +282,12 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
         if (op == GODIET_OP_CONTAIN) b.take<uint8_t>((n_index + 3) / 4 * 4);
         return b.off;
     }
+    case GODIET_OP_VOTE: {
+        if (n_index >= (1ull << 32) || seqs->n_seq >= (1u << 31)) return 0;
+        VoteWs o;
+        plan_vote_ws(b, seqs->n_seq, n_index, &o);
+        return b.off;
+    }
     default: return 0;
     }
 }
@@ -371,6 +403,33 @@ godiet_status godiet_contain(const godiet_index *index, const godiet_seqs *reads
     if (st != GODIET_OK) return st;
     GD_TRY(launch_contain(A, W.slot, index->keys, (const uint64_t *)index->vals, index->n, mark,
                           n_genomes, counts, genome_sizes, status, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anchor_off,
+                          uint32_t n_reads, uint64_t anchor_capacity,
+                          const godiet_vote_opts *opts, godiet_winner *out, uint32_t *n_win,
+                          void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream)
+{
+    if (!opts || !status || opts->max_winners < 1 || opts->max_winners > 16) return GODIET_E_INVAL;
+    if (n_reads > 0 && (!read_anchor_off || !out || !n_win)) return GODIET_E_INVAL;
+    if (anchor_capacity > 0 && !anchors) return GODIET_E_INVAL;
+    if (n_reads >= (1u << 31) || anchor_capacity >= (1ull << 32)) return GODIET_E_RANGE;
+    Bump b(ws);
+    VoteWs W;
+    plan_vote_ws(b, n_reads, anchor_capacity, &W);
+    if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    VoteArgs A;
+    A.max_dist = opts->max_dist;
+    A.min_votes = opts->min_votes;
+    A.max_win = opts->max_winners;
+    int rb = 0;                                   // bits of the largest read id
+    while (rb < 31 && ((uint64_t)(n_reads > 0 ? n_reads - 1 : 0) >> rb) != 0) rb++;
+    A.lz = 64 - 33 - rb;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(launch_vote(A, (const uint4 *)anchors, read_anchor_off, n_reads, anchor_capacity,
+                       W.sp, W.so, W.keys, W.vals, W.long_ids, W.long_n, out, n_win, status,
+                       stream));
     return GODIET_OK;
 }
 

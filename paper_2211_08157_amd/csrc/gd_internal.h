@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "gd_common.h"
+#include "godiet.h"
 
 namespace gd {
 
@@ -130,6 +131,17 @@ struct SortWs {
 };
 hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void *vals,
                        int val_bytes, const uint64_t *n_ptr, uint64_t capacity, hipStream_t s);
+
+// ---- location voting (gd_vote.hip) ----
+struct VoteArgs {
+    uint32_t max_dist, min_votes, max_win;
+    int lz;                 // key shift that puts the read id at the top of the key
+};
+hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *read_off,
+                       uint32_t n_reads, uint64_t capacity, const SortPlan &sp,
+                       const SortWs &sw, uint64_t *keys, uint32_t *vals, uint32_t *long_ids,
+                       uint32_t *long_n, godiet_winner *out, uint32_t *n_win,
+                       uint32_t *status, hipStream_t s);
 
 // ---- lookups, alignment, anchors (gd_seed.hip) ----
 // lb/occ of min(*n_q, q_cap) queries (n_q may be null: q_cap queries); rmi nullable.

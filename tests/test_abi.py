@@ -118,3 +118,27 @@ def test_pack_layout():
     assert p.size % 16 == 0
     with pytest.raises(ValueError):
         gd.pack(np.array([4], np.uint8))
+
+
+def test_vote_host_checks_and_workspace():
+    from paper_2211_08157_amd.api import VoteOpts, Seqs, OP_VOTE, E_INVAL, E_WORKSPACE, E_RANGE
+    L = _lib()
+    dummy = ctypes.c_void_p(0x3000)
+    for cap in (0, 17):                                    # max_winners outside 1..16
+        assert L.godiet_vote(dummy, dummy, 10, 100, ctypes.byref(VoteOpts(10, 2, cap)), dummy,
+                             dummy, dummy, 1 << 40, dummy, None) == E_INVAL
+    ok = VoteOpts(10, 2, 4)
+    assert L.godiet_vote(dummy, dummy, 10, 100, ctypes.byref(ok), dummy, dummy, dummy, 1 << 40,
+                         None, None) == E_INVAL            # no status word
+    assert L.godiet_vote(None, dummy, 10, 100, ctypes.byref(ok), dummy, dummy, dummy, 1 << 40,
+                         dummy, None) == E_INVAL           # anchors missing
+    assert L.godiet_vote(dummy, dummy, 1 << 31, 100, ctypes.byref(ok), dummy, dummy, dummy,
+                         1 << 40, dummy, None) == E_RANGE  # read ids need 31 bits
+    assert L.godiet_vote(dummy, dummy, 10, 100, ctypes.byref(ok), dummy, dummy, dummy, 16,
+                         dummy, None) == E_WORKSPACE
+    # workspace grows with the anchor capacity; only n_seq of the batch is read
+    s = Seqs(None, None, 1000, 0)
+    w1 = L.godiet_workspace_size(OP_VOTE, ctypes.byref(s), None, 10_000)
+    w2 = L.godiet_workspace_size(OP_VOTE, ctypes.byref(s), None, 1_000_000)
+    assert 0 < w1 < w2
+    assert L.godiet_workspace_size(OP_VOTE, ctypes.byref(s), None, 1 << 32) == 0
