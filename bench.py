@@ -164,6 +164,38 @@ def sketch_gbps(gd, torch, seqs, pattern, k, w, reps=5):
     return by / (ms * 1e-3) / 1e9, ms, m, {kn: v[1] / reps for kn, v in tr.items()}
 
 
+VOTE_PARAMS = (16, 3, 4)     # location voting on the step's anchors: D, V, max winners
+
+
+def voting(gd, torch, s, steps, cpu=True):
+    """Location voting over the learned-index step's anchors: GPU time per pass (K passes
+    on the current stream, after one untimed pass) and the oracle on the same anchors."""
+    D, V, cap = VOTE_PARAMS
+    anchors = s.anchors[:4 * s.n_anchors].view(-1, 4)
+    w, nw = gd.vote(anchors, s.roff, D, V, cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w, nw = gd.vote(anchors, s.roff, D, V, cap)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rows = gd.winners_rows(w, nw)
+    out = dict(D=D, V=V, max_winners=cap, ms_per_pass=ms,
+               reads_per_s=s.reads.n_seq / (ms * 1e-3), winners=int(rows.shape[0]),
+               rescued=int((rows[:, 3] & 1).sum()),
+               reads_with_winner=int(((nw.cpu().numpy() > 0)).sum()))
+    if cpu:
+        import oracle
+        a = anchors.cpu().numpy().view(np.uint32)
+        off = s.roff.cpu().numpy().view(np.uint64)
+        t0 = time.perf_counter()
+        oracle.vote(a, off, D, V, cap)
+        sec = time.perf_counter() - t0
+        out["cpu_oracle"] = dict(reads_per_s=s.reads.n_seq / sec, cores=1,
+                                 sample="all reads of the step")
+    return out
+
+
 def cpu_baseline(data, pattern, k, w, sample_reads):
     import oracle
     t0 = time.perf_counter()
@@ -331,6 +363,9 @@ def main():
     second = sorted(trace.items(), key=lambda kv: -kv[1][1])[1]
     roof_next = roofline(second[0], s, units, second[1][1], args.steps, second[1][0])
 
+    vote = voting(gd, torch, s, args.steps, cpu=not args.no_cpu_baseline)
+    log("[bench] location voting: %.3f ms per pass, %.3e reads/s" % (vote["ms_per_pass"],
+                                                                    vote["reads_per_s"]))
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
 
@@ -378,6 +413,7 @@ def main():
         "sketch_GBps": gbps, "sketch_ms": sk_ms, "sketch_bytes_rule": "ceil(L/4) + 12 B/minimizer",
         "sketch_kernels_ms": sk_kernels,
         "sketch_1Gbp": sketch_1g,
+        "location_voting": vote,
         "index_records": n_index, "anchors": n_anchors, "lookups_per_step": queries,
         "kernels": per_kernel, "output_sha256_16": digest,
     }

@@ -62,6 +62,22 @@ def lookup_digest(lb, occ):
                 occ_sum=int(occ.astype(np.uint64).sum()), sha256=_h(lb, occ), parts=parts)
 
 
+def votes_digest(n_win, rows):
+    """rows: (n, 5) int64 (read, strand, votes, flags, loc) of every output winner in read
+    order; n_win: winners per read."""
+    nw = np.ascontiguousarray(n_win).astype(np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.int64).reshape(-1, 5)
+    off = np.zeros(nw.size + 1, np.int64)
+    off[1:] = np.cumsum(nw)
+    n_reads = nw.size
+    cut = [i * n_reads // PARTS for i in range(PARTS + 1)]
+    parts = [[int(off[cut[i + 1]] - off[cut[i]]), _h(rows[off[cut[i]]:off[cut[i + 1]]],
+                                                       nw[cut[i]:cut[i + 1]])[:16]]
+             for i in range(PARTS)]
+    return dict(n=int(rows.shape[0]), sha256=_h(rows, nw),
+                rescued=int((rows[:, 3] & 1).sum()), parts=parts)
+
+
 def lookup_queries(read_keys, n_total=500_000_000, absent_frac=0.2, seed=404):
     """Lookup workload: n_total queries, the first (1 - absent_frac) drawn uniformly with
     replacement from read_keys (seed 404), the rest random 64-bit keys (seed 304; one

@@ -65,6 +65,15 @@ def parallel_seed(ik, iv, codes, offsets, pattern, chunk=20_000):
     return anchors, read_off, shift
 
 
+# location-voting parameters per workload: (D, V, max_winners)
+VOTE = {"illumina-100Mbp": (16, 3, 4), "uneven-1Gbp": (100, 3, 4)}
+
+
+def vote_rows(out, nw):
+    r, j = np.nonzero(np.arange(out.shape[1])[None, :] < nw[:, None])
+    return np.concatenate([r[:, None].astype(np.int64), out[r, j]], axis=1)
+
+
 def seed_entry(d, pattern):
     ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], pattern, K, W)
     log("%s %s: index %d records" % (d["name"], pattern, ik.size))
@@ -72,6 +81,10 @@ def seed_entry(d, pattern):
     a, off, sh = parallel_seed(ik, iv, d["reads"], d["read_offsets"], pattern)
     log("%s %s: %d anchors" % (d["name"], pattern, a.shape[0]))
     ent["anchors"] = fullsize.anchors_digest(a, off, sh)
+    D, V, cap = VOTE[d["name"]]
+    out, nw = oracle.vote(a, off, D, V, cap)
+    ent["votes"] = dict(fullsize.votes_digest(nw, vote_rows(out, nw)), D=D, V=V, cap=cap)
+    log("%s %s: %d winners" % (d["name"], pattern, ent["votes"]["n"]))
     return ent, ik
 
 

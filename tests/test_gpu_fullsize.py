@@ -6,10 +6,10 @@ part that differs when a check fails.
 
   * Illumina-like 100 Mbp reference, 1M x 150 bp reads, '10', k21 w11: the benchmark's
     own preallocated step (index build + seeding), with binary search and with the
-    learned index;
+    learned index, then location voting on its anchors (D 16, V 3, 4 winners);
   * 1 Gbp reference with one mixed batch of 2M short + 20k HiFi-like + 20k ONT-like reads,
     '10' and '110': index build, then one HIP-graph-captured seeding pass with launch
-    parameters from the autotuner;
+    parameters from the autotuner, then location voting (D 100, V 3, 4 winners);
   * 500M lookups (80 % drawn from that batch's read minimizers, 20 % random keys) in the
     1 Gbp '10' index: learned index (MLP and linear roots, 2^18 leaves) equals binary
     search equals the oracle; every result also satisfies the lower-bound property;
@@ -77,6 +77,13 @@ def test_illumina_100mbp_benchmark_step(gpu, golden):
         a = s.anchors[:4 * na].cpu().numpy().view(np.uint32)
         got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
         assert_digest(got, exp["anchors"], "anchors (learned index %s)" % learned)
+    check_votes(gpu, s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, exp["votes"])
+
+
+def check_votes(gpu, anchors, read_off, exp):
+    w, nw = gpu.vote(anchors, read_off, exp["D"], exp["V"], exp["cap"])
+    got = fullsize.votes_digest(nw.cpu().numpy().view(np.uint32), gpu.winners_rows(w, nw))
+    assert_digest(got, exp, "location votes")
 
 
 @pytest.fixture(scope="module")
@@ -110,6 +117,7 @@ def test_uneven_1gbp_graph_captured_autotuned(gpu, golden, uneven, pattern, tmp_
     got = fullsize.anchors_digest(a.cpu().numpy().view(np.uint32), host_u64(off),
                                   sh.cpu().numpy())
     assert_digest(got, exp["anchors"], "anchors")
+    check_votes(gpu, a, off, exp["votes"])
 
 
 @pytest.mark.timeout(900)
