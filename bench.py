@@ -90,6 +90,10 @@ class Session:
         self.cix = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32, None, 0)
         self.cix_rmi = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
                                  self.rmi.data_ptr(), self.rmi.numel())
+        self.table = torch.empty(api.lib().godiet_table_size(self.n_index), dtype=torch.uint8,
+                                 device=dev)
+        self.cix_table = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
+                                   None, 0, self.table.data_ptr(), self.table.numel())
         self.opts = api.SeedOpts(-1, 0, 0, 0, 0, 0)
         del ix, a, off
         # per-shift query counts (minimizers of the reads at every shift) for byte accounting
@@ -102,7 +106,11 @@ class Session:
             del kq
         torch.cuda.synchronize()
 
-    def step(self, learned=False):
+    def step(self, mode="binary_search"):
+        """One step: index build, then (learned_index) learned-index training or
+        (hash_table) hash-table build, then seeding of every read."""
+        if mode is True or mode is False:
+            mode = "learned_index" if mode else "binary_search"
         L = self.api.lib()
         st = ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
         r = L.godiet_index_build(ctypes.byref(self.cref), ctypes.byref(self.prm),
@@ -113,12 +121,17 @@ class Session:
                                  ctypes.c_void_p(self.st_i.data_ptr()), st)
         if r != 0:
             raise RuntimeError("godiet_index_build failed: %d" % r)
-        if learned:
+        if mode == "learned_index":
             r = L.godiet_rmi_train(ctypes.byref(self.cix), 1, self.log2_leaves,
                                    ctypes.c_void_p(self.rmi.data_ptr()), self.rmi.numel(), st)
             if r != 0:
                 raise RuntimeError("godiet_rmi_train failed: %d" % r)
-        cix = self.cix_rmi if learned else self.cix
+        elif mode == "hash_table":
+            r = L.godiet_table_build(ctypes.byref(self.cix), ctypes.c_void_p(self.table.data_ptr()),
+                                     self.table.numel(), st)
+            if r != 0:
+                raise RuntimeError("godiet_table_build failed: %d" % r)
+        cix = {"learned_index": self.cix_rmi, "hash_table": self.cix_table}.get(mode, self.cix)
         r = L.godiet_seed(ctypes.byref(cix), ctypes.byref(self.creads), ctypes.byref(self.prm),
                           ctypes.byref(self.opts), ctypes.c_void_p(self.anchors.data_ptr()),
                           self.acap, ctypes.c_void_p(self.roff.data_ptr()),
@@ -307,9 +320,9 @@ def main():
     log("[bench] index %d records, %d anchors, %d lookups per step" % (s.n_index, s.n_anchors,
                                                                       s.queries))
     modes = {}
-    for learned in (False, True):
+    for mode in ("binary_search", "hash_table", "learned_index"):
         for _ in range(args.warmup):
-            s.step(learned)
+            s.step(mode)
         s.check()
         digest = s.digest()
         # per-kernel breakdown from a traced pass of the same K steps (events around every
@@ -319,7 +332,7 @@ def main():
         gd.trace_dump()
         gd.trace_enable(True)
         for _ in range(args.steps):
-            s.step(learned)
+            s.step(mode)
         torch.cuda.synchronize()
         gd.trace_enable(False)
         trace = gd.trace_dump()
@@ -330,7 +343,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            s.step(learned)
+            s.step(mode)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         gd.trace_enable(False)
@@ -340,14 +353,14 @@ def main():
         if s.digest() != digest:
             raise RuntimeError("outputs changed between steps")
         ms_step = (t1 - t0) * 1e3 / args.steps
-        modes["learned_index" if learned else "binary_search"] = dict(
+        modes[mode] = dict(
             ms_per_step=ms_step, reads_per_s=s.reads.n_seq / (ms_step * 1e-3), digest=digest,
             trace=trace, dominant=dom, live=live)
-        log("[bench] %s: %.3f ms/step, %.3e reads/s" % ("learned index" if learned else
-                                                         "binary search", ms_step,
+        log("[bench] %s: %.3f ms/step, %.3e reads/s" % (mode.replace("_", " "), ms_step,
                                                          s.reads.n_seq / (ms_step * 1e-3)))
-    if modes["learned_index"]["digest"] != modes["binary_search"]["digest"]:
-        raise RuntimeError("learned-index anchors differ from binary-search anchors")
+    for mode in ("learned_index", "hash_table"):
+        if modes[mode]["digest"] != modes["binary_search"]["digest"]:
+            raise RuntimeError("%s anchors differ from binary-search anchors" % mode)
     head = "learned_index"
     ms_step = modes[head]["ms_per_step"]
     value = modes[head]["reads_per_s"]
@@ -406,6 +419,11 @@ def main():
                           "kernels": {kn: dict(launches=n, ms_per_step=ms / args.steps)
                                       for kn, (n, ms) in modes["binary_search"]["trace"].items()}},
         "learned_vs_binary_speedup": modes["binary_search"]["ms_per_step"] / ms_step,
+        "hash_table": {"ms_per_step": modes["hash_table"]["ms_per_step"],
+                       "reads_per_s": modes["hash_table"]["reads_per_s"],
+                       "note": "the paper's index form (hash -> location list), built in the step",
+                       "kernels": {kn: dict(launches=n, ms_per_step=ms / args.steps)
+                                   for kn, (n, ms) in modes["hash_table"]["trace"].items()}},
         "roofline": roof,
         "roofline_second_kernel": roof_next,
         "work_per_step": units,

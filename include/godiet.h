@@ -103,6 +103,9 @@ typedef struct {
     int32_t val_bits;
     const void *rmi;
     size_t rmi_bytes;         /* [host] */
+    const void *table;        /* NULL, or the hash-table form built by godiet_table_build on
+                                 exactly these keys; used by seeding and containment lookups */
+    size_t table_bytes;       /* [host] */
 } godiet_index;
 
 typedef struct {
@@ -244,6 +247,21 @@ godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anc
  * q, lb, occ: device arrays of n_q entries.  Needs index->n < 2^32. */
 godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64_t n_q,
                             uint32_t *lb, uint32_t *occ, hipStream_t stream);
+
+/* Hash-table form of the seed index (Section 3.1: every distinct minimizer hash maps to
+ * its sorted location list; here the list is the run [start, start + count) of the sorted
+ * keys/vals).  Open addressing with linear probing: a 64-byte header, then 2^b slots of
+ * 16 bytes {uint64 key, uint32 start, uint32 count}, 2^b the smallest power of two >=
+ * 2 * index->n (load factor <= 1/2), home slot = the key's low b bits, count 0 = empty.
+ * godiet_table_size(n) is the byte size (0 if n >= 2^32); godiet_table_build writes the
+ * whole buffer (16-byte aligned, table_bytes >= that size) from index->keys.  godiet_seed
+ * and godiet_contain then look read minimizers up in it when index->table is set, with
+ * results identical to binary search; godiet_lookup ignores it (a table has no lower
+ * bound for an absent key).  A table built for other keys is detected by its key count
+ * and ignored. */
+size_t godiet_table_size(uint64_t n_index);
+godiet_status godiet_table_build(const godiet_index *index, void *table, size_t table_bytes,
+                                 hipStream_t stream);
 
 /* Learned index (not part of the paper; its counterpart there is the hash table of
  * Section 3.1): a two-stage recursive model index over index->keys.  The root (root_kind

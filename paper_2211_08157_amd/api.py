@@ -32,7 +32,8 @@ class Params(ctypes.Structure):
 class Index(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("n", ctypes.c_uint64),
                 ("val_bits", ctypes.c_int32), ("rmi", ctypes.c_void_p),
-                ("rmi_bytes", ctypes.c_size_t)]
+                ("rmi_bytes", ctypes.c_size_t), ("table", ctypes.c_void_p),
+                ("table_bytes", ctypes.c_size_t)]
 
 
 class SeedOpts(ctypes.Structure):
@@ -81,6 +82,10 @@ def lib():
         L.godiet_contain.restype = i32
         L.godiet_vote.argtypes = [P, P, u32, u64, S(VoteOpts), P, P, P, sz, P, P]
         L.godiet_vote.restype = i32
+        L.godiet_table_size.argtypes = [u64]
+        L.godiet_table_size.restype = sz
+        L.godiet_table_build.argtypes = [S(Index), P, sz, P]
+        L.godiet_table_build.restype = i32
         L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
         L.godiet_lookup.restype = i32
         L.godiet_rmi_size.argtypes = [u32]
@@ -252,19 +257,40 @@ def sketch(seqs, pattern, k, w, shift=None, capacity=None):
 
 class DeviceIndex:
     """A sorted seed index in device memory (keys as int64 bit patterns of uint64), with an
-    optional learned-index model (uint8 tensor) used for its lookups."""
+    optional learned-index model and an optional hash table (uint8 tensors) used for its
+    lookups."""
 
-    def __init__(self, keys, vals, n, val_bits, rmi=None):
+    def __init__(self, keys, vals, n, val_bits, rmi=None, table=None):
         self.keys, self.vals, self.n, self.val_bits = keys, vals, int(n), int(val_bits)
         self.rmi = rmi
+        self.table = table
 
     def c(self):
         return Index(self.keys.data_ptr(), self.vals.data_ptr(), self.n, self.val_bits,
                      self.rmi.data_ptr() if self.rmi is not None else None,
-                     self.rmi.numel() if self.rmi is not None else 0)
+                     self.rmi.numel() if self.rmi is not None else 0,
+                     self.table.data_ptr() if self.table is not None else None,
+                     self.table.numel() if self.table is not None else 0)
 
     def with_rmi(self, rmi):
-        return DeviceIndex(self.keys, self.vals, self.n, self.val_bits, rmi)
+        return DeviceIndex(self.keys, self.vals, self.n, self.val_bits, rmi, self.table)
+
+    def with_table(self, table):
+        return DeviceIndex(self.keys, self.vals, self.n, self.val_bits, self.rmi, table)
+
+
+def table_build(index):
+    """Build the hash-table form of index (seeding and containment lookups use it);
+    returns a copy of the index that carries it."""
+    torch = _torch()
+    L = lib()
+    nbytes = L.godiet_table_size(index.n)
+    if nbytes == 0:
+        raise ValueError("index too large for a hash table")
+    blob = _empty(nbytes, torch.uint8)
+    _check(L.godiet_table_build(ctypes.byref(index.c()), _ptr(blob), nbytes, _stream()),
+           "godiet_table_build")
+    return index.with_table(blob)
 
 
 def rmi_train(index, root="mlp", log2_leaves=18):

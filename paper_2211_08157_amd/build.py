@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libgodiet.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["gd_api.hip", "gd_scan.hip", "gd_sketch.hip", "gd_sort.hip", "gd_seed.hip",
-           "gd_trace.hip", "gd_rmi.hip", "gd_contain.hip", "gd_vote.hip"]
+           "gd_trace.hip", "gd_rmi.hip", "gd_contain.hip", "gd_vote.hip", "gd_table.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

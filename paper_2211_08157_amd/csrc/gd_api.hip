@@ -198,7 +198,8 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
                              prm->w, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
-                             W.occ + si * W.stride, index->rmi, opts->lookup_blocks, stream));
+                             W.occ + si * W.stride, index->rmi, index->table,
+                             opts->lookup_blocks, stream));
     }
     AlignArgs &A = *Ap;
     A.mzofs = W.mzofs;
@@ -433,6 +434,24 @@ godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anc
     return GODIET_OK;
 }
 
+size_t godiet_table_size(uint64_t n_index)
+{
+    if (n_index >= (1ull << 32)) return 0;
+    return table_bytes(n_index);
+}
+
+godiet_status godiet_table_build(const godiet_index *index, void *table, size_t table_bytes_,
+                                 hipStream_t stream)
+{
+    if (!index || !table) return GODIET_E_INVAL;
+    if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (table_bytes_ < table_bytes(index->n)) return GODIET_E_WORKSPACE;
+    if (((uintptr_t)table & 15) != 0) return GODIET_E_INVAL;
+    GD_TRY(launch_table_build(index->keys, index->n, table, stream));
+    return GODIET_OK;
+}
+
 size_t godiet_rmi_size(uint32_t log2_leaves)
 {
     if (log2_leaves < 1 || log2_leaves > 24) return 0;
@@ -460,7 +479,8 @@ godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64
     if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
     if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
     if (n_q == 0) return GODIET_OK;
-    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, 0, stream));
+    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, nullptr, 0,
+                         stream));
     return GODIET_OK;
 }
 

@@ -145,9 +145,15 @@ hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *
 
 // ---- lookups, alignment, anchors (gd_seed.hip) ----
 // lb/occ of min(*n_q, q_cap) queries (n_q may be null: q_cap queries); rmi nullable.
+// table (nullable, seeding only): hash-table lookups, whose lb is 0 for absent keys
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, uint32_t blocks, hipStream_t s);
+                         const void *rmi, const void *table, uint32_t blocks, hipStream_t s);
+
+// ---- hash-table index form (gd_table.hip) ----
+uint32_t table_log2_slots(uint64_t n);
+size_t table_bytes(uint64_t n);
+hipError_t launch_table_build(const uint64_t *keys, uint64_t n, void *table, hipStream_t s);
 
 // ---- learned index (gd_rmi.hip)
 size_t rmi_bytes(uint32_t log2_leaves);

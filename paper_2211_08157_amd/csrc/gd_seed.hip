@@ -10,6 +10,7 @@
 // anchors of a read are written as one contiguous run in (qpos, rpos) order.
 #include "gd_internal.h"
 #include "gd_rmi_model.h"
+#include "gd_table_model.h"
 
 namespace gd {
 
@@ -104,13 +105,13 @@ __device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, 
     u = run_end(keys, n, l, q);
 }
 
-// One lane per query; `rmi` (nullable) switches the lower bound to the learned index
-// (kWide: keys 16-byte aligned, windowed loads).
-template <bool kModel, bool kWide>
+// One lane per query.  kMode: 0 binary search, 1 learned index (scalar loads), 2 learned
+// index (keys 16-byte aligned, windowed loads), 3 hash table (lb 0 for absent keys).
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64_t in,
                                                    const uint64_t *q, const uint64_t *n_q,
                                                    uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                                                   const void *rmi)
+                                                   const void *model)
 {
     uint64_t n = n_q ? *n_q : q_cap;
     if (n > q_cap) n = q_cap;
@@ -118,10 +119,18 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
          i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t x = q[i];
         uint64_t l, u;
-        if (kModel && kWide) {
-            rmi_find(rmi, ikeys, in, x, l, u);
+        if (kMode == 3) {
+            uint64_t c;
+            if (table_find(model, in, x, l, c)) {
+                u = l + c;
+            } else {
+                l = lower_bound_u64(ikeys, in, x);
+                u = run_end(ikeys, in, l, x);
+            }
+        } else if (kMode == 2) {
+            rmi_find(model, ikeys, in, x, l, u);
         } else {
-            l = kModel ? rmi_lower_bound(rmi, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
+            l = kMode == 1 ? rmi_lower_bound(model, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
             u = run_end(ikeys, in, l, x);
         }
         lb[i] = (uint32_t)l;
@@ -353,21 +362,24 @@ __global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint3
 
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, uint32_t max_blocks, hipStream_t s)
+                         const void *rmi, const void *table, uint32_t max_blocks, hipStream_t s)
 {
     uint64_t blocks = (q_cap + kBlock - 1) / kBlock;
     const uint64_t cap = max_blocks ? max_blocks : 8192;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
-    if (rmi && ((uintptr_t)ikeys & 15) == 0)
-        GD_LAUNCH((k_lookup<true, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in,
-                  q, n_q, q_cap, lb, occ, rmi);
+    if (table)
+        GD_LAUNCH(k_lookup<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, table);
+    else if (rmi && ((uintptr_t)ikeys & 15) == 0)
+        GD_LAUNCH(k_lookup<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, rmi);
     else if (rmi)
-        GD_LAUNCH((k_lookup<true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in,
-                  q, n_q, q_cap, lb, occ, rmi);
+        GD_LAUNCH(k_lookup<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, rmi);
     else
-        GD_LAUNCH((k_lookup<false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys,
-                  in, q, n_q, q_cap, lb, occ, rmi);
+        GD_LAUNCH(k_lookup<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
+                  q_cap, lb, occ, rmi);
     return hipGetLastError();
 }
 

@@ -142,3 +142,19 @@ def test_vote_host_checks_and_workspace():
     w2 = L.godiet_workspace_size(OP_VOTE, ctypes.byref(s), None, 1_000_000)
     assert 0 < w1 < w2
     assert L.godiet_workspace_size(OP_VOTE, ctypes.byref(s), None, 1 << 32) == 0
+
+
+def test_table_size_and_host_checks():
+    from paper_2211_08157_amd.api import Index, E_INVAL, E_WORKSPACE, E_RANGE
+    L = _lib()
+    # 64-byte header + 16-byte slots, slots the smallest power of two >= 2n (at least 16)
+    for n, slots in ((0, 16), (1, 16), (8, 16), (9, 32), (1000, 2048), (8_335_754, 1 << 24)):
+        assert L.godiet_table_size(n) == 64 + 16 * slots
+    assert L.godiet_table_size(1 << 32) == 0
+    ix = Index(0x4000, 0x5000, 100, 32, None, 0)
+    need = L.godiet_table_size(100)
+    assert L.godiet_table_build(ctypes.byref(ix), None, need, None) == E_INVAL
+    assert L.godiet_table_build(ctypes.byref(ix), ctypes.c_void_p(0x6000), need - 1, None) == E_WORKSPACE
+    assert L.godiet_table_build(ctypes.byref(ix), ctypes.c_void_p(0x6008), need, None) == E_INVAL
+    big = Index(0x4000, 0x5000, 1 << 32, 32, None, 0)
+    assert L.godiet_table_build(ctypes.byref(big), ctypes.c_void_p(0x6000), 1 << 40, None) == E_RANGE
