@@ -51,11 +51,18 @@ struct SeqCache {
     const uint64_t *pofs;   // global boundaries, n_seq + 1 entries
     uint32_t n_seq;
     const uint64_t *sh;     // LDS copy of pofs[lo .. lo + n]
+    const uint64_t *offs;   // original offsets (global) and, if osh, their LDS copy
+    const uint64_t *osh;
     uint32_t lo, n;         // n == 0: no cache
     __device__ __forceinline__ uint64_t at(uint32_t s) const
     {
         const uint32_t d = s - lo;
         return d <= n ? sh[d] : pofs[s];
+    }
+    __device__ __forceinline__ uint64_t orig(uint32_t s) const
+    {
+        const uint32_t d = s - lo;
+        return (osh && d <= n) ? osh[d] : offs[s];
     }
     // last s with pofs[s] <= j (j < pofs[n_seq])
     __device__ __forceinline__ uint32_t find(uint64_t j) const
@@ -101,18 +108,27 @@ __global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, ui
 
 // Fill the cache with the boundaries of sequences lo..hi from k_window_seqs (all threads
 // of the workgroup call this).
+// With offs/osh set, the sequences' original offsets are cached as well (loaded together
+// with the boundaries, so no later load waits on the sequence search).
 __device__ __forceinline__ SeqCache seq_cache(const uint64_t *pofs, uint32_t n_seq,
-                                              const uint32_t *lohi, uint64_t win, uint64_t *sh)
+                                              const uint32_t *lohi, uint64_t win, uint64_t *sh,
+                                              const uint64_t *offs = nullptr,
+                                              uint64_t *osh = nullptr)
 {
     SeqCache c;
     c.pofs = pofs;
     c.n_seq = n_seq;
     c.sh = sh;
+    c.offs = offs;
+    c.osh = osh;
     const uint32_t lo = lohi[2 * win], hi = lohi[2 * win + 1];
     c.lo = lo;
     c.n = lo < n_seq ? hi - lo + 1 : 0;      // sequences lo..hi, boundaries lo..hi+1
     if (c.n + 1 > (uint32_t)kSeqCache) c.n = 0;
-    for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += kBlock) sh[i] = pofs[c.lo + i];
+    for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += kBlock) {
+        sh[i] = pofs[c.lo + i];
+        if (osh) osh[i] = offs[c.lo + i];
+    }
     __syncthreads();
     return c;
 }
@@ -132,6 +148,19 @@ __global__ __launch_bounds__(kBlock) void k_kept(const uint64_t *offsets, uint32
 }
 
 // ---------------------------------------------------------------- sparsify
+
+// (li / x, li % x) without an integer divide: a double estimate, corrected.
+__device__ __forceinline__ void div_x(uint64_t li, uint32_t x, double inv_x, uint64_t *q,
+                                      uint32_t *r)
+{
+    int64_t qq = (int64_t)((double)li * inv_x);
+    int64_t rr = (int64_t)li - qq * (int64_t)x;
+    while (rr < 0) { qq--; rr += x; }
+    while (rr >= (int64_t)x) { qq++; rr -= x; }
+    *q = (uint64_t)qq;
+    *r = (uint32_t)rr;
+}
+
 
 __device__ __forceinline__ uint32_t base_at(const uint8_t *bases, uint64_t g)
 {
@@ -163,10 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                                                      const uint32_t *shift, uint32_t uniform,
                                                      const uint64_t *pofs, uint32_t *psw,
                                                      size_t words, uint64_t nbytes, int compact,
-                                                     const uint32_t *lohi)
+                                                     double inv_x, const uint32_t *lohi)
 {
     __shared__ uint64_t sh_pofs[kSeqCache];
-    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs);
+    __shared__ uint64_t sh_offs[kSeqCache];
+    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs, offsets, sh_offs);
     const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
     if (q >= words) return;
     const uint64_t np = pofs[n_seq];
@@ -178,17 +208,39 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
         while (j0 >= end) { s++; beg = end; end = C.at(s + 1); }
         uint32_t a = seq_shift(shift, uniform, s);
         if (a >= P.p) a = 0;
-        if (P.p == 2 && P.x == 1 && j0 + 16 <= end) {
-            const uint64_t o0 = offsets[s] + ((j0 - beg) / P.x) * 2 + kept_phase(P, a, 0);
-            const uint64_t g = o0 >> 4;
-            if ((g + 3) * 4 <= nbytes) {
-                const uint32_t *wd = (const uint32_t *)bases;
+        if (P.p == 2 && P.x == 1) {
+            // 16 kept bases from original position o: every other base of a run of 32
+            const uint32_t *wd = (const uint32_t *)bases;
+            auto run16 = [&](uint64_t o) -> uint32_t {
+                const uint64_t g = o >> 4;
                 const uint32_t W0 = wd[g], W1 = wd[g + 1], W2 = wd[g + 2];
-                const int sh = 2 * (int)(o0 & 15);
+                const int sh = 2 * (int)(o & 15);
                 const uint32_t lo = __builtin_amdgcn_alignbit(W1, W0, sh);
                 const uint32_t hi = __builtin_amdgcn_alignbit(W2, W1, sh);
-                psw[q] = unzip_even(((uint64_t)hi << 32) | lo);
+                return unzip_even(((uint64_t)hi << 32) | lo);
+            };
+            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + kept_phase(P, a, 0);   // x == 1
+            if (j0 + 16 <= end && ((o0 >> 4) + 3) * 4 <= nbytes) {
+                psw[q] = run16(o0);
                 return;
+            }
+            // a word that ends inside the next non-empty sequence (most read boundaries):
+            // the first n1 bases from this sequence, the rest from the start of the next;
+            // both runs are read at once
+            if (j0 + 16 > end && j0 + 16 <= np) {
+                uint32_t s2 = s + 1;
+                while (C.at(s2 + 1) == C.at(s2)) s2++;        // skip empty sequences
+                const uint64_t end2 = C.at(s2 + 1);
+                uint32_t a2 = seq_shift(shift, uniform, s2);
+                if (a2 >= P.p) a2 = 0;
+                const uint64_t o2 = C.orig(s2) + kept_phase(P, a2, 0);
+                if (j0 + 16 <= end2 && ((o0 >> 4) + 3) * 4 <= nbytes &&
+                    ((o2 >> 4) + 3) * 4 <= nbytes) {
+                    const int n1 = (int)(end - j0);           // 1..15
+                    const uint32_t w1 = run16(o0), w2 = run16(o2);
+                    psw[q] = (w1 & ((1u << (2 * n1)) - 1u)) | (w2 << (2 * n1));
+                    return;
+                }
             }
         }
         int u = 0;
@@ -202,12 +254,13 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
             }
             const int seg = (int)min((uint64_t)(16 - u), end - j);   // bases of sequence s
             const uint64_t li = j - beg;
-            const uint64_t per = li / P.x;
-            const uint32_t r = (uint32_t)(li - per * P.x);
+            uint64_t per;
+            uint32_t r;
+            div_x(li, P.x, inv_x, &per, &r);
             const uint64_t rot = rotated_mask(P, a);
             uint64_t m = rot;                      // kept phases of the period not yet used
             for (uint32_t t = 0; t < r; t++) m &= m - 1;
-            const uint64_t ob = offsets[s] + per * P.p;                // period start
+            const uint64_t ob = C.orig(s) + per * P.p;                // period start
             const uint64_t g = (ob + (uint64_t)__builtin_ctzll(m)) >> 4;
             if (compact && (g + 4) * 4 <= nbytes) {
                 const uint32_t *wd = (const uint32_t *)bases;
@@ -297,17 +350,6 @@ __device__ __forceinline__ uint32_t mask_le(int64_t x)
     return x < 0 ? 0u : (x >= 15 ? 0xFFFFu : (2u << x) - 1u);
 }
 
-// (li / x, li % x) without an integer divide: a double estimate, corrected.
-__device__ __forceinline__ void div_x(uint64_t li, uint32_t x, double inv_x, uint64_t *q,
-                                      uint32_t *r)
-{
-    int64_t qq = (int64_t)((double)li * inv_x);
-    int64_t rr = (int64_t)li - qq * (int64_t)x;
-    while (rr < 0) { qq--; rr += x; }
-    while (rr >= (int64_t)x) { qq++; rr -= x; }
-    *q = (uint64_t)qq;
-    *r = (uint32_t)rr;
-}
 
 // Minimizer selection for the 16 positions of this thread, w = W known at compile time.
 // Window minima of the windows starting in the chunk come from the chunk's suffix minima
@@ -733,7 +775,7 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
     const int compact = (int)(((15 + P.x - 1) / P.x + 1) * P.p <= 48);
     GD_LAUNCH(k_sparsify, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.bases, b.offsets,
               b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4, compact,
-              (const uint32_t *)lohi);
+              1.0 / (double)P.x, (const uint32_t *)lohi);
     return hipGetLastError();
 }
 
