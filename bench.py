@@ -210,20 +210,113 @@ def voting(gd, torch, s, steps, cpu=True):
 
 
 def cpu_baseline(data, pattern, k, w, sample_reads):
+    """The oracle on the host: index build (one call), then seeding of a bounded sample of
+    reads split over threads by read ranges (each read's anchors are independent; the
+    oracle is C called through ctypes, which releases the interpreter lock)."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(os.cpu_count() or 1, 16))
     t0 = time.perf_counter()
     ik, iv = oracle.index_build(data["ref"], data["ref_offsets"], pattern, k, w)
     t1 = time.perf_counter()
-    ro = data["read_offsets"][:sample_reads + 1]
-    oracle.seed(ik, iv, data["reads"][:int(ro[-1])], ro, pattern, k, w)
+    ro = np.asarray(data["read_offsets"], np.int64)
+    chunk = max(1, sample_reads // (4 * threads))
+    starts = list(range(0, sample_reads, chunk))
+
+    def one(r0):
+        r1 = min(r0 + chunk, sample_reads)
+        oracle.seed(ik, iv, data["reads"][ro[r0]:ro[r1]], ro[r0:r1 + 1] - ro[r0], pattern, k, w)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, starts))
     t2 = time.perf_counter()
-    n_reads = data["read_offsets"].size - 1
+    n_reads = ro.size - 1
     per_read = (t2 - t1) / sample_reads
     total = (t1 - t0) + per_read * n_reads
-    return dict(value=n_reads / total, unit="reads/s", cores=1, kind="oracle",
-                sample="index of the full reference (%.1f s) + seeding of the first %d of %d "
-                       "reads (%.1f s), scaled to the full batch" % (t1 - t0, sample_reads,
-                                                                    n_reads, t2 - t1))
+    return dict(value=n_reads / total, unit="reads/s", cores=threads, kind="oracle",
+                sample="index of the full reference on 1 thread (%.1f s) + seeding of the first "
+                       "%d of %d reads on %d threads (%.1f s), scaled to the full batch"
+                       % (t1 - t0, sample_reads, n_reads, threads, t2 - t1))
+
+
+def copy_gbps(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time): the measured HBM
+    ceiling next to the published 8 TB/s."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def gather_rate(torch, n_keys, n_q, reps=5):
+    """Random 8-byte gathers per second into an array of n_keys (torch's index kernel):
+    the random-line reference for the lookups."""
+    keys = torch.arange(n_keys, dtype=torch.int64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(404)
+    idx = torch.randint(0, n_keys, (n_q,), device="cuda", generator=g)
+    out = keys[idx]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = keys[idx]
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del keys, idx, out
+    return n_q / (ms * 1e-3)
+
+
+def uneven_batch(gd, torch, steps):
+    """The 1 Gbp reference with the mixed batch of 2M short, 20k HiFi-like and 20k
+    ONT-like reads: one seeding pass (learned index sized at ~32 keys per leaf) captured
+    in a HIP graph with launch parameters from the autotuner, replayed; per pattern."""
+    import datagen
+    from paper_2211_08157_amd import autotune
+    from paper_2211_08157_amd.plan import SeedPlan
+    d = datagen.workload_uneven()
+    ref = gd.to_device(d["ref"], d["ref_offsets"])
+    reads = gd.to_device(d["reads"], d["read_offsets"])
+    n_reads, n_bases = reads.n_seq, reads.n_bases
+    del d
+    out = {}
+    for pat in ("10", "110"):
+        ix = gd.index_build(ref, pat, 21, 11)
+        leaves = max(18, int(np.ceil(np.log2(max(ix.n, 1) / 32))))     # ~32 keys per leaf
+        ix = gd.rmi_train(ix, root="mlp", log2_leaves=leaves)
+        grid = {"long_records": [64, 192], "lookup_blocks": [8192], "long_blocks": [1024]}
+        tuning, _ = autotune.tune(ix, reads, pat, 21, 11, grid=grid, reps=1, use_cache=False)
+        plan = SeedPlan(ix, reads, pat, 21, 11, tuning=tuning)
+        plan.capture()
+        plan.replay()
+        plan.check()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        plan.check()
+        ms = e0.elapsed_time(e1) / steps
+        n_anch = int(plan.read_off[-1].item())
+        out[pat] = dict(ms_per_pass=ms, reads_per_s=n_reads / (ms * 1e-3),
+                        bases_per_s=n_bases / (ms * 1e-3), anchors=n_anch, index_records=ix.n,
+                        log2_leaves=leaves, tuning=tuning)
+        log("[bench] uneven 1 Gbp batch, pattern %s: %.2f ms per graph replay, %.3e reads/s"
+            % (pat, ms, n_reads / (ms * 1e-3)))
+        del plan, ix
+        torch.cuda.empty_cache()
+    out["reads"] = n_reads
+    out["bases"] = n_bases
+    return out
 
 
 def kept_counts(lengths, pattern, shift):
@@ -298,7 +391,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=200_000)
-    ap.add_argument("--no-1gbp", action="store_true", help="skip the 1 Gbp reference sketch")
+    ap.add_argument("--no-1gbp", action="store_true",
+                    help="skip the 1 Gbp reference sketch and the uneven 1 Gbp batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -379,10 +473,12 @@ def main():
     vote = voting(gd, torch, s, args.steps, cpu=not args.no_cpu_baseline)
     log("[bench] location voting: %.3f ms per pass, %.3e reads/s" % (vote["ms_per_pass"],
                                                                     vote["reads_per_s"]))
+    lookup_gather = gather_rate(torch, s.n_index, s.queries)
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
 
     n_reads, n_index, n_anchors, queries = s.reads.n_seq, s.n_index, s.n_anchors, s.queries
+    s_queries = queries
     sketch_1g = None
     if not args.no_1gbp:
         del s
@@ -399,6 +495,11 @@ def main():
             log("[bench] 1 Gbp sketch, pattern %s: %.3f ms, %.1f GB/s" % (pat, ms, g))
         del bseq
         torch.cuda.empty_cache()
+        uneven = uneven_batch(gd, torch, max(3, args.steps // 4))
+    else:
+        uneven = None
+    copy_bw = copy_gbps(torch)
+    log("[bench] device copy %.0f GB/s; random gathers %.3e per s" % (copy_bw, lookup_gather))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -432,6 +533,13 @@ def main():
         "sketch_kernels_ms": sk_kernels,
         "sketch_1Gbp": sketch_1g,
         "location_voting": vote,
+        "uneven_batch_1Gbp": uneven,
+        "measured_copy_GBps": copy_bw,
+        "sketch_frac_of_measured_copy": gbps / copy_bw,
+        "random_gather_per_s": lookup_gather,
+        "lookup_requests_per_query": (roof_next["avg_launch_ms"] * 1e-3 * lookup_gather /
+                                      (s_queries / roof_next["launches_per_step"]))
+        if roof_next["kernel"].startswith("k_lookup") else None,
         "index_records": n_index, "anchors": n_anchors, "lookups_per_step": queries,
         "kernels": per_kernel, "output_sha256_16": digest,
     }

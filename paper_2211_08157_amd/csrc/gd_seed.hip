@@ -46,8 +46,8 @@ __device__ __forceinline__ uint64_t run_end(const uint64_t *keys, uint64_t n, ui
 // aligned.  The lookup is bound by the number of random memory requests, so the leaf is
 // one 16-byte load and the key window [lo - 1, hi] (both brackets included) is read as
 // up to kPairs independent 16-byte loads; both ends come from those keys.  The bracket
-// check keeps the result exact whatever the model holds; a window too wide or a failed
-// check takes the plain searches.
+// check keeps the result exact whatever the model holds; a wider window is searched by
+// bisection after the same check, and a failed check takes the plain searches.
 constexpr int kPairs = 8;
 
 __device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, uint64_t n,
@@ -99,6 +99,18 @@ __device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, 
                 u = hi_eq ? run_end(keys, n, (uint64_t)hi, q) : l + eq;
                 return;
             }
+        } else if (lo <= hi && (lo == 0 || keys[lo - 1] < q) &&
+                   (hi == (int64_t)n || keys[hi] >= q)) {
+            // a wide window (few leaves for many keys): binary search inside it
+            uint64_t a = (uint64_t)lo, len = (uint64_t)(hi - lo);
+            while (len > 0) {
+                const uint64_t half = len >> 1;
+                if (keys[a + half] < q) { a += half + 1; len -= half + 1; }
+                else len = half;
+            }
+            l = a;
+            u = run_end(keys, n, l, q);
+            return;
         }
     }
     l = lower_bound_u64(keys, n, q);
