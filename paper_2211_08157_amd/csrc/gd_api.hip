@@ -163,8 +163,8 @@ void plan_seed_ws(Bump &b, const godiet_seqs *reads, const Pattern &P, int w, ui
     o->occ = b.take<uint32_t>(o->stride * n_shift);
     o->slot = b.take<uint32_t>(nr + 1);
     o->cnt = b.take<uint32_t>(nr + 1);
-    o->long_ids = b.take<uint32_t>(nr + 1);
-    o->long_n = b.take<uint32_t>(1);
+    o->long_ids = b.take<uint32_t>(nr + 1);     // long reads from the front, huge from the back
+    o->long_n = b.take<uint32_t>(2);            // counts of both lists
     o->scan = b.take<uint64_t>(scan_scratch(nr + 1));
 }
 
@@ -213,7 +213,7 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
     A.align_t = opts->align_t;
     A.max_occ = opts->max_occ;
     A.long_records = opts->long_records ? opts->long_records : 192u;
-    A.long_blocks = opts->long_blocks ? opts->long_blocks : 1024u;
+    A.long_blocks = opts->long_blocks ? opts->long_blocks : 4096u;
     GD_TRY(launch_align(A, shift_out, W.slot, W.cnt, W.long_ids, W.long_n, stream));
     return GODIET_OK;
 }

@@ -174,7 +174,8 @@ struct AlignArgs {
     uint32_t long_blocks;    // workgroups of those kernels
 };
 // Shift choice and per-read anchor counts; reads with many records go to long_ids
-// (n_reads entries) for a wave-per-read pass, long_n counts them.
+// (n_reads entries) for a wave-per-read pass (from the front, count long_n[0]), reads with
+// very many to its back for a workgroup-per-read pass (count long_n[1]).
 hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_slot,
                         uint32_t *anchor_cnt, uint32_t *long_ids, uint32_t *long_n, hipStream_t s);
 hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot,

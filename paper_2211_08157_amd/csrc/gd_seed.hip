@@ -151,6 +151,8 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
 }
 
 constexpr int kReadsPerBlock = kBlock / kWave;
+constexpr int kHugeBlock = 1024;            // threads per read on the huge-read path
+constexpr uint64_t kHugeRecords = 16384;    // reads with more records take that path
 // Reads whose minimizer records (summed over the sketched shifts) exceed A.long_records are
 // handled by one wave each; shorter reads by one thread each.
 
@@ -200,7 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_align(AlignArgs A, uint8_t *shift_ou
 {
     const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= A.n_reads) return;
-    if (read_records(A, r) > A.long_records) {
+    const uint64_t recs = read_records(A, r);
+    if (recs > kHugeRecords) {
+        long_ids[A.n_reads - 1 - atomicAdd(long_n + 1, 1u)] = r;
+        return;
+    }
+    if (recs > A.long_records) {
         long_ids[atomicAdd(long_n, 1u)] = r;
         return;
     }
@@ -240,7 +247,16 @@ __global__ __launch_bounds__(kBlock) void k_align_long(AlignArgs A, uint8_t *shi
             for (uint32_t s = 0; s < A.n_shift; s++) {
                 const uint32_t *occ = A.occ + s * A.stride + rec_beg(A, s, r);
                 uint64_t sc = 0;
-                for (uint64_t j = lane; j < nstar; j += kWave) sc += keep_occ(A, occ[j]);
+                for (uint64_t j0 = 0; j0 < nstar; j0 += 4 * kWave) {    // 4 loads in flight
+                    uint32_t v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint64_t j = j0 + (uint64_t)(u * kWave + lane);
+                        v[u] = j < nstar ? occ[j] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) sc += keep_occ(A, v[u]);
+                }
                 sc = wave_sum<uint64_t>(sc);
                 if (sc > best) { best = sc; slot = s; }
             }
@@ -248,7 +264,16 @@ __global__ __launch_bounds__(kBlock) void k_align_long(AlignArgs A, uint8_t *shi
         const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
         const uint32_t *occ = A.occ + slot * A.stride;
         uint64_t cnt = 0;
-        for (uint64_t j = beg + lane; j < end; j += kWave) cnt += keep_occ(A, occ[j]);
+        for (uint64_t j0 = beg; j0 < end; j0 += 4 * kWave) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint64_t j = j0 + (uint64_t)(u * kWave + lane);
+                v[u] = j < end ? occ[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) cnt += keep_occ(A, v[u]);
+        }
         cnt = wave_sum<uint64_t>(cnt);
         if (lane == 0) align_store(A, r, slot, cnt, shift_out, shift_slot, anchor_cnt);
     }
@@ -351,13 +376,21 @@ __global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint3
         const uint32_t *lb = A.lb + slot * A.stride;
         const uint32_t *qv = A.qval + slot * A.stride;
         uint64_t out = read_off[r];
+        // the next chunk's records are loaded before this chunk's gathers and writes
+        uint32_t on = 0, ln = 0, qn = 0;
+        if (beg + lane < end) {
+            on = keep_occ(A, occ[beg + lane]);
+            ln = lb[beg + lane];
+            qn = qv[beg + lane];
+        }
         for (uint64_t j0 = beg; j0 < end; j0 += kWave) {
-            const uint64_t j = j0 + lane;
-            uint32_t o = 0, l = 0, q = 0;
-            if (j < end) {
-                o = keep_occ(A, occ[j]);
-                l = lb[j];
-                q = qv[j];
+            const uint32_t o = on, l = ln, q = qn;
+            const uint64_t jn = j0 + kWave + lane;
+            on = ln = qn = 0;
+            if (jn < end) {
+                on = keep_occ(A, occ[jn]);
+                ln = lb[jn];
+                qn = qv[jn];
             }
             const uint32_t incl = wave_incl_scan<uint32_t>(o);
             const uint64_t at = out + (incl - o);
@@ -366,6 +399,118 @@ __global__ __launch_bounds__(kBlock) void k_expand_long(AlignArgs A, const uint3
                 anchors[at + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
             }
             out += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+}
+
+// Reads with more than kHugeRecords records (the longest ONT reads) take one workgroup
+// of kHugeBlock threads each, so the one or two longest reads of a batch do not leave a
+// single wave working through their records while the rest of the GPU is idle.
+__device__ __forceinline__ uint64_t huge_block_sum(uint64_t v, uint64_t *sh)
+{
+    v = wave_sum<uint64_t>(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kHugeBlock / kWave; i++) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kHugeBlock) void k_align_huge(AlignArgs A, uint8_t *shift_out,
+                                                           uint32_t *shift_slot,
+                                                           uint32_t *anchor_cnt,
+                                                           const uint32_t *long_ids,
+                                                           const uint32_t *long_n)
+{
+    __shared__ uint64_t sh[kHugeBlock / kWave];
+    const uint32_t nh = long_n[1];
+    for (uint32_t hi = blockIdx.x; hi < nh; hi += gridDim.x) {
+        const uint32_t r = long_ids[A.n_reads - 1 - hi];
+        uint32_t slot = 0;
+        if (A.n_shift > 1) {
+            const uint64_t nstar = align_nstar(A, r);
+            uint64_t best = 0;
+            for (uint32_t s = 0; s < A.n_shift; s++) {
+                const uint32_t *occ = A.occ + s * A.stride + rec_beg(A, s, r);
+                uint64_t sc = 0;
+                for (uint64_t j0 = 0; j0 < nstar; j0 += 4 * kHugeBlock) {
+                    uint32_t v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint64_t j = j0 + (uint64_t)(u * kHugeBlock + threadIdx.x);
+                        v[u] = j < nstar ? occ[j] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) sc += keep_occ(A, v[u]);
+                }
+                sc = huge_block_sum(sc, sh);
+                if (sc > best) { best = sc; slot = s; }
+            }
+        }
+        const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
+        const uint32_t *occ = A.occ + slot * A.stride;
+        uint64_t cnt = 0;
+        for (uint64_t j0 = beg; j0 < end; j0 += 4 * kHugeBlock) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint64_t j = j0 + (uint64_t)(u * kHugeBlock + threadIdx.x);
+                v[u] = j < end ? occ[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) cnt += keep_occ(A, v[u]);
+        }
+        cnt = huge_block_sum(cnt, sh);
+        if (threadIdx.x == 0) align_store(A, r, slot, cnt, shift_out, shift_slot, anchor_cnt);
+    }
+}
+
+__global__ __launch_bounds__(kHugeBlock) void k_expand_huge(AlignArgs A, const uint32_t *shift_slot,
+                                                            const uint64_t *read_off,
+                                                            const uint32_t *ivals, uint4 *anchors,
+                                                            uint64_t capacity,
+                                                            const uint32_t *long_ids,
+                                                            const uint32_t *long_n)
+{
+    __shared__ uint32_t sh[kHugeBlock / kWave];
+    if (read_off[A.n_reads] > capacity) return;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint32_t nh = long_n[1];
+    for (uint32_t hi = blockIdx.x; hi < nh; hi += gridDim.x) {
+        const uint32_t r = long_ids[A.n_reads - 1 - hi];
+        const uint32_t slot = shift_slot[r];
+        const uint64_t beg = rec_beg(A, slot, r), end = rec_beg(A, slot, r + 1);
+        const uint32_t *occ = A.occ + slot * A.stride;
+        const uint32_t *lb = A.lb + slot * A.stride;
+        const uint32_t *qv = A.qval + slot * A.stride;
+        uint64_t out = read_off[r];
+        for (uint64_t j0 = beg; j0 < end; j0 += kHugeBlock) {
+            const uint64_t j = j0 + threadIdx.x;
+            uint32_t o = 0, l = 0, q = 0;
+            if (j < end) {
+                o = keep_occ(A, occ[j]);
+                l = lb[j];
+                q = qv[j];
+            }
+            const uint32_t incl = wave_incl_scan<uint32_t>(o);
+            if (lane == kWave - 1) sh[wv] = incl;
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int i = 0; i < kHugeBlock / kWave; i++) {
+                const uint32_t c = sh[i];
+                before += i < wv ? c : 0u;
+                total += c;
+            }
+            __syncthreads();
+            const uint64_t at = out + before + (incl - o);
+            for (uint32_t e = 0; e < o; e++) {
+                const uint32_t v = ivals[l + e];
+                anchors[at + e] = make_uint4(r, q >> 1, v >> 1, (q ^ v) & 1u);
+            }
+            out += total;
         }
     }
 }
@@ -399,11 +544,13 @@ hipError_t launch_align(const AlignArgs &a, uint8_t *shift_out, uint32_t *shift_
                         uint32_t *anchor_cnt, uint32_t *long_ids, uint32_t *long_n, hipStream_t s)
 {
     if (a.n_reads == 0) return hipSuccess;
-    hipError_t e = fill_u32(long_n, 0, 1, s);
+    hipError_t e = fill_u32(long_n, 0, 2, s);
     if (e != hipSuccess) return e;
     const unsigned blocks = (a.n_reads + kBlock - 1) / kBlock;
     GD_LAUNCH(k_align, dim3(blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot, anchor_cnt,
               long_ids, long_n);
+    GD_LAUNCH(k_align_huge, dim3(64), dim3(kHugeBlock), 0, s, a, shift_out, shift_slot,
+              anchor_cnt, (const uint32_t *)long_ids, (const uint32_t *)long_n);
     GD_LAUNCH(k_align_long, dim3(a.long_blocks), dim3(kBlock), 0, s, a, shift_out, shift_slot,
               anchor_cnt,
               (const uint32_t *)long_ids, (const uint32_t *)long_n);
@@ -420,6 +567,8 @@ hipError_t launch_expand(const AlignArgs &a, const uint32_t *shift_slot, const u
     GD_LAUNCH(k_expand, dim3(blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
               (const uint32_t *)ivals, (uint4 *)anchors, capacity, status);
     GD_LAUNCH(k_expand_long, dim3(a.long_blocks), dim3(kBlock), 0, s, a, shift_slot, read_off,
+              (const uint32_t *)ivals, (uint4 *)anchors, capacity, long_ids, long_n);
+    GD_LAUNCH(k_expand_huge, dim3(64), dim3(kHugeBlock), 0, s, a, shift_slot, read_off,
               (const uint32_t *)ivals, (uint4 *)anchors, capacity, long_ids, long_n);
     return hipGetLastError();
 }

@@ -90,3 +90,16 @@ def test_autotune_candidates_agree(gpu, mixed, tmp_path):
     a, _, _ = gpu.seed(ix, reads, PAT, K, W, tuning=best)
     ea, _, _ = oracle.seed(ek, ev, codes, offs, PAT, K, W)
     assert np.array_equal(u32(a).reshape(-1, 4), ea)
+
+
+def test_batch_with_huge_reads_matches_oracle(gpu, mixed):
+    # reads above 16,384 minimizer records take the workgroup-per-read path
+    ref, ix, ek, ev, classes, codes, offs = mixed
+    huge = datagen.variable_reads(ref, [400_000, 150, 250_000, 30_000, 150], 66, 0.01, 0.005,
+                                  0.005)
+    hc, ho = datagen.concat([classes[0], huge[:2]])
+    a, off, sh = gpu.seed(ix, gpu.to_device(hc, ho), PAT, K, W)
+    ea, eoff, esh = oracle.seed(ek, ev, hc, ho, PAT, K, W)
+    assert np.array_equal(u32(a).reshape(-1, 4), ea)
+    assert np.array_equal(off.cpu().numpy().view(np.uint64), eoff)
+    assert np.array_equal(sh.cpu().numpy().astype(np.uint32), esh)
