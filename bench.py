@@ -37,8 +37,8 @@ OPS_PER_KMER = 4 + 3 + 17 + 18
 # HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
 # kernel source; reported only while that source is unchanged.
 MEASURED_TRAFFIC = {
-    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="f9d3abf5f521625e",
-                         bytes_per_step=428.3e6,
+    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="061092b11b5dbc95",
+                         bytes_per_step=427.6e6,
                          summary="profiles/k_sketch_illumina-100Mbp_hbm_bytes.md"),
 }
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
@@ -539,7 +539,7 @@ def main():
         "random_gather_per_s": lookup_gather,
         "lookup_requests_per_query": (roof_next["avg_launch_ms"] * 1e-3 * lookup_gather /
                                       (s_queries / roof_next["launches_per_step"]))
-        if roof_next["kernel"].startswith("k_lookup") else None,
+        if roof_next and roof_next.get("kernel", "").startswith("k_lookup") else None,
         "index_records": n_index, "anchors": n_anchors, "lookups_per_step": queries,
         "kernels": per_kernel, "output_sha256_16": digest,
     }
