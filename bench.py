@@ -37,8 +37,8 @@ OPS_PER_KMER = 4 + 3 + 17 + 18
 # HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
 # kernel source; reported only while that source is unchanged.
 MEASURED_TRAFFIC = {
-    "k_sketch<11>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="061092b11b5dbc95",
-                         bytes_per_step=427.6e6,
+    "k_sketch<11,0>": dict(src="paper_2211_08157_amd/csrc/gd_sketch.hip",
+                           sha256_16="b2ef021c023a4fed", bytes_per_step=427.9e6,
                          summary="profiles/k_sketch_illumina-100Mbp_hbm_bytes.md"),
 }
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"

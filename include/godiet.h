@@ -89,6 +89,10 @@ typedef struct {
     const char *pattern;      /* [host] NUL-terminated '0'/'1' string, 1..64 chars, >= one '1' */
     int32_t k;                /* 1..32 */
     int32_t w;                /* 1..256 */
+    int32_t hash;             /* k-mer hash: 0 = splitmix64 finalizer (default); 1 = Thomas
+                                 Wang's 64-bit integer hash with every step masked to 2k bits
+                                 (the paper's hash, Section 3.6.1, in minimap2's form).  An
+                                 index and the reads seeded against it must use the same. */
 } godiet_sketch_params;
 
 /* A sorted seed index as produced by godiet_index_build.  val_bits 32: vals is uint32

@@ -70,6 +70,10 @@ def lib():
         L.gdo_contain.restype = i64
         L.gdo_vote.argtypes = [P, P, u32, u32, u32, u32, P, P]
         L.gdo_vote.restype = i64
+        L.gdo_wang64.argtypes = [u64, i32]
+        L.gdo_wang64.restype = u64
+        L.gdo_set_hash.argtypes = [i32]
+        L.gdo_set_hash.restype = i32
         _lib = L
     return _lib
 
@@ -198,3 +202,23 @@ def vote(anchors, read_off, max_dist, min_votes, max_win):
     _check(lib().gdo_vote(_ptr(a), _ptr(off), n_reads, int(max_dist), int(min_votes),
                           int(max_win), _ptr(out), _ptr(nw)), "vote")
     return out[:n_reads], nw[:n_reads]
+
+
+def wang64(key, k):
+    return int(lib().gdo_wang64(int(key) & (2**64 - 1), int(k)))
+
+
+class use_hash:
+    """Context manager selecting the k-mer hash of the oracle's sketches:
+    with oracle.use_hash("wang"): ..."""
+
+    def __init__(self, name):
+        self.kind = {"splitmix64": 0, "wang": 1}[name]
+
+    def __enter__(self):
+        _check(lib().gdo_set_hash(self.kind), "set_hash")
+        return self
+
+    def __exit__(self, *exc):
+        lib().gdo_set_hash(0)
+        return False

@@ -19,8 +19,9 @@
  * design notes of the repository):
  *   - pattern phase for reads: base j is kept iff P[(j - a) mod p] == 1 (cyclic form of
  *     the set {Q[i+a] * P[i mod p]} of Section 3);
- *   - hash: splitmix64 finalizer of the canonical 2k-bit code (the paper uses Thomas
- *     Wang's hash, Section 3.6.1; the workloads fix splitmix64);
+ *   - hash: splitmix64 finalizer of the canonical 2k-bit code (the workloads fix it), or
+ *     Thomas Wang's hash masked to 2k bits (the paper's, Section 3.6.1) after
+ *     gdo_set_hash(1);
  *   - window ties: every k-mer attaining a window minimum is a minimizer;
  *   - only full windows of w k-mers count; palindromic k-mers (fwd == rc) are never
  *     minimizers and never lower a window minimum;
@@ -77,6 +78,34 @@ uint64_t gdo_mix64(uint64_t z)
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
     return z ^ (z >> 31);
+}
+
+/* Thomas Wang's 64-bit integer hash (his integer-hash note; the k-mer hash of Section
+ * 3.6.1), with every step reduced to the 2k-bit code space as minimap2 applies it to k-mer
+ * codes.  Steps: key = ~key + key*2^21; key ^= key >> 24; key *= 265; key ^= key >> 14;
+ * key *= 21; key ^= key >> 28; key *= 2^31 + 1, each result taken mod 2^(2k). */
+uint64_t gdo_wang64(uint64_t key, int k)
+{
+    const uint64_t mask = k >= 32 ? ~0ULL : ((1ULL << (2 * k)) - 1);
+    key = (~key + (key << 21)) & mask;
+    key = key ^ (key >> 24);
+    key = (key * 265u) & mask;
+    key = key ^ (key >> 14);
+    key = (key * 21u) & mask;
+    key = key ^ (key >> 28);
+    key = (key * ((1ULL << 31) + 1)) & mask;
+    return key;
+}
+
+/* Which k-mer hash the sketches use: 0 splitmix64 finalizer, 1 Wang's hash (set before
+ * the calls; a test-infrastructure switch, not thread-safe). */
+static int g_hash = 0;
+
+int gdo_set_hash(int kind)
+{
+    if (kind != 0 && kind != 1) return GDO_EINVAL;
+    g_hash = kind;
+    return GDO_OK;
 }
 
 /* Number of kept bases of a sequence of length L under shift a, counted by definition. */
@@ -155,7 +184,7 @@ static int64_t sketch_one(const uint8_t *S, uint64_t L, const gdo_pattern *P, ui
             if (fwd == rc) { ok[i] = 0; h[i] = 0; strand[i] = 0; continue; }
             ok[i] = 1;
             strand[i] = rc < fwd ? 1 : 0;
-            h[i] = gdo_mix64(rc < fwd ? rc : fwd);
+            h[i] = g_hash ? gdo_wang64(rc < fwd ? rc : fwd, k) : gdo_mix64(rc < fwd ? rc : fwd);
         }
         for (uint64_t s = 0; s < nwin; s++) {
             wany[s] = 0;

@@ -26,7 +26,11 @@ class Seqs(ctypes.Structure):
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("pattern", ctypes.c_char_p), ("k", ctypes.c_int32), ("w", ctypes.c_int32)]
+    _fields_ = [("pattern", ctypes.c_char_p), ("k", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("hash", ctypes.c_int32)]
+
+
+HASHES = {"splitmix64": 0, "wang": 1}
 
 
 class Index(ctypes.Structure):
@@ -180,8 +184,10 @@ def to_device(codes, offsets, device="cuda"):
     return DeviceSeqs(b, o, offs.size - 1, int(offs[-1]))
 
 
-def _params(pattern, k, w):
-    return Params(pattern.encode(), int(k), int(w))
+def _params(pattern, k, w, hash="splitmix64"):
+    if hash not in HASHES:
+        raise ValueError("hash must be one of %s" % sorted(HASHES))
+    return Params(pattern.encode(), int(k), int(w), HASHES[hash])
 
 
 def workspace_size(op, seqs, pattern, k, w, n_index=0):
@@ -223,13 +229,13 @@ def sparsify(seqs, pattern, shift=None):
     return out, offs
 
 
-def sketch(seqs, pattern, k, w, shift=None, capacity=None):
+def sketch(seqs, pattern, k, w, shift=None, capacity=None, hash="splitmix64"):
     """Minimizers of every sequence.  Returns (keys int64 tensor holding uint64 bits,
     vals int32 tensor holding uint32 pos<<1|strand, mz_offsets int64 tensor)."""
     torch = _torch()
     s = seqs.c()
     L = lib()
-    prm = _params(pattern, k, w)
+    prm = _params(pattern, k, w, hash)
     if capacity is None:
         capacity = max(1024, int(kept_bound(seqs, pattern) * 2.2 / (w + 1)) + 4096)
     sh = None if shift is None else torch.as_tensor(np.asarray(shift, np.uint32).view(np.int32),
@@ -322,11 +328,11 @@ def lookup(index, queries):
     return lb[:n], occ[:n]
 
 
-def index_build(ref, pattern, k, w, val_bits=32, capacity=None):
+def index_build(ref, pattern, k, w, val_bits=32, capacity=None, hash="splitmix64"):
     torch = _torch()
     s = ref.c()
     L = lib()
-    prm = _params(pattern, k, w)
+    prm = _params(pattern, k, w, hash)
     if capacity is None:
         capacity = max(1024, int(kept_bound(ref, pattern) * 2.2 / (w + 1)) + 4096)
     st = _empty(1, torch.int32)
@@ -349,13 +355,13 @@ def index_build(ref, pattern, k, w, val_bits=32, capacity=None):
 
 
 def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capacity=None,
-         tuning=None):
+         tuning=None, hash="splitmix64"):
     """Pattern alignment + compressed seeding.  Returns (anchors int32 tensor (n, 4) of
     read_id, qpos, rpos, strand; read_anchor_off int64 tensor; shift uint8 tensor)."""
     torch = _torch()
     s = reads.c()
     L = lib()
-    prm = _params(pattern, k, w)
+    prm = _params(pattern, k, w, hash)
     ix = index.c()
     t = tuning or {}
     opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), int(t.get("long_records", 0)),
@@ -379,13 +385,14 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capac
         return anchors[:4 * n].view(n, 4), off, shift[:reads.n_seq]
 
 
-def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, max_occ=0):
+def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, max_occ=0,
+            hash="splitmix64"):
     """Per-genome shared distinct minimizer counts against a 64-bit-val (genome id) index.
     Returns (counts, sizes) int32 tensors (uint32 bits)."""
     torch = _torch()
     s = reads.c()
     L = lib()
-    prm = _params(pattern, k, w)
+    prm = _params(pattern, k, w, hash)
     ix = index.c()
     opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), 0, 0, 0)
     ws = _empty(workspace_size(OP_CONTAIN, reads, pattern, k, w, index.n), torch.uint8)

@@ -36,7 +36,8 @@ bool valid_seqs(const godiet_seqs *q)
 bool valid_params(const godiet_sketch_params *prm, Pattern *P)
 {
     if (!prm || !parse_pattern(prm->pattern, P)) return false;
-    return prm->k >= 1 && prm->k <= 32 && prm->w >= 1 && prm->w <= 256;
+    return prm->k >= 1 && prm->k <= 32 && prm->w >= 1 && prm->w <= 256 &&
+           (prm->hash == 0 || prm->hash == 1);
 }
 
 uint64_t kept_bound(const godiet_seqs *q, const Pattern &P)
@@ -196,7 +197,7 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         uint32_t *qv = W.qvals + si * W.stride;
         SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
-                             prm->w, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
+                             prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
                              W.occ + si * W.stride, index->rmi, index->table,
                              opts->lookup_blocks, stream));
@@ -332,7 +333,7 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, status, stream));
     SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
-    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, npb, prm->k, prm->w, o, W.tiles,
+    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, npb, prm->k, prm->w, prm->hash, o, W.tiles,
                          W.counter, W.lohi, status, stream));
     return GODIET_OK;
 }
@@ -357,7 +358,7 @@ godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_par
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));
     SketchOut o{keys, vals, val_bits == 32 ? VAL_GLOBAL32 : VAL_SEQ64, nullptr, capacity, n_out};
-    GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, npb, prm->k, prm->w, o,
+    GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, npb, prm->k, prm->w, prm->hash, o,
                          W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
     if (capacity > 0) GD_TRY(launch_sort(W.sp, W.so, keys, vals, vb, n_out, capacity, stream));
     return GODIET_OK;

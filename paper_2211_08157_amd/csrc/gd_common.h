@@ -24,6 +24,29 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// Thomas Wang's 64-bit integer hash restricted to the 2k-bit code space (each step masked
+// to 2k bits, as minimap2 applies it to k-mer codes): the paper's k-mer hash (Section
+// 3.6.1).  Every step is invertible on the masked space, so it permutes the codes.
+__device__ __forceinline__ uint64_t wang64(uint64_t key, uint64_t mask)
+{
+    key = (~key + (key << 21)) & mask;
+    key = key ^ (key >> 24);
+    key = ((key + (key << 3)) + (key << 8)) & mask;
+    key = key ^ (key >> 14);
+    key = ((key + (key << 2)) + (key << 4)) & mask;
+    key = key ^ (key >> 28);
+    key = (key + (key << 31)) & mask;
+    return key;
+}
+
+// k-mer hash of a canonical code: kHash 0 = splitmix64 finalizer, 1 = Thomas Wang's hash.
+template <int kHash>
+__device__ __forceinline__ uint64_t kmer_hash(uint64_t code, uint64_t mask)
+{
+    if constexpr (kHash == 1) return wang64(code, mask);
+    else return mix64(code);
+}
+
 // Pattern rotated right by a: bit t set iff P[(t - a) mod p] == '1'.
 __host__ __device__ __forceinline__ uint64_t rotated_mask(const Pattern &P, uint32_t a)
 {

@@ -100,7 +100,7 @@ struct SketchOut {
 size_t sketch_tiles_bound(uint64_t np_bound, int w);
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
-                         uint64_t np_bound, int k, int w, const SketchOut &o,
+                         uint64_t np_bound, int k, int w, int hash, const SketchOut &o,
                          uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
                          uint32_t *status, hipStream_t s);
 

@@ -507,7 +507,7 @@ __device__ uint32_t select_lds(const uint64_t (&v)[16], uint32_t selm, uint32_t 
 }
 
 // One tile: the T positions [tile*T, tile*T + T) of the batch's patterned stream.
-template <int W>
+template <int W, int HK>
 __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
                                             uint64_t n_tiles, uint64_t *ex, uint64_t *sh_scan,
                                             uint64_t *sh_base_p, const SeqCache &C)
@@ -549,7 +549,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t rc = (~X) & A.kmask;
                 const uint64_t fwd = F >> fsh;
                 const bool strand = rc < fwd;
-                hv[u] = mix64(strand ? rc : fwd);
+                hv[u] = kmer_hash<HK>(strand ? rc : fwd, A.kmask);
                 smask |= (strand ? 1u : 0u) << u;
             }
         } else if (interior) {
@@ -561,7 +561,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t rc = (~X) & A.kmask;
                 const uint64_t fwd = F >> fsh;
                 const bool strand = rc < fwd;
-                const uint64_t h = mix64(strand ? rc : fwd);
+                const uint64_t h = kmer_hash<HK>(strand ? rc : fwd, A.kmask);
                 const bool pal = fwd == rc;
                 hv[u] = pal ? kMax64 : h;
                 selm |= (pal ? 0u : 1u) << u;
@@ -598,7 +598,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 const uint64_t rc = (~X) & A.kmask;
                 const uint64_t fwd = F >> fsh;
                 const bool strand = rc < fwd;
-                const uint64_t h = mix64(strand ? rc : fwd);
+                const uint64_t h = kmer_hash<HK>(strand ? rc : fwd, A.kmask);
                 const bool use = ((kv >> u) & 1u) && !((k & 1) == 0 && fwd == rc);
                 hv[u] = use ? h : kMax64;
                 selm |= (use ? 1u : 0u) << u;
@@ -727,7 +727,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
     }
 }
 
-template <int W>
+template <int W, int HK>
 __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
 {
     __shared__ uint64_t ex[kE];       // neighbour exchange / sliding-reduction work array
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
     const SeqCache C = seq_cache(A.pofs, A.n_seq, A.lohi, tile, sh_pofs);
-    sketch_tile<W>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C);
+    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C);
 }
 
 }  // namespace
@@ -781,7 +781,7 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
 
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
-                         uint64_t np_bound, int k, int w, const SketchOut &o,
+                         uint64_t np_bound, int k, int w, int hash, const SketchOut &o,
                          uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
                          uint32_t *status, hipStream_t s)
 {
@@ -821,11 +821,18 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     A.inv_x = 1.0 / (double)P.x;
     const size_t grid = tiles;
     switch (w) {
-#define GD_W(n) case n: GD_LAUNCH(k_sketch<n>, dim3((unsigned)grid), dim3(kBlock), 0, s, A); break;
+#define GD_W(n)                                                                             \
+    case n:                                                                                 \
+        if (hash == 1) GD_LAUNCH((k_sketch<n, 1>), dim3((unsigned)grid), dim3(kBlock), 0, s, A); \
+        else GD_LAUNCH((k_sketch<n, 0>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);          \
+        break;
         GD_W(2) GD_W(3) GD_W(4) GD_W(5) GD_W(6) GD_W(7) GD_W(8) GD_W(9) GD_W(10) GD_W(11)
         GD_W(12) GD_W(13) GD_W(14) GD_W(15) GD_W(16) GD_W(17)
 #undef GD_W
-    default: GD_LAUNCH(k_sketch<0>, dim3((unsigned)grid), dim3(kBlock), 0, s, A); break;
+    default:
+        if (hash == 1) GD_LAUNCH((k_sketch<0, 1>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
+        else GD_LAUNCH((k_sketch<0, 0>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
+        break;
     }
     return hipGetLastError();
 }

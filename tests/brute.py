@@ -15,6 +15,20 @@ def mix64(z):
     return z ^ (z >> 31)
 
 
+def wang64(key, k):
+    # Thomas Wang's 64-bit integer hash in its published shift-and-add form, each step
+    # reduced to the 2k-bit code space (the oracle writes the same steps as products)
+    m = (1 << (2 * k)) - 1 if k < 32 else MASK
+    key = ((~key & MASK) + (key << 21)) & m
+    key = key ^ (key >> 24)
+    key = ((key + (key << 3)) + (key << 8)) & m
+    key = key ^ (key >> 14)
+    key = ((key + (key << 2)) + (key << 4)) & m
+    key = key ^ (key >> 28)
+    key = (key + (key << 31)) & m
+    return key
+
+
 def kept_positions(length, pattern, shift):
     p = len(pattern)
     return [j for j in range(length) if pattern[(j - shift) % p] == "1"]
@@ -24,8 +38,9 @@ def numeral(bases):
     return int("".join("0123"[b] for b in bases), 4) if bases else 0
 
 
-def sketch(seq, pattern, shift, k, w):
+def sketch(seq, pattern, shift, k, w, hash="splitmix64"):
     """List of (key, val = orig << 1 | strand) in ascending k-mer order."""
+    hf = (lambda c: wang64(c, k)) if hash == "wang" else mix64
     kept = kept_positions(len(seq), pattern, shift)
     ps = [int(seq[j]) for j in kept]
     ent = []
@@ -33,7 +48,7 @@ def sketch(seq, pattern, shift, k, w):
         kmer = ps[i:i + k]
         f = numeral(kmer)
         r = numeral([3 - b for b in reversed(kmer)])
-        ent.append(None if f == r else (mix64(min(f, r)), 1 if r < f else 0))
+        ent.append(None if f == r else (hf(min(f, r)), 1 if r < f else 0))
     chosen = set()
     for s in range(len(ent) - w + 1):
         hs = [e[0] for e in ent[s:s + w] if e is not None]

@@ -60,6 +60,9 @@ MUTANTS = [
      "if (c.votes >= rescue.votes) rescue = c;"),
     ("winners by ascending votes", "if (a->votes != b->votes) return a->votes > b->votes ? -1 : 1;",
      "if (a->votes != b->votes) return a->votes < b->votes ? -1 : 1;"),
+    ("Wang hash multiplier", "key = (key * 265u) & mask;", "key = (key * 273u) & mask;"),
+    ("Wang hash first step unmasked", "key = (~key + (key << 21)) & mask;",
+     "key = (~key + (key << 21));"),
     ("containment counts every genome hash",
      "if (bsearch(&gh[i].val, sample, (size_t)nu, sizeof(uint64_t), u64_cmp)) counts[g]++;",
      "if (1) counts[g]++;"),

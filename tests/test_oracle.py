@@ -469,3 +469,32 @@ def test_vote_ignores_anchor_order_and_counts_exact_reads():
     perm = a[rng.permutation(len(rows))]
     out2, nw2 = oracle.vote(perm, off, 8, 3, 4)
     assert np.array_equal(out, out2) and np.array_equal(nw, nw2)
+
+
+# ---------------------------------------------------------------- Wang's hash (paper form)
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_wang_hash_permutes_the_code_space(k):
+    n = 4 ** k
+    out = {oracle.wang64(x, k) for x in range(n)}
+    assert out == set(range(n))
+
+
+def test_wang_hash_matches_the_shift_and_add_form():
+    rng = np.random.default_rng(5)
+    for k in (4, 11, 15, 21, 31, 32):
+        for x in rng.integers(0, 4 ** k if k < 32 else 2**63, 200, dtype=np.uint64):
+            assert oracle.wang64(int(x), k) == brute.wang64(int(x), k)
+
+
+@pytest.mark.parametrize("pattern,k,w", [("10", 5, 4), ("110", 4, 3), ("1", 7, 5), ("101001", 3, 6)])
+def test_wang_sketch_matches_brute_force(pattern, k, w):
+    rng = np.random.default_rng(len(pattern) * 7 + k)
+    for _ in range(20):
+        seq = rng.integers(0, 4, int(rng.integers(0, 90)), dtype=np.uint8)
+        for shift in range(len(pattern)):
+            with oracle.use_hash("wang"):
+                keys, vals, _ = oracle.sketch(seq, one(seq), pattern, k, w,
+                                              shifts=np.array([shift], np.uint32))
+            want = brute.sketch(list(seq), pattern, shift, k, w, hash="wang")
+            assert list(zip(keys.tolist(), vals.tolist())) == want
