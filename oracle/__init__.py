@@ -85,8 +85,8 @@ def _ptr(a):
 def _codes(codes, offsets):
     codes = np.ascontiguousarray(codes, dtype=np.uint8)
     offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
-    if codes.size and codes.max() > 3:
-        raise ValueError("base codes must be 0..3")
+    if codes.size and codes.max() > 4:
+        raise ValueError("base codes must be 0..3, or 4 for the ambiguous base N")
     return codes, offsets
 
 

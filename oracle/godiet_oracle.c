@@ -11,7 +11,8 @@
  * blocking, fusion or reordering: sequences are handled one at a time, k-mer codes are
  * recomputed from their k bases, window minima are recomputed from their w members.
  *
- * Inputs are bases as one code per byte (A=0, C=1, G=2, T=3) plus n_seq+1 offsets.
+ * Inputs are bases as one code per byte (A=0, C=1, G=2, T=3, and 4 for the ambiguous
+ * base N) plus n_seq+1 offsets.
  * Positions stored in minimizer records are coordinates of the ORIGINAL (unpatterned)
  * sequence (Section 3.1, step 3).
  *
@@ -145,15 +146,73 @@ int64_t gdo_sparsify(const uint8_t *codes, const uint64_t *offsets, uint32_t n_s
     return (int64_t)n;
 }
 
-/* Minimizers of one sequence (Section 3.1 step (3) and its minimizer definition):
- *   1. sparsify with shift a, remembering the original coordinate of each kept base;
- *   2. for every k-mer of the patterned sequence: forward code (first base most
- *      significant), reverse-complement code, canonical = smaller, strand = rc < fwd,
- *      hash = mix64(canonical);
+/* Steps 2-3 of the sketch on one run of patterned bases PS[0..n) with no ambiguous base:
+ *   2. for every k-mer: forward code (first base most significant), reverse-complement
+ *      code, canonical = smaller, strand = rc < fwd, hash = mix64(canonical) (or Wang's);
  *   3. a k-mer is a minimizer iff its hash equals the minimum of some full window of w
  *      consecutive k-mers containing it.
- * Records are (key = hash, val = orig << 1 | strand) in ascending k-mer order.
- * Returns the number of records, or GDO_ECAP if more than cap would be written. */
+ * Records (key = hash, val = orig << 1 | strand) are appended in ascending k-mer order.
+ * Returns the number of records, GDO_ECAP if more than cap would be written. */
+static int64_t sketch_run(const uint8_t *PS, const uint64_t *orig, uint64_t n, int k, int w,
+                          uint64_t *keys, uint64_t *vals, uint64_t cap)
+{
+    int64_t out = 0;
+    if (n < (uint64_t)k || n - (uint64_t)k + 1 < (uint64_t)w) return 0;
+    uint64_t nk = n - (uint64_t)k + 1;
+    uint64_t *h = (uint64_t *)malloc(nk * sizeof(uint64_t));
+    uint8_t *ok = (uint8_t *)malloc(nk);
+    uint8_t *strand = (uint8_t *)malloc(nk);
+    uint64_t nwin = nk - (uint64_t)w + 1;
+    uint64_t *wmin = (uint64_t *)malloc(nwin * sizeof(uint64_t));
+    uint8_t *wany = (uint8_t *)malloc(nwin);
+    if (!h || !ok || !strand || !wmin || !wany) {
+        free(h); free(ok); free(strand); free(wmin); free(wany);
+        return GDO_ENOMEM;
+    }
+    for (uint64_t i = 0; i < nk; i++) {
+        uint64_t fwd = 0, rc = 0;
+        for (int t = 0; t < k; t++) fwd = fwd * 4 + PS[i + t];
+        for (int t = 0; t < k; t++) rc = rc * 4 + (uint64_t)(3 - PS[i + (uint64_t)k - 1 - t]);
+        if (fwd == rc) { ok[i] = 0; h[i] = 0; strand[i] = 0; continue; }
+        ok[i] = 1;
+        strand[i] = rc < fwd ? 1 : 0;
+        h[i] = g_hash ? gdo_wang64(rc < fwd ? rc : fwd, k) : gdo_mix64(rc < fwd ? rc : fwd);
+    }
+    for (uint64_t s = 0; s < nwin; s++) {
+        wany[s] = 0;
+        wmin[s] = 0;
+        for (uint64_t t = s; t < s + (uint64_t)w; t++) {
+            if (!ok[t]) continue;
+            if (!wany[s] || h[t] < wmin[s]) wmin[s] = h[t];
+            wany[s] = 1;
+        }
+    }
+    for (uint64_t i = 0; i < nk; i++) {
+        if (!ok[i]) continue;
+        uint64_t s_lo = i + 1 >= (uint64_t)w ? i + 1 - (uint64_t)w : 0;
+        uint64_t s_hi = i < nwin - 1 ? i : nwin - 1;
+        int sel = 0;
+        for (uint64_t s = s_lo; s <= s_hi; s++)
+            if (wany[s] && h[i] == wmin[s]) { sel = 1; break; }
+        if (!sel) continue;
+        if ((uint64_t)out >= cap) { out = GDO_ECAP; break; }
+        keys[out] = h[i];
+        vals[out] = (orig[i] << 1) | strand[i];
+        out++;
+    }
+    free(h); free(ok); free(strand); free(wmin); free(wany);
+    return out;
+}
+
+/* Minimizers of one sequence (Section 3.1 step (3) and its minimizer definition):
+ *   1. sparsify with shift a, remembering the original coordinate of each kept base;
+ *   1b. an ambiguous base (code 4, N) among the kept bases ends the current run of
+ *      patterned bases and the next run starts right after it (Section 3.6.1): every run
+ *      is sketched on its own, so no k-mer and no window contains an N or spans one.
+ *      An N at a dropped position is dropped with it and splits nothing;
+ *   2-3. each run as in sketch_run.
+ * Records are in ascending k-mer order.  Returns the number of records, or GDO_ECAP if
+ * more than cap would be written. */
 static int64_t sketch_one(const uint8_t *S, uint64_t L, const gdo_pattern *P, uint32_t a,
                           int k, int w, uint64_t *keys, uint64_t *vals, uint64_t cap)
 {
@@ -165,50 +224,14 @@ static int64_t sketch_one(const uint8_t *S, uint64_t L, const gdo_pattern *P, ui
         if (is_kept(P, j, a)) { PS[n] = S[j]; orig[n] = j; n++; }
 
     int64_t out = 0;
-    if (n >= (uint64_t)k && n - (uint64_t)k + 1 >= (uint64_t)w) {
-        uint64_t nk = n - (uint64_t)k + 1;
-        uint64_t *h = (uint64_t *)malloc(nk * sizeof(uint64_t));
-        uint8_t *ok = (uint8_t *)malloc(nk);
-        uint8_t *strand = (uint8_t *)malloc(nk);
-        uint64_t nwin = nk - (uint64_t)w + 1;
-        uint64_t *wmin = (uint64_t *)malloc(nwin * sizeof(uint64_t));
-        uint8_t *wany = (uint8_t *)malloc(nwin);
-        if (!h || !ok || !strand || !wmin || !wany) {
-            free(h); free(ok); free(strand); free(wmin); free(wany); free(PS); free(orig);
-            return GDO_ENOMEM;
-        }
-        for (uint64_t i = 0; i < nk; i++) {
-            uint64_t fwd = 0, rc = 0;
-            for (int t = 0; t < k; t++) fwd = fwd * 4 + PS[i + t];
-            for (int t = 0; t < k; t++) rc = rc * 4 + (uint64_t)(3 - PS[i + (uint64_t)k - 1 - t]);
-            if (fwd == rc) { ok[i] = 0; h[i] = 0; strand[i] = 0; continue; }
-            ok[i] = 1;
-            strand[i] = rc < fwd ? 1 : 0;
-            h[i] = g_hash ? gdo_wang64(rc < fwd ? rc : fwd, k) : gdo_mix64(rc < fwd ? rc : fwd);
-        }
-        for (uint64_t s = 0; s < nwin; s++) {
-            wany[s] = 0;
-            wmin[s] = 0;
-            for (uint64_t t = s; t < s + (uint64_t)w; t++) {
-                if (!ok[t]) continue;
-                if (!wany[s] || h[t] < wmin[s]) wmin[s] = h[t];
-                wany[s] = 1;
-            }
-        }
-        for (uint64_t i = 0; i < nk; i++) {
-            if (!ok[i]) continue;
-            uint64_t s_lo = i + 1 >= (uint64_t)w ? i + 1 - (uint64_t)w : 0;
-            uint64_t s_hi = i < nwin - 1 ? i : nwin - 1;
-            int sel = 0;
-            for (uint64_t s = s_lo; s <= s_hi; s++)
-                if (wany[s] && h[i] == wmin[s]) { sel = 1; break; }
-            if (!sel) continue;
-            if ((uint64_t)out >= cap) { out = GDO_ECAP; break; }
-            keys[out] = h[i];
-            vals[out] = (orig[i] << 1) | strand[i];
-            out++;
-        }
-        free(h); free(ok); free(strand); free(wmin); free(wany);
+    uint64_t r0 = 0;                        /* start of the current run */
+    for (uint64_t i = 0; i <= n; i++) {
+        if (i < n && PS[i] != 4) continue;
+        int64_t r = sketch_run(PS + r0, orig + r0, i - r0, k, w, keys + out, vals + out,
+                               cap - (uint64_t)out);
+        if (r < 0) { out = r; break; }
+        out += r;
+        r0 = i + 1;
     }
     free(PS);
     free(orig);

@@ -15,6 +15,9 @@ def mix64(z):
     return z ^ (z >> 31)
 
 
+N = 4                                      # code of the ambiguous base
+
+
 def wang64(key, k):
     # Thomas Wang's 64-bit integer hash in its published shift-and-add form, each step
     # reduced to the 2k-bit code space (the oracle writes the same steps as products)
@@ -46,11 +49,16 @@ def sketch(seq, pattern, shift, k, w, hash="splitmix64"):
     ent = []
     for i in range(len(ps) - k + 1):
         kmer = ps[i:i + k]
+        if N in kmer:                      # no k-mer holds the ambiguous base
+            ent.append(None)
+            continue
         f = numeral(kmer)
         r = numeral([3 - b for b in reversed(kmer)])
         ent.append(None if f == r else (hf(min(f, r)), 1 if r < f else 0))
     chosen = set()
     for s in range(len(ent) - w + 1):
+        if N in ps[s:s + w + k - 1]:       # a window never spans an N
+            continue
         hs = [e[0] for e in ent[s:s + w] if e is not None]
         if not hs:
             continue

@@ -63,6 +63,8 @@ MUTANTS = [
     ("Wang hash multiplier", "key = (key * 265u) & mask;", "key = (key * 273u) & mask;"),
     ("Wang hash first step unmasked", "key = (~key + (key << 21)) & mask;",
      "key = (~key + (key << 21));"),
+    ("N does not end a run", "if (i < n && PS[i] != 4) continue;", "if (i < n) continue;"),
+    ("run restarts at the N instead of after it", "        r0 = i + 1;", "        r0 = i;"),
     ("containment counts every genome hash",
      "if (bsearch(&gh[i].val, sample, (size_t)nu, sizeof(uint64_t), u64_cmp)) counts[g]++;",
      "if (1) counts[g]++;"),

@@ -498,3 +498,92 @@ def test_wang_sketch_matches_brute_force(pattern, k, w):
                                               shifts=np.array([shift], np.uint32))
             want = brute.sketch(list(seq), pattern, shift, k, w, hash="wang")
             assert list(zip(keys.tolist(), vals.tolist())) == want
+
+
+# ---------------------------------------------------------------- ambiguous bases (N)
+
+def with_ns(rng, L, runs=2, singles=3):
+    s = rng.integers(0, 4, L, dtype=np.uint8)
+    for _ in range(singles if L else 0):
+        s[int(rng.integers(0, L))] = 4
+    for _ in range(runs if L > 10 else 0):
+        a = int(rng.integers(0, L - 5))
+        s[a:a + int(rng.integers(1, 12))] = 4
+    return s
+
+
+@pytest.mark.parametrize("pattern,k,w", [("1", 5, 4), ("10", 4, 3), ("110", 3, 5), ("101001", 3, 2),
+                                         ("1", 2, 1), ("100", 6, 7)])
+def test_n_sketch_matches_brute_force(pattern, k, w):
+    # brute force: a k-mer holding an N is no k-mer, a window over any N is no window
+    rng = np.random.default_rng(k * 31 + w)
+    for _ in range(25):
+        seq = with_ns(rng, int(rng.integers(0, 120)))
+        for shift in range(len(pattern)):
+            keys, vals, _ = oracle.sketch(seq, one(seq), pattern, k, w,
+                                          shifts=np.array([shift], np.uint32))
+            want = brute.sketch(list(seq), pattern, shift, k, w)
+            assert list(zip(keys.tolist(), vals.tolist())) == want
+
+
+def test_n_at_a_dropped_position_changes_nothing():
+    rng = np.random.default_rng(40)
+    seq = rng.integers(0, 4, 3000, dtype=np.uint8)
+    for pattern, shift in [("10", 0), ("10", 1), ("110", 2), ("1001", 1)]:
+        dropped = [j for j in range(seq.size) if pattern[(j - shift) % len(pattern)] == "0"]
+        s2 = seq.copy()
+        s2[rng.choice(dropped, 200, replace=False)] = 4
+        sh = np.array([shift], np.uint32)
+        a = oracle.sketch(seq, one(seq), pattern, 11, 7, shifts=sh)
+        b = oracle.sketch(s2, one(s2), pattern, 11, 7, shifts=sh)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_kept_n_splits_the_sequence_in_two():
+    # X + N + Y with the N kept sketches as X, then Y alone under the phase Y has in place
+    rng = np.random.default_rng(41)
+    for pattern, k, w in [("10", 9, 5), ("110", 7, 4), ("1", 8, 6), ("1011", 5, 3)]:
+        p = len(pattern)
+        for _ in range(20):
+            L1 = int(rng.integers(0, 200))
+            a = int(rng.integers(0, p))
+            if pattern[(L1 - a) % p] != "1":
+                continue
+            x = rng.integers(0, 4, L1, dtype=np.uint8)
+            y = rng.integers(0, 4, int(rng.integers(0, 200)), dtype=np.uint8)
+            xy = np.concatenate([x, [4], y]).astype(np.uint8)
+            got = oracle.sketch(xy, one(xy), pattern, k, w, shifts=np.array([a], np.uint32))
+            kx, vx, _ = oracle.sketch(x, one(x), pattern, k, w, shifts=np.array([a], np.uint32))
+            ay = (a - L1 - 1) % p
+            ky, vy, _ = oracle.sketch(y, one(y), pattern, k, w, shifts=np.array([ay], np.uint32))
+            assert np.array_equal(got[0], np.concatenate([kx, ky]))
+            assert np.array_equal(got[1], np.concatenate([vx, vy + (np.uint64(L1 + 1) << 1)]))
+
+
+def test_all_n_and_short_runs_give_nothing():
+    s = np.full(500, 4, np.uint8)
+    s[::7] = 1                                  # runs of one base between Ns
+    for pattern in ("1", "10"):
+        keys, _, mz = oracle.sketch(s, one(s), pattern, 3, 2)
+        assert keys.size == 0 and mz.tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("pattern,k,w", [("10", 5, 3), ("110", 4, 2), ("1", 6, 4)])
+def test_n_seed_matches_brute_force(pattern, k, w):
+    rng = np.random.default_rng(17)
+    ref = with_ns(rng, 700, runs=3, singles=10)
+    ik, iv = oracle.index_build(ref, one(ref), pattern, k, w)
+    index = list(zip(ik.tolist(), iv.tolist()))
+    reads = []
+    for L in (60, 45, 0, 90, 30):
+        st = int(rng.integers(0, 700 - L))
+        r = ref[st:st + L].copy()
+        if L > 20:
+            r[int(rng.integers(0, L))] = 4
+        reads.append(r)
+    offs = np.concatenate([[0], np.cumsum([len(r) for r in reads])]).astype(np.uint64)
+    codes = np.concatenate(reads)
+    a, _, sh = oracle.seed(ik, iv, codes, offs, pattern, k, w)
+    exp, exp_sh = brute.seed(index, [r.tolist() for r in reads], pattern, k, w)
+    assert [tuple(x) for x in a.tolist()] == exp and sh.tolist() == exp_sh
+    assert len(exp) > 20
