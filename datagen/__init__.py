@@ -27,8 +27,9 @@ LONG_MAX = 1331423
 
 
 def revcomp(codes):
-    """Reverse complement of a code array (the opposite DNA strand)."""
-    return (3 - codes[::-1]).astype(np.uint8)
+    """Reverse complement of a code array (the opposite DNA strand; N stays N)."""
+    r = np.asarray(codes, np.uint8)[::-1]
+    return np.where(r == 4, 4, 3 - r).astype(np.uint8)
 
 
 def random_genome(length, seed):
@@ -95,7 +96,8 @@ def fixed_reads(ref, n, length, seed, sub=0.01, ins=0.0, dele=0.0, margin=16):
                 m = np.concatenate([m, rng.integers(0, 4, size=length - m.size, dtype=np.uint8)])
             reads[r] = m
     rev = strands == 1
-    reads[rev] = 3 - reads[rev][:, ::-1]
+    flipped = reads[rev][:, ::-1]
+    reads[rev] = np.where(flipped == 4, 4, 3 - flipped)
     offsets = np.arange(0, (n + 1) * length, length, dtype=np.int64)
     return reads.reshape(-1).copy(), offsets, starts.astype(np.int64), strands
 
@@ -210,7 +212,8 @@ def sample_from_genomes(codes, offsets, n_reads, n_source, length, seed, sub=0.0
     reads = codes[st[:, None] + np.arange(length)[None, :]]
     _substitute(rng, reads, sub)
     rev = strands == 1
-    reads[rev] = 3 - reads[rev][:, ::-1]
+    flipped = reads[rev][:, ::-1]
+    reads[rev] = np.where(flipped == 4, 4, 3 - flipped)
     ro = np.arange(0, (n_reads + 1) * length, length, dtype=np.int64)
     return reads.reshape(-1).copy(), ro, which.astype(np.int64)
 
@@ -219,6 +222,37 @@ def sample_from_genomes(codes, offsets, n_reads, n_source, length, seed, sub=0.0
 # The five workloads.  Seeds: reference = workload number, reads = 100 + number,
 # repeats = 200 + number, absent lookup keys = 304.
 # ---------------------------------------------------------------------------------------
+
+def add_gaps(codes, seed, n_runs=0, run_len=(100, 10_000), n_single=0):
+    """A copy of codes with ambiguous bases (code 4): n_runs runs of N with uniform lengths
+    in run_len (assembly gaps) at uniform starts, plus n_single isolated Ns."""
+    rng = np.random.default_rng(seed)
+    out = np.array(codes, np.uint8, copy=True)
+    if out.size == 0:
+        return out
+    for _ in range(n_runs):
+        L = int(rng.integers(run_len[0], run_len[1] + 1))
+        a = int(rng.integers(0, max(out.size - L, 1)))
+        out[a:a + L] = 4
+    if n_single:
+        out[rng.integers(0, out.size, n_single)] = 4
+    return out
+
+
+def to_text(codes, seed=None):
+    """Codes as sequence text: A C G T for 0..3 and N for 4; with a seed, a random mix of
+    upper and lower case and of other ambiguity letters in place of N."""
+    c = np.asarray(codes, np.uint8)
+    upper = np.frombuffer(b"ACGTN", np.uint8)[c]
+    if seed is None:
+        return upper.tobytes()
+    rng = np.random.default_rng(seed)
+    out = np.where(rng.random(c.size) < 0.5, upper, upper | 0x20).astype(np.uint8)
+    amb = np.frombuffer(b"NnRYKMSWBDHV-.*", np.uint8)
+    isn = c == 4
+    out[isn] = amb[rng.integers(0, amb.size, int(isn.sum()))]
+    return out.tobytes()
+
 
 def workload_tiny():
     """1 Mbp i.i.d. reference; 2,000 x 150 bp reads, both strands, 1 % substitutions;

@@ -28,10 +28,14 @@
  * Sequence layout (the paper's 2-bit encoding of A, C, G, T; Section 3.6.1)
  * -----------------------------------------------------------------------
  *  A batch of n_seq sequences is one 2-bit packed byte array: base i of the batch is
- *  bits [2*(i%4), 2*(i%4)+1] of byte i/4, with A=0, C=1, G=2, T=3 (N cannot be encoded;
- *  the host packer rejects it).  offsets[n_seq+1] (uint64, non-decreasing, offsets[0] = 0,
- *  offsets[n_seq] = n_bases) delimit the sequences; they need not be multiples of 4.
- *  The byte array must hold at least ceil(n_bases / 4) bytes.
+ *  bits [2*(i%4), 2*(i%4)+1] of byte i/4, with A=0, C=1, G=2, T=3.  offsets[n_seq+1]
+ *  (uint64, non-decreasing, offsets[0] = 0, offsets[n_seq] = n_bases) delimit the
+ *  sequences; they need not be multiples of 4.  The byte array must hold at least
+ *  ceil(n_bases / 4) bytes.
+ *  Ambiguous bases (N) ride beside the codes in an optional bit mask nmask: bit (i%32)
+ *  of 32-bit word i/32 is set iff base i is N (its 2-bit code is then ignored), at
+ *  least ceil(n_bases / 32) words.  With nmask NULL the batch holds no N.
+ *  godiet_pack_ascii builds both arrays from text.
  *
  * The method (Section 3; Sections 3.1-3.3)
  * -----------------------------------------
@@ -44,6 +48,11 @@
  *  the canonical code.  A k-mer of the patterned sequence is a minimizer iff its hash
  *  equals the minimum over some full window of w consecutive k-mers (all ties kept).
  *  Locations are coordinates in the ORIGINAL sequence of the k-mer's first kept base.
+ *  An N among the KEPT bases ends the current run of patterned bases and the next run
+ *  starts right after it (Section 3.6.1): no k-mer contains an N and no window spans
+ *  one, so every run is sketched as if it were a sequence of its own (its locations
+ *  stay those of the original sequence).  An N at a dropped position is dropped with
+ *  it and changes nothing.
  */
 #ifndef GODIET_H
 #define GODIET_H
@@ -83,6 +92,7 @@ typedef struct {
     const uint64_t *offsets;  /* n_seq + 1 base offsets */
     uint32_t n_seq;           /* [host] */
     uint64_t n_bases;         /* [host] must equal offsets[n_seq] */
+    const uint32_t *nmask;    /* N bit mask (layout above), or NULL: no N in the batch */
 } godiet_seqs;
 
 typedef struct {
@@ -167,10 +177,24 @@ size_t godiet_sparsify_bytes(const godiet_seqs *seqs, const char *pattern);
  * keep base j of sequence s iff P[(j - a_s) mod p] == '1', a_s = shift[s] (shift NULL:
  * all 0).  out_bases receives the kept bases of all sequences back to back in the same
  * 2-bit layout, zero-padded to godiet_sparsify_bytes(); out_offsets[n_seq+1] their
- * boundaries. */
+ * boundaries.  out_nmask (may be NULL; ignored when in->nmask is NULL) receives the N
+ * mask of the kept bases in the layout above, godiet_sparsify_bytes() / 2 bytes. */
 godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const uint32_t *shift,
-                              uint8_t *out_bases, uint64_t *out_offsets,
+                              uint8_t *out_bases, uint64_t *out_offsets, uint32_t *out_nmask,
                               void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
+
+/* [host] Bytes godiet_pack_ascii writes to bases (16 per 64 characters, rounded up);
+ * the N mask takes half as many. */
+size_t godiet_pack_bytes(uint64_t n_chars);
+
+/* Text to the batch layout (Section 3.6.1: 2-bit codes, with N kept aside): character i
+ * of `text` (n_chars bytes, device) becomes base i; A/a = 0, C/c = 1, G/g = 2, T/t and
+ * U/u = 3; every other byte is the ambiguous base N (code 0 with its nmask bit set).
+ * Writes godiet_pack_bytes(n_chars) bytes to bases and half of that to nmask, padding
+ * with zero codes and clear bits.  Offsets are the caller's: the text of the batch's
+ * sequences back to back, without separators. */
+godiet_status godiet_pack_ascii(const char *text, uint64_t n_chars, uint8_t *bases,
+                                uint32_t *nmask, hipStream_t stream);
 
 /* Minimizer sketch (Section 3.1 step 3, canonical (w,k)-minimizers of both strands;
  * Section 3.6.1):

@@ -22,7 +22,8 @@ class GodietError(RuntimeError):
 
 class Seqs(ctypes.Structure):
     _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
-                ("n_seq", ctypes.c_uint32), ("n_bases", ctypes.c_uint64)]
+                ("n_seq", ctypes.c_uint32), ("n_bases", ctypes.c_uint64),
+                ("nmask", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -72,8 +73,12 @@ def lib():
         L.godiet_kept_bound.restype = u64
         L.godiet_sparsify_bytes.argtypes = [S(Seqs), ctypes.c_char_p]
         L.godiet_sparsify_bytes.restype = sz
-        L.godiet_sparsify.argtypes = [S(Seqs), ctypes.c_char_p, P, P, P, P, sz, P, P]
+        L.godiet_sparsify.argtypes = [S(Seqs), ctypes.c_char_p, P, P, P, P, P, sz, P, P]
         L.godiet_sparsify.restype = i32
+        L.godiet_pack_bytes.argtypes = [u64]
+        L.godiet_pack_bytes.restype = sz
+        L.godiet_pack_ascii.argtypes = [P, u64, P, P, P]
+        L.godiet_pack_ascii.restype = i32
         L.godiet_sketch.argtypes = [S(Seqs), S(Params), P, P, P, P, u64, P, sz, P, P]
         L.godiet_sketch.restype = i32
         L.godiet_index_build.argtypes = [S(Seqs), S(Params), P, P, i32, u64, P, P, sz, P, P]
@@ -152,7 +157,7 @@ def pack(codes):
     The result is padded with zero bytes to a multiple of 16."""
     c = np.ascontiguousarray(codes, dtype=np.uint8)
     if c.size and c.max() > 3:
-        raise ValueError("only A, C, G, T (codes 0..3) can be packed")
+        raise ValueError("only A, C, G, T (codes 0..3) can be packed; N goes into pack_n")
     n = c.size
     padded = np.zeros((n + 63) // 64 * 64, np.uint8)
     padded[:n] = c
@@ -160,28 +165,75 @@ def pack(codes):
     return (q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)).astype(np.uint8)
 
 
-class DeviceSeqs:
-    """A 2-bit packed batch of sequences resident in device memory."""
+def pack_n(is_n):
+    """N bit mask of a batch: bit i%32 of 32-bit word i//32 set iff base i is N, padded
+    with zero bits to 64 bits per 64 bases (as uint8 bytes)."""
+    b = np.ascontiguousarray(is_n, dtype=bool)
+    padded = np.zeros((b.size + 63) // 64 * 64, bool)
+    padded[:b.size] = b
+    return np.packbits(padded, bitorder="little")
 
-    def __init__(self, bases, offsets, n_seq, n_bases):
+
+class DeviceSeqs:
+    """A 2-bit packed batch of sequences resident in device memory, with an optional N
+    bit mask (uint8 tensor, or None when the batch holds no N)."""
+
+    def __init__(self, bases, offsets, n_seq, n_bases, nmask=None):
         self.bases, self.offsets = bases, offsets
         self.n_seq, self.n_bases = int(n_seq), int(n_bases)
+        self.nmask = nmask
 
     def c(self):
-        return Seqs(self.bases.data_ptr(), self.offsets.data_ptr(), self.n_seq, self.n_bases)
+        return Seqs(self.bases.data_ptr(), self.offsets.data_ptr(), self.n_seq, self.n_bases,
+                    self.nmask.data_ptr() if self.nmask is not None else None)
 
 
-def to_device(codes, offsets, device="cuda"):
-    torch = _torch()
+def _offsets(offsets, n):
     offs = np.ascontiguousarray(offsets, dtype=np.int64)
     if offs.size < 1 or offs[0] != 0 or np.any(np.diff(offs) < 0):
         raise ValueError("offsets must start at 0 and be non-decreasing")
-    packed = pack(codes)
-    if offs[-1] > np.asarray(codes).size:
+    if offs[-1] > n:
         raise ValueError("offsets exceed the number of bases")
-    b = torch.from_numpy(packed).to(device)
+    return offs
+
+
+def to_device(codes, offsets, device="cuda"):
+    """Upload base codes (A=0, C=1, G=2, T=3; 4 = the ambiguous base N) with their
+    n_seq + 1 offsets.  An N mask is attached only when some code is 4."""
+    torch = _torch()
+    c = np.asarray(codes, dtype=np.uint8)
+    offs = _offsets(offsets, c.size)
+    if c.size and c.max() > 4:
+        raise ValueError("base codes must be 0..3, or 4 for N")
+    nm = None
+    if c.size and c.max() == 4:
+        is_n = c == 4
+        nm = torch.from_numpy(pack_n(is_n)).to(device)
+        c = np.where(is_n, 0, c).astype(np.uint8)
+    b = torch.from_numpy(pack(c)).to(device)
     o = torch.from_numpy(offs).to(device)
-    return DeviceSeqs(b, o, offs.size - 1, int(offs[-1]))
+    return DeviceSeqs(b, o, offs.size - 1, int(offs[-1]), nm)
+
+
+def to_device_ascii(text, offsets, device="cuda"):
+    """Upload sequence text (bytes, str or a uint8 array; the batch's sequences back to
+    back) and pack it on the device: A/C/G/T/U in either case are bases, every other
+    character is N.  Always attaches an N mask."""
+    torch = _torch()
+    if isinstance(text, str):
+        text = text.encode()
+    raw = np.frombuffer(bytes(text), np.uint8) if isinstance(text, (bytes, bytearray)) \
+        else np.ascontiguousarray(text, dtype=np.uint8)
+    offs = _offsets(offsets, raw.size)
+    L = lib()
+    nb = L.godiet_pack_bytes(raw.size)
+    t = torch.from_numpy(raw.copy()).to(device) if raw.size else None
+    bases = _empty(nb, torch.uint8)
+    nmask = _empty(max(nb // 2, 4), torch.uint8)
+    _check(L.godiet_pack_ascii(_ptr(t), raw.size, _ptr(bases), _ptr(nmask), _stream()),
+           "godiet_pack_ascii")
+    o = torch.from_numpy(offs).to(device)
+    return DeviceSeqs(bases, o, offs.size - 1, int(offs[-1]), nmask)
 
 
 def _params(pattern, k, w, hash="splitmix64"):
@@ -210,8 +262,10 @@ def _status_value(st):
     return int(st.item())
 
 
-def sparsify(seqs, pattern, shift=None):
-    """Returns (packed patterned bases as uint8 tensor, patterned offsets int64 tensor)."""
+def sparsify(seqs, pattern, shift=None, with_nmask=False):
+    """Returns (packed patterned bases as uint8 tensor, patterned offsets int64 tensor),
+    and with with_nmask the N mask of the kept bases (uint8 tensor, None when the batch
+    has none) as a third element."""
     torch = _torch()
     s = seqs.c()
     L = lib()
@@ -222,11 +276,13 @@ def sparsify(seqs, pattern, shift=None):
     st = _empty(1, torch.int32)
     sh = None if shift is None else torch.as_tensor(np.asarray(shift, np.uint32).view(np.int32),
                                                      device="cuda")
+    pn = _empty(max(nbytes // 2, 4), torch.uint8) if seqs.nmask is not None else None
     _check(L.godiet_sparsify(ctypes.byref(s), pattern.encode(), _ptr(sh), _ptr(out), _ptr(offs),
-                             _ptr(ws), ws.numel(), _ptr(st), _stream()), "godiet_sparsify")
+                             _ptr(pn), _ptr(ws), ws.numel(), _ptr(st), _stream()),
+           "godiet_sparsify")
     if _status_value(st) & STATUS_SHIFT:
         raise ValueError("a shift is >= the pattern length")
-    return out, offs
+    return (out, offs, pn) if with_nmask else (out, offs)
 
 
 def sketch(seqs, pattern, k, w, shift=None, capacity=None, hash="splitmix64"):

@@ -46,7 +46,10 @@ uint64_t kept_bound(const godiet_seqs *q, const Pattern &P)
     return b < q->n_bases ? b : q->n_bases;
 }
 
-Batch batch_of(const godiet_seqs *q) { return Batch{q->bases, q->offsets, q->n_seq, q->n_bases}; }
+Batch batch_of(const godiet_seqs *q)
+{
+    return Batch{q->bases, q->offsets, q->n_seq, q->n_bases, q->nmask};
+}
 
 #define GD_TRY(expr)                                   \
     do {                                               \
@@ -58,17 +61,20 @@ Batch batch_of(const godiet_seqs *q) { return Batch{q->bases, q->offsets, q->n_s
 struct SketchWs {
     uint64_t *kept, *scan, *pofs;
     uint32_t *psw;
+    uint32_t *pnw;        // N bits of the patterned stream (null without an N mask)
     uint64_t *tiles;
     uint32_t *counter;
     uint32_t *lohi;       // per-window sequence ranges (sparsify blocks, then sketch tiles)
 };
 
-void plan_sketch_ws(Bump &b, uint32_t n_seq, uint64_t npb, int w, SketchWs *o)
+void plan_sketch_ws(Bump &b, const godiet_seqs *q, uint64_t npb, int w, SketchWs *o)
 {
+    const uint32_t n_seq = q->n_seq;
     o->kept = b.take<uint64_t>((size_t)n_seq + 1);
     o->scan = b.take<uint64_t>(scan_scratch((size_t)n_seq + 1));
     o->pofs = b.take<uint64_t>((size_t)n_seq + 1);
     o->psw = b.take<uint32_t>(psw_words(npb));
+    o->pnw = q->nmask ? b.take<uint32_t>(pnw_words(npb)) : nullptr;
     o->tiles = b.take<uint64_t>(sketch_tiles_bound(npb, w));
     o->counter = b.take<uint32_t>(1);
     const size_t a = sparsify_lohi(psw_words(npb)), t = 2 * sketch_tiles_bound(npb, w);
@@ -85,7 +91,8 @@ hipError_t sparsify_to_stream(const godiet_seqs *in, const Pattern &P, const uin
     if (e != hipSuccess) return e;
     e = exclusive_scan_u64(W.kept, W.pofs, in->n_seq, W.scan, s);
     if (e != hipSuccess) return e;
-    return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, psw_words(npb), W.lohi, s);
+    return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, W.pnw, psw_words(npb), W.lohi,
+                           s);
 }
 
 struct IndexWs {
@@ -98,7 +105,7 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
                    int val_bytes, IndexWs *o)
 {
     const uint64_t npb = kept_bound(ref, P);
-    plan_sketch_ws(b, ref->n_seq, npb, w, &o->sk);
+    plan_sketch_ws(b, ref, npb, w, &o->sk);
     uint64_t expected = npb * 2 / (uint64_t)(w + 1) + 1;
     if (expected > capacity) expected = capacity;
     o->sp = sort_plan(expected, capacity, val_bytes);
@@ -154,7 +161,7 @@ void plan_seed_ws(Bump &b, const godiet_seqs *reads, const Pattern &P, int w, ui
                   SeedWs *o)
 {
     const uint64_t npb = kept_bound(reads, P);
-    plan_sketch_ws(b, reads->n_seq, npb, w, &o->sk);
+    plan_sketch_ws(b, reads, npb, w, &o->sk);
     o->stride = (size_t)npb + 1;
     const size_t nr = (size_t)reads->n_seq;
     o->mzofs = b.take<uint64_t>((nr + 1) * n_shift);
@@ -196,8 +203,9 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         uint64_t *qk = W.qkeys + si * W.stride;
         uint32_t *qv = W.qvals + si * W.stride;
         SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
-        GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, npb, prm->k,
-                             prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
+        GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, W.sk.pnw, npb,
+                             prm->k, prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi,
+                             status, stream));
         GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
                              W.occ + si * W.stride, index->rmi, index->table,
                              opts->lookup_blocks, stream));
@@ -267,7 +275,7 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
     case GODIET_OP_SKETCH: {
         if (!valid_params(prm, &P)) return 0;
         SketchWs o;
-        plan_sketch_ws(b, seqs->n_seq, kept_bound(seqs, P), prm->w, &o);
+        plan_sketch_ws(b, seqs, kept_bound(seqs, P), prm->w, &o);
         return b.off;
     }
     case GODIET_OP_INDEX_BUILD: {
@@ -295,13 +303,13 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
 }
 
 godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const uint32_t *shift,
-                              uint8_t *out_bases, uint64_t *out_offsets, void *ws, size_t ws_bytes,
-                              uint32_t *status, hipStream_t stream)
+                              uint8_t *out_bases, uint64_t *out_offsets, uint32_t *out_nmask,
+                              void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream)
 {
     Pattern P;
     if (!valid_seqs(in) || !parse_pattern(pattern, &P) || !out_bases || !out_offsets || !status)
         return GODIET_E_INVAL;
-    if (((uintptr_t)out_bases & 3) != 0) return GODIET_E_INVAL;
+    if (((uintptr_t)out_bases & 3) != 0 || ((uintptr_t)out_nmask & 3) != 0) return GODIET_E_INVAL;
     Bump b(ws);
     uint64_t *kept = b.take<uint64_t>((size_t)in->n_seq + 1);
     uint64_t *scan = b.take<uint64_t>(scan_scratch((size_t)in->n_seq + 1));
@@ -312,8 +320,20 @@ godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const 
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(launch_kept(bt, P, shift, 0, kept, status, stream));
     GD_TRY(exclusive_scan_u64(kept, out_offsets, in->n_seq, scan, stream));
-    GD_TRY(launch_sparsify(bt, P, shift, 0, out_offsets, (uint32_t *)out_bases, psw_words(npb),
-                           lohi, stream));
+    GD_TRY(launch_sparsify(bt, P, shift, 0, out_offsets, (uint32_t *)out_bases, out_nmask,
+                           psw_words(npb), lohi, stream));
+    return GODIET_OK;
+}
+
+size_t godiet_pack_bytes(uint64_t n_chars) { return (size_t)((n_chars + 63) / 64) * 16; }
+
+godiet_status godiet_pack_ascii(const char *text, uint64_t n_chars, uint8_t *bases,
+                                uint32_t *nmask, hipStream_t stream)
+{
+    if (n_chars > 0 && (!text || !bases || !nmask)) return GODIET_E_INVAL;
+    if (((uintptr_t)bases & 3) != 0 || ((uintptr_t)nmask & 3) != 0) return GODIET_E_INVAL;
+    if (n_chars >= (1ull << 48)) return GODIET_E_RANGE;
+    GD_TRY(launch_pack_ascii(text, n_chars, (uint32_t *)bases, (uint16_t *)nmask, stream));
     return GODIET_OK;
 }
 
@@ -328,13 +348,13 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
     const uint64_t npb = kept_bound(in, P);
     Bump b(ws);
     SketchWs W;
-    plan_sketch_ws(b, in->n_seq, npb, prm->w, &W);
+    plan_sketch_ws(b, in, npb, prm->w, &W);
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, status, stream));
     SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
-    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, npb, prm->k, prm->w, prm->hash, o, W.tiles,
-                         W.counter, W.lohi, status, stream));
+    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, W.pnw, npb, prm->k, prm->w,
+                         prm->hash, o, W.tiles, W.counter, W.lohi, status, stream));
     return GODIET_OK;
 }
 
@@ -358,8 +378,9 @@ godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_par
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));
     SketchOut o{keys, vals, val_bits == 32 ? VAL_GLOBAL32 : VAL_SEQ64, nullptr, capacity, n_out};
-    GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, npb, prm->k, prm->w, prm->hash, o,
-                         W.sk.tiles, W.sk.counter, W.sk.lohi, status, stream));
+    GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, W.sk.pnw, npb, prm->k,
+                         prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status,
+                         stream));
     if (capacity > 0) GD_TRY(launch_sort(W.sp, W.so, keys, vals, vb, n_out, capacity, stream));
     return GODIET_OK;
 }

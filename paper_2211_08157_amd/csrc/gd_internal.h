@@ -76,15 +76,20 @@ struct Batch {
     const uint64_t *offsets;
     uint32_t n_seq;
     uint64_t n_bases;
+    const uint32_t *nmask;   // N bit per base, or null
 };
 
 // Per-sequence kept counts (shift from shift[] or the uniform value) -> out[n_seq].
 hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
                        uint32_t uniform_shift, uint64_t *kept, uint32_t *status, hipStream_t s);
-// Patterned stream (uint32 words, 16 bases each) of `words` words from pofs.
+// Patterned stream (uint32 words, 16 bases each) of `words` words from pofs; with b.nmask
+// and pnw set, also the N bits of the kept bases (pnw: `words` 16-bit halves).
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           size_t words, uint32_t *lohi, hipStream_t s);
+                           uint32_t *pnw, size_t words, uint32_t *lohi, hipStream_t s);
+// Text to 2-bit codes and N bits (godiet_pack_ascii).
+hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint16_t *nmask,
+                             hipStream_t s);
 // Entries of the lohi scratch a sparsify of `words` output words needs.
 inline size_t sparsify_lohi(size_t words) { return 2 * ((words + 255) / 256) + 2; }
 
@@ -100,12 +105,15 @@ struct SketchOut {
 size_t sketch_tiles_bound(uint64_t np_bound, int w);
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
-                         uint64_t np_bound, int k, int w, int hash, const SketchOut &o,
+                         const uint32_t *pnw, uint64_t np_bound, int k, int w, int hash,
+                         const SketchOut &o,
                          uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
                          uint32_t *status, hipStream_t s);
 
 // Words of the patterned stream buffer for an upper bound on kept bases.
 inline size_t psw_words(uint64_t np_bound) { return (size_t)(np_bound / 16) + 8; }
+// 32-bit words of its N mask (16 bits per stream word).
+inline size_t pnw_words(uint64_t np_bound) { return (psw_words(np_bound) + 1) / 2; }
 
 // ---- index sort (gd_sort.hip) ----
 struct SortPlan {

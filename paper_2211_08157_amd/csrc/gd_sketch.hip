@@ -289,6 +289,78 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
     psw[q] = word;
 }
 
+// N bits of the kept bases: one thread per 16 patterned positions (the words of
+// k_sparsify, with the same workgroups and sequence ranges), writing 16 bits.  Each base
+// is located as in the per-base path above; N runs are rare, so nothing faster is needed.
+__global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
+                                                       const uint64_t *offsets, uint32_t n_seq,
+                                                       Pattern P, const uint32_t *shift,
+                                                       uint32_t uniform, const uint64_t *pofs,
+                                                       uint16_t *pnw, size_t words, double inv_x,
+                                                       const uint32_t *lohi)
+{
+    __shared__ uint64_t sh_pofs[kSeqCache];
+    __shared__ uint64_t sh_offs[kSeqCache];
+    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs, offsets, sh_offs);
+    const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
+    if (q >= words) return;
+    const uint64_t np = pofs[n_seq];
+    const uint64_t j0 = (uint64_t)q * 16;
+    uint32_t bits = 0;
+    if (j0 < np) {
+        uint32_t s = C.find(j0);
+        uint64_t beg = C.at(s), end = C.at(s + 1);
+        while (j0 >= end) { s++; beg = end; end = C.at(s + 1); }
+        int u = 0;
+        while (u < 16) {
+            const uint64_t j = j0 + (uint64_t)u;
+            if (j >= np) break;
+            while (j >= end) { s++; beg = end; end = C.at(s + 1); }
+            uint32_t a = seq_shift(shift, uniform, s);
+            if (a >= P.p) a = 0;
+            const int seg = (int)min((uint64_t)(16 - u), end - j);
+            uint64_t per;
+            uint32_t r;
+            div_x(j - beg, P.x, inv_x, &per, &r);
+            const uint64_t rot = rotated_mask(P, a);
+            uint64_t m = rot;
+            for (uint32_t t = 0; t < r; t++) m &= m - 1;
+            uint64_t pb = C.orig(s) + per * P.p;
+            for (int i = 0; i < seg; i++) {
+                const uint64_t g = pb + (uint64_t)__builtin_ctzll(m);
+                bits |= ((nmask[g >> 5] >> (g & 31)) & 1u) << (u + i);
+                m &= m - 1;
+                if (m == 0) { m = rot; pb += P.p; }
+            }
+            u += seg;
+        }
+    }
+    pnw[q] = (uint16_t)bits;
+}
+
+// Text to codes: one thread per 16 characters, one 2-bit word and 16 N bits.
+__global__ __launch_bounds__(kBlock) void k_pack_ascii(const uint8_t *text, uint64_t n,
+                                                       uint32_t *bases, uint16_t *nmask,
+                                                       size_t words)
+{
+    const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
+    if (q >= words) return;
+    uint32_t code = 0, nb = 0;
+    const uint64_t i0 = (uint64_t)q * 16;
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        if (i0 + u < n) {
+            const uint32_t c = text[i0 + u] | 0x20u;            // lower case
+            const uint32_t v = c == 'a' ? 0u : c == 'c' ? 1u : c == 'g' ? 2u
+                             : (c == 't' || c == 'u') ? 3u : 4u;
+            code |= (v & 3u) << (2 * u);
+            nb |= (v == 4u ? 1u : 0u) << u;
+        }
+    }
+    bases[q] = code;
+    nmask[q] = (uint16_t)nb;
+}
+
 // ---------------------------------------------------------------- sketch
 
 constexpr int kE = kBlock * 16;     // LDS positions per tile (T + 2H)
@@ -297,6 +369,7 @@ constexpr int kMaxRegW = 17;        // largest w handled by the register path
 
 struct SketchArgs {
     const uint32_t *psw;
+    const uint32_t *pnw;            // N bits of the patterned stream, or null
     const uint64_t *pofs;
     const uint64_t *offsets;
     const uint32_t *shift;
@@ -342,6 +415,39 @@ __device__ __forceinline__ uint64_t kmer_msb(uint32_t m0, uint32_t m1, uint32_t 
     const uint32_t hi = u == 0 ? m0 : __builtin_amdgcn_alignbit(m0, m1, 32 - 2 * u);
     const uint32_t lo = u == 0 ? m1 : __builtin_amdgcn_alignbit(m1, m2, 32 - 2 * u);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// First N of the patterned stream in [a, b), else b (b - a is at most a few hundred).
+__device__ __forceinline__ uint64_t first_n(const uint32_t *pnw, uint64_t a, uint64_t b)
+{
+    while (a < b) {
+        uint32_t wd = pnw[a >> 5] >> (a & 31);
+        uint64_t avail = 32 - (a & 31);
+        if (b - a < avail) {
+            avail = b - a;
+            wd &= (1u << avail) - 1u;
+        }
+        if (wd) return a + (uint64_t)(__ffs(wd) - 1);
+        a += avail;
+    }
+    return b;
+}
+
+// One past the last N of the patterned stream in [a, b), else a.
+__device__ __forceinline__ uint64_t after_last_n(const uint32_t *pnw, uint64_t a, uint64_t b)
+{
+    while (b > a) {
+        const uint64_t top = b - 1;               // highest position of this step
+        uint32_t wd = pnw[top >> 5] << (31 - (top & 31));     // bit 31 = position top
+        uint64_t avail = (top & 31) + 1;
+        if (b - a < avail) {
+            avail = b - a;
+            wd &= ~((1u << (32 - avail)) - 1u);
+        }
+        if (wd) return top - (uint64_t)__clz(wd) + 1;
+        b -= avail;
+    }
+    return a;
 }
 
 // Bits u in [0, 16) with u <= x.
@@ -537,8 +643,12 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         const uint32_t mw0 = msb_first(w0), mw1 = msb_first(w1), mw2 = msb_first(w2);
         const int fsh = 64 - 2 * k;
         // every position of the chunk has its k-mer and a valid window in one sequence
-        const bool interior = (uint64_t)jc + 16 + (uint64_t)(k + w - 2) <= seq_end &&
-                              seq_end - seq_beg >= (uint64_t)(k + w - 1);
+        // (and, with ambiguous bases, no N among the bases those windows cover)
+        const uint64_t L = (uint64_t)(k + w - 1);
+        bool interior = (uint64_t)jc + 16 + (uint64_t)(k + w - 2) <= seq_end &&
+                        seq_end - seq_beg >= L;
+        if (interior && A.pnw)
+            interior = first_n(A.pnw, (uint64_t)jc, (uint64_t)jc + 15 + L) == (uint64_t)jc + 15 + L;
         if (interior && (k & 1)) {
             // odd k: a k-mer never equals its reverse complement
             selm = winm = 0xFFFFu;
@@ -574,7 +684,40 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             // loop per sequence overlapping the chunk; then all 16 positions are hashed
             // as in the interior and masked, without per-position branches.
             uint32_t kv = 0, wv = 0, okm = 0;
-            {
+            if (A.pnw) {
+                // With ambiguous bases the runs between Ns (within a sequence) play the
+                // part of sequences.  A run's start before jc - L or its end beyond
+                // jc + 16 + L changes no mask, so the searches stop there.
+                uint64_t c = (uint64_t)jc;
+                uint32_t s = seq;
+                uint64_t sb = seq_beg, se = seq_end;
+                const uint64_t far = (uint64_t)jc + 16 + L;
+                while (c < (uint64_t)jc + 16 && c < np) {
+                    if (c >= se) {
+                        s++;
+                        sb = se;
+                        se = C.at(s + 1);
+                        continue;
+                    }
+                    if ((A.pnw[c >> 5] >> (c & 31)) & 1u) {     // an N: in no run
+                        c++;
+                        continue;
+                    }
+                    uint64_t b = c;
+                    if (c == (uint64_t)jc && c > sb) {
+                        const uint64_t lo = (uint64_t)jc - sb > L ? (uint64_t)jc - L : sb;
+                        b = after_last_n(A.pnw, lo, c);
+                    }
+                    const uint64_t e = first_n(A.pnw, c, se < far ? se : far);
+                    const int lo = (int)(c - (uint64_t)jc);
+                    const int hi = e - (uint64_t)jc >= 16 ? 16 : (int)(e - (uint64_t)jc);
+                    const uint32_t span = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                    kv |= span & mask_le((int64_t)e - (int64_t)k - jc);
+                    wv |= span & mask_le((int64_t)e - (int64_t)L - jc);
+                    if (e - b >= L) okm |= span;
+                    c = e;
+                }
+            } else {
                 uint64_t b = seq_beg, e = seq_end;
                 uint32_t s = seq;
                 int lo = 0;
@@ -762,7 +905,7 @@ hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
 
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           size_t words, uint32_t *lohi, hipStream_t s)
+                           uint32_t *pnw, size_t words, uint32_t *lohi, hipStream_t s)
 {
     const size_t blocks = (words + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
@@ -776,12 +919,28 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
     GD_LAUNCH(k_sparsify, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.bases, b.offsets,
               b.n_seq, P, shift, uniform_shift, pofs, psw, words, (b.n_bases + 3) / 4, compact,
               1.0 / (double)P.x, (const uint32_t *)lohi);
+    if (b.nmask && pnw)
+        GD_LAUNCH(k_sparsify_n, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.nmask, b.offsets,
+                  b.n_seq, P, shift, uniform_shift, pofs, (uint16_t *)pnw, words,
+                  1.0 / (double)P.x, (const uint32_t *)lohi);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint16_t *nmask,
+                             hipStream_t s)
+{
+    const size_t words = (size_t)((n + 63) / 64) * 4;
+    const size_t blocks = (words + kBlock - 1) / kBlock;
+    if (blocks == 0) return hipSuccess;
+    GD_LAUNCH(k_pack_ascii, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const uint8_t *)text, n,
+              bases, nmask, words);
     return hipGetLastError();
 }
 
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
-                         uint64_t np_bound, int k, int w, int hash, const SketchOut &o,
+                         const uint32_t *pnw, uint64_t np_bound, int k, int w, int hash,
+                         const SketchOut &o,
                          uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
                          uint32_t *status, hipStream_t s)
 {
@@ -797,6 +956,7 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     if (e != hipSuccess) return e;
     SketchArgs A;
     A.psw = psw;
+    A.pnw = pnw;
     A.pofs = pofs;
     A.offsets = b.offsets;
     A.shift = shift;

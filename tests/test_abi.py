@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -158,3 +159,37 @@ def test_table_size_and_host_checks():
     assert L.godiet_table_build(ctypes.byref(ix), ctypes.c_void_p(0x6008), need, None) == E_INVAL
     big = Index(0x4000, 0x5000, 1 << 32, 32, None, 0)
     assert L.godiet_table_build(ctypes.byref(big), ctypes.c_void_p(0x6000), 1 << 40, None) == E_RANGE
+
+
+def test_n_mask_adds_workspace_and_pack_sizes():
+    from paper_2211_08157_amd.api import Params, OP_SKETCH, OP_SEED, Seqs
+    L = _lib()
+    prm = Params(b"10", 21, 11, 0)
+    plain = Seqs(0x1000, 0x2000, 3, 1_000_000)
+    with_n = Seqs(0x1000, 0x2000, 3, 1_000_000, 0x3000)
+    for op in (OP_SKETCH, OP_SEED):
+        a = L.godiet_workspace_size(op, ctypes.byref(plain), ctypes.byref(prm), 1000)
+        b = L.godiet_workspace_size(op, ctypes.byref(with_n), ctypes.byref(prm), 1000)
+        # one bit per kept base: 500,000 kept bases -> ~62.5 kB more
+        assert a > 0 and 62_000 <= b - a <= 64_000, (op, a, b)
+    assert L.godiet_pack_bytes(0) == 0
+    assert L.godiet_pack_bytes(1) == 16 and L.godiet_pack_bytes(64) == 16
+    assert L.godiet_pack_bytes(65) == 32
+
+
+def test_pack_ascii_host_checks():
+    L = _lib()
+    assert L.godiet_pack_ascii(None, 0, None, None, None) == 0        # nothing to do
+    assert L.godiet_pack_ascii(None, 10, 0x1000, 0x2000, None) == -1  # no text
+    assert L.godiet_pack_ascii(0x1000, 10, 0x1002, 0x2000, None) == -1  # misaligned output
+    assert L.godiet_pack_ascii(0x1000, 10, 0x1000, None, None) == -1  # no N mask
+
+
+def test_pack_n_bit_layout():
+    from paper_2211_08157_amd.api import pack_n
+    is_n = np.zeros(70, bool)
+    is_n[[0, 5, 31, 32, 63, 69]] = True
+    words = pack_n(is_n).view(np.uint32)
+    assert words.size == 4                               # 64 bits per 64 bases, padded
+    got = [i for i in range(128) if (words[i // 32] >> (i % 32)) & 1]
+    assert got == [0, 5, 31, 32, 63, 69]
