@@ -209,6 +209,56 @@ def voting(gd, torch, s, steps, cpu=True):
     return out
 
 
+def gapped_step(gd, torch, steps, warmup):
+    """The learned-index step on the Illumina-like workload with assembly gaps (about 5 %
+    N in the reference) and N calls in the reads, which takes the N-aware path; plus the
+    device text packer on the reference's text."""
+    import datagen
+    d = datagen.workload_gapped()
+    g = Session(gd, d, "10", d["k"], d["w"])
+    for _ in range(warmup):
+        g.step("learned_index")
+    g.check()
+    torch.cuda.synchronize()
+    gd.trace_dump()
+    gd.trace_enable(True)
+    for _ in range(steps):
+        g.step("learned_index")
+    torch.cuda.synchronize()
+    gd.trace_enable(False)
+    kernels = {kn: dict(launches=c // steps, ms_per_step=t / steps)
+               for kn, (c, t) in sorted(gd.trace_dump().items(), key=lambda kv: -kv[1][1])}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step("learned_index")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    g.check()
+    n_frac_ref = float((d["ref"] == 4).mean())
+    n_frac_reads = float((d["reads"] == 4).mean())
+    text = datagen.to_text(d["ref"], seed=7)
+    n_reads = g.reads.n_seq
+    del g
+    gd.to_device_ascii(text, [0, len(text)])
+    torch.cuda.synchronize()
+    gd.trace_dump()
+    gd.trace_enable(True)
+    for _ in range(5):
+        gd.to_device_ascii(text, [0, len(text)])
+    torch.cuda.synchronize()
+    gd.trace_enable(False)
+    tr = gd.trace_dump()
+    pk = tr.get("k_pack_ascii", (5, float("nan")))[1] / 5
+    n = len(text)
+    return dict(workload="illumina-gapped-100Mbp: the Illumina-like workload with 50 gaps of "
+                         "20-180 kbp and 20,000 isolated N in the reference, one N call per "
+                         "1,000 read bases",
+                ms_per_step=ms, reads_per_s=n_reads / (ms * 1e-3),
+                n_fraction_reference=n_frac_ref, n_fraction_reads=n_frac_reads,
+                pack_ascii_ms=pk, pack_ascii_GBps=(n + n // 4 + n // 8) / (pk * 1e-3) / 1e9,
+                pack_ascii_bytes_rule="text in + 2-bit codes + N bits out", kernels=kernels)
+
+
 def cpu_baseline(data, pattern, k, w, sample_reads):
     """The oracle on the host: index build (one call), then seeding of a bounded sample of
     reads split over threads by read ranges (each read's anchors are independent; the
@@ -473,6 +523,9 @@ def main():
     vote = voting(gd, torch, s, args.steps, cpu=not args.no_cpu_baseline)
     log("[bench] location voting: %.3f ms per pass, %.3e reads/s" % (vote["ms_per_pass"],
                                                                     vote["reads_per_s"]))
+    gapped = gapped_step(gd, torch, args.steps, args.warmup)
+    log("[bench] gapped workload: %.3f ms/step, %.3e reads/s; text packing %.1f GB/s"
+        % (gapped["ms_per_step"], gapped["reads_per_s"], gapped["pack_ascii_GBps"]))
     lookup_gather = gather_rate(torch, s.n_index, s.queries)
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
@@ -533,6 +586,7 @@ def main():
         "sketch_kernels_ms": sk_kernels,
         "sketch_1Gbp": sketch_1g,
         "location_voting": vote,
+        "n_aware_step": gapped,
         "uneven_batch_1Gbp": uneven,
         "measured_copy_GBps": copy_bw,
         "sketch_frac_of_measured_copy": gbps / copy_bw,

@@ -274,6 +274,17 @@ def workload_illumina(ref_len=100_000_000, n_reads=1_000_000):
                 patterns=["10"], k=21, w=11)
 
 
+def workload_gapped(ref_len=100_000_000, n_reads=1_000_000):
+    """The Illumina-like workload with ambiguous bases: its reference with 50 assembly
+    gaps of 20-180 kbp (about 5 % N, the share of N in a human reference assembly) and
+    20,000 isolated Ns; its reads with one N call per 1,000 bases on average."""
+    d = workload_illumina(ref_len, n_reads)
+    d["ref"] = add_gaps(d["ref"], 402, n_runs=50, run_len=(20_000, 180_000), n_single=20_000)
+    d["reads"] = add_gaps(d["reads"], 403, n_single=d["reads"].size // 1000)
+    d["name"] = "illumina-gapped-100Mbp"
+    return d
+
+
 def workload_uneven(ref_len=1_000_000_000, n_short=2_000_000, n_hifi=20_000, n_ont=20_000):
     """1 Gbp reference (same repeat model); one mixed batch of short, HiFi-like and
     ONT-like reads; patterns '10' and '110'; k=21, w=11."""

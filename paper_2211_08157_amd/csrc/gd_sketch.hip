@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
                                                        Pattern P, const uint32_t *shift,
                                                        uint32_t uniform, const uint64_t *pofs,
                                                        uint16_t *pnw, size_t words, double inv_x,
-                                                       const uint32_t *lohi)
+                                                       const uint32_t *lohi, uint64_t nwords)
 {
     __shared__ uint64_t sh_pofs[kSeqCache];
     __shared__ uint64_t sh_offs[kSeqCache];
@@ -311,6 +311,42 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
         uint32_t s = C.find(j0);
         uint64_t beg = C.at(s), end = C.at(s + 1);
         while (j0 >= end) { s++; beg = end; end = C.at(s + 1); }
+        if (P.p == 2 && P.x == 1) {
+            // period 2: the bits of every other base of a run of 31, one funnel shift and
+            // a bit unzip (the next mask word is read only when the run reaches into it);
+            // a word that ends inside the next sequence takes its tail from a second run
+            auto run16 = [&](uint64_t o) -> uint32_t {
+                const uint64_t g = o >> 5;
+                const uint32_t sh = (uint32_t)(o & 31);
+                const uint32_t lo = nmask[g], hi = sh >= 2 ? nmask[g + 1] : 0u;
+                uint32_t x = __builtin_amdgcn_alignbit(hi, lo, sh) & 0x55555555u;
+                x = (x | (x >> 1)) & 0x33333333u;
+                x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+                x = (x | (x >> 4)) & 0x00FF00FFu;
+                return (x | (x >> 8)) & 0x0000FFFFu;
+            };
+            uint32_t a = seq_shift(shift, uniform, s);
+            if (a >= P.p) a = 0;
+            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + kept_phase(P, a, 0);
+            if (j0 + 16 <= end) {
+                pnw[q] = (uint16_t)run16(o0);
+                return;
+            }
+            if (j0 + 16 <= np) {
+                uint32_t s2 = s + 1;
+                while (C.at(s2 + 1) == C.at(s2)) s2++;        // skip empty sequences
+                uint32_t a2 = seq_shift(shift, uniform, s2);
+                if (a2 >= P.p) a2 = 0;
+                const uint64_t o2 = C.orig(s2) + kept_phase(P, a2, 0);
+                // both runs' reads stay inside the mask (ceil(n_bases / 32) words)
+                if (j0 + 16 <= C.at(s2 + 1) && ((o0 + 30) >> 5) < nwords &&
+                    ((o2 + 30) >> 5) < nwords) {
+                    const int n1 = (int)(end - j0);           // 1..15
+                    pnw[q] = (uint16_t)((run16(o0) & ((1u << n1) - 1u)) | (run16(o2) << n1));
+                    return;
+                }
+            }
+        }
         int u = 0;
         while (u < 16) {
             const uint64_t j = j0 + (uint64_t)u;
@@ -338,23 +374,39 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
     pnw[q] = (uint16_t)bits;
 }
 
-// Text to codes: one thread per 16 characters, one 2-bit word and 16 N bits.
+// Code of one character (4 = N).
+__device__ __forceinline__ uint32_t base_code(uint32_t ch)
+{
+    const uint32_t c = ch | 0x20u;                                  // lower case
+    return c == 'a' ? 0u : c == 'c' ? 1u : c == 'g' ? 2u : (c == 't' || c == 'u') ? 3u : 4u;
+}
+
+// Text to codes: one thread per 16 characters (one 16-byte load when the text is
+// 16-byte aligned and the group is whole), one 2-bit word and 16 N bits.
 __global__ __launch_bounds__(kBlock) void k_pack_ascii(const uint8_t *text, uint64_t n,
                                                        uint32_t *bases, uint16_t *nmask,
-                                                       size_t words)
+                                                       size_t words, int aligned)
 {
     const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
     if (q >= words) return;
     uint32_t code = 0, nb = 0;
     const uint64_t i0 = (uint64_t)q * 16;
+    if (aligned && i0 + 16 <= n) {
+        const uint4 v = *(const uint4 *)(text + i0);
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        if (i0 + u < n) {
-            const uint32_t c = text[i0 + u] | 0x20u;            // lower case
-            const uint32_t v = c == 'a' ? 0u : c == 'c' ? 1u : c == 'g' ? 2u
-                             : (c == 't' || c == 'u') ? 3u : 4u;
-            code |= (v & 3u) << (2 * u);
-            nb |= (v == 4u ? 1u : 0u) << u;
+        for (int u = 0; u < 16; u++) {
+            const uint32_t b = base_code((wd[u >> 2] >> (8 * (u & 3))) & 0xFFu);
+            code |= (b & 3u) << (2 * u);
+            nb |= (b >> 2) << u;
+        }
+    } else {
+        for (int u = 0; u < 16; u++) {
+            if (i0 + u < n) {
+                const uint32_t b = base_code(text[i0 + u]);
+                code |= (b & 3u) << (2 * u);
+                nb |= (b >> 2) << u;
+            }
         }
     }
     bases[q] = code;
@@ -431,6 +483,26 @@ __device__ __forceinline__ uint64_t first_n(const uint32_t *pnw, uint64_t a, uin
         a += avail;
     }
     return b;
+}
+
+// Whether [a, b) holds an N: up to four mask words loaded at once when the range spans
+// at most 96 positions (the loads issue together with the chunk's stream words), the
+// scanning loop otherwise.
+__device__ __forceinline__ bool any_n(const uint32_t *pnw, uint64_t a, uint64_t b)
+{
+    if (b <= a) return false;
+    if (b - a > 96) return first_n(pnw, a, b) != b;
+    const uint64_t wa = a >> 5, wb = (b - 1) >> 5;       // wb - wa <= 3
+    uint32_t m[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) m[i] = wa + i <= wb ? pnw[wa + i] : 0u;
+    m[0] &= ~0u << (a & 31);
+    const uint32_t top = (uint32_t)((b - 1) & 31);
+    const uint32_t keep = top == 31 ? ~0u : ((2u << top) - 1u);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (wa + i == wb) m[i] &= keep;
+    return (m[0] | m[1] | m[2] | m[3]) != 0;
 }
 
 // One past the last N of the patterned stream in [a, b), else a.
@@ -612,6 +684,84 @@ __device__ uint32_t select_lds(const uint64_t (&v)[16], uint32_t selm, uint32_t 
     return sel;
 }
 
+// N bits of the patterned stream read from the mask in memory.
+struct MemN {
+    const uint32_t *pnw;
+    __device__ __forceinline__ bool at(uint64_t c) const { return (pnw[c >> 5] >> (c & 31)) & 1u; }
+    __device__ __forceinline__ uint64_t first(uint64_t a, uint64_t b) const
+    {
+        return first_n(pnw, a, b);
+    }
+    __device__ __forceinline__ uint64_t after_last(uint64_t a, uint64_t b) const
+    {
+        return after_last_n(pnw, a, b);
+    }
+};
+
+// N bits of positions [jc - 64, jc + 64) held in two registers (Y below jc, X from jc):
+// the run loop then waits on no load.  Valid for the queries it makes when L <= 48.
+struct RegN {
+    uint64_t X, Y;
+    uint64_t jc;
+    __device__ __forceinline__ bool at(uint64_t c) const { return (X >> (c - jc)) & 1u; }
+    // first N in [a, b), a >= jc, b <= jc + 64
+    __device__ __forceinline__ uint64_t first(uint64_t a, uint64_t b) const
+    {
+        if (b <= a) return b;
+        uint64_t m = X >> (a - jc);
+        if (b - a < 64) m &= (1ull << (b - a)) - 1;
+        return m ? a + (uint64_t)__builtin_ctzll(m) : b;
+    }
+    // one past the last N in [a, b), b == jc, jc - a <= 64
+    __device__ __forceinline__ uint64_t after_last(uint64_t a, uint64_t b) const
+    {
+        if (b <= a) return a;
+        const uint64_t m = Y >> (64 - (b - a));          // bit i: position a + i
+        return m ? a + 64 - (uint64_t)__builtin_clzll(m) : a;
+    }
+};
+
+// Masks of a chunk near an N (kv: the k-mer fits, wv: a window starts, okm: the position
+// lies in a run long enough for one window): with ambiguous bases the runs between Ns
+// within a sequence play the part of sequences.  A run's start before jc - L or its end
+// beyond jc + 16 + L changes no mask, so the searches stop there.
+template <typename NB>
+__device__ __forceinline__ void run_masks(const NB &nb, const SeqCache &C, int64_t jc,
+                                          uint32_t seq, uint64_t seq_beg, uint64_t seq_end,
+                                          uint64_t np, int k, uint64_t L, uint32_t &kv,
+                                          uint32_t &wv, uint32_t &okm)
+{
+    uint64_t c = (uint64_t)jc;
+    uint32_t s = seq;
+    uint64_t sb = seq_beg, se = seq_end;
+    const uint64_t far = (uint64_t)jc + 16 + L;
+    while (c < (uint64_t)jc + 16 && c < np) {
+        if (c >= se) {
+            s++;
+            sb = se;
+            se = C.at(s + 1);
+            continue;
+        }
+        if (nb.at(c)) {                                  // an N: in no run
+            c++;
+            continue;
+        }
+        uint64_t b = c;
+        if (c == (uint64_t)jc && c > sb) {
+            const uint64_t lo = (uint64_t)jc - sb > L ? (uint64_t)jc - L : sb;
+            b = nb.after_last(lo, c);
+        }
+        const uint64_t e = nb.first(c, se < far ? se : far);
+        const int lo = (int)(c - (uint64_t)jc);
+        const int hi = e - (uint64_t)jc >= 16 ? 16 : (int)(e - (uint64_t)jc);
+        const uint32_t span = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+        kv |= span & mask_le((int64_t)e - (int64_t)k - jc);
+        wv |= span & mask_le((int64_t)e - (int64_t)L - jc);
+        if (e - b >= L) okm |= span;
+        c = e;
+    }
+}
+
 // One tile: the T positions [tile*T, tile*T + T) of the batch's patterned stream.
 template <int W, int HK>
 __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
@@ -640,14 +790,21 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         seq0 = seq; beg0 = seq_beg; end0 = seq_end;
         const size_t wi = (size_t)jc / 16;
         const uint32_t w0 = A.psw[wi], w1 = A.psw[wi + 1], w2 = A.psw[wi + 2];
+        // an N within k + w - 1 positions of the chunk needs the run-aware masks below
+        const uint64_t L = (uint64_t)(k + w - 1);
+        bool n_near = false;
+        if (A.pnw) {
+            const uint64_t lo = (uint64_t)jc > L ? (uint64_t)jc - L : 0;
+            const uint64_t hi = (uint64_t)jc + 16 + L < np ? (uint64_t)jc + 16 + L : np;
+            n_near = any_n(A.pnw, lo, hi);
+        }
         const uint32_t mw0 = msb_first(w0), mw1 = msb_first(w1), mw2 = msb_first(w2);
         const int fsh = 64 - 2 * k;
         // every position of the chunk has its k-mer and a valid window in one sequence
         // (and, with ambiguous bases, no N among the bases those windows cover)
-        const uint64_t L = (uint64_t)(k + w - 1);
         bool interior = (uint64_t)jc + 16 + (uint64_t)(k + w - 2) <= seq_end &&
                         seq_end - seq_beg >= L;
-        if (interior && A.pnw)
+        if (interior && n_near)
             interior = first_n(A.pnw, (uint64_t)jc, (uint64_t)jc + 15 + L) == (uint64_t)jc + 15 + L;
         if (interior && (k & 1)) {
             // odd k: a k-mer never equals its reverse complement
@@ -684,39 +841,23 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             // loop per sequence overlapping the chunk; then all 16 positions are hashed
             // as in the interior and masked, without per-position branches.
             uint32_t kv = 0, wv = 0, okm = 0;
-            if (A.pnw) {
-                // With ambiguous bases the runs between Ns (within a sequence) play the
-                // part of sequences.  A run's start before jc - L or its end beyond
-                // jc + 16 + L changes no mask, so the searches stop there.
-                uint64_t c = (uint64_t)jc;
-                uint32_t s = seq;
-                uint64_t sb = seq_beg, se = seq_end;
-                const uint64_t far = (uint64_t)jc + 16 + L;
-                while (c < (uint64_t)jc + 16 && c < np) {
-                    if (c >= se) {
-                        s++;
-                        sb = se;
-                        se = C.at(s + 1);
-                        continue;
-                    }
-                    if ((A.pnw[c >> 5] >> (c & 31)) & 1u) {     // an N: in no run
-                        c++;
-                        continue;
-                    }
-                    uint64_t b = c;
-                    if (c == (uint64_t)jc && c > sb) {
-                        const uint64_t lo = (uint64_t)jc - sb > L ? (uint64_t)jc - L : sb;
-                        b = after_last_n(A.pnw, lo, c);
-                    }
-                    const uint64_t e = first_n(A.pnw, c, se < far ? se : far);
-                    const int lo = (int)(c - (uint64_t)jc);
-                    const int hi = e - (uint64_t)jc >= 16 ? 16 : (int)(e - (uint64_t)jc);
-                    const uint32_t span = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
-                    kv |= span & mask_le((int64_t)e - (int64_t)k - jc);
-                    wv |= span & mask_le((int64_t)e - (int64_t)L - jc);
-                    if (e - b >= L) okm |= span;
-                    c = e;
-                }
+            if (n_near && L <= 48) {
+                // N bits of [jc - 64, jc + 64) from five words loaded at once
+                const int64_t q0 = jc >> 5;
+                const uint32_t sh = (uint32_t)(jc & 31);
+                uint32_t nw[5];
+#pragma unroll
+                for (int i = 0; i < 5; i++) nw[i] = q0 - 2 + i >= 0 ? A.pnw[q0 - 2 + i] : 0u;
+                RegN nb;
+                nb.jc = (uint64_t)jc;
+                nb.Y = ((uint64_t)__builtin_amdgcn_alignbit(nw[2], nw[1], sh) << 32) |
+                       __builtin_amdgcn_alignbit(nw[1], nw[0], sh);
+                nb.X = ((uint64_t)__builtin_amdgcn_alignbit(nw[4], nw[3], sh) << 32) |
+                       __builtin_amdgcn_alignbit(nw[3], nw[2], sh);
+                run_masks(nb, C, jc, seq, seq_beg, seq_end, np, k, L, kv, wv, okm);
+            } else if (n_near) {
+                MemN nb{A.pnw};
+                run_masks(nb, C, jc, seq, seq_beg, seq_end, np, k, L, kv, wv, okm);
             } else {
                 uint64_t b = seq_beg, e = seq_end;
                 uint32_t s = seq;
@@ -922,7 +1063,7 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
     if (b.nmask && pnw)
         GD_LAUNCH(k_sparsify_n, dim3((unsigned)blocks), dim3(kBlock), 0, s, b.nmask, b.offsets,
                   b.n_seq, P, shift, uniform_shift, pofs, (uint16_t *)pnw, words,
-                  1.0 / (double)P.x, (const uint32_t *)lohi);
+                  1.0 / (double)P.x, (const uint32_t *)lohi, (b.n_bases + 31) / 32);
     return hipGetLastError();
 }
 
@@ -933,7 +1074,7 @@ hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint
     const size_t blocks = (words + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
     GD_LAUNCH(k_pack_ascii, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const uint8_t *)text, n,
-              bases, nmask, words);
+              bases, nmask, words, (int)(((uintptr_t)text & 15) == 0));
     return hipGetLastError();
 }
 

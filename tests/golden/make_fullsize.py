@@ -4,7 +4,8 @@ Writes tests/golden/fullsize_oracle.json, which the full-size GPU tests compare 
 Every value in it comes from the oracle (oracle/) on inputs from datagen; nothing here
 calls the GPU library.  Run from the repository root:
 
-    python tests/golden/make_fullsize.py [--out FILE] [illumina] [uneven] [lookups] [containment]
+    python tests/golden/make_fullsize.py [--out FILE] [illumina] [gapped] [uneven] [lookups]
+        [containment]
 
 (no argument: all).  It needs about 20 GB of memory and takes tens of minutes on 8 cores.
 Seeding and lookups are split over threads by read and query ranges (each read's anchors
@@ -66,7 +67,8 @@ def parallel_seed(ik, iv, codes, offsets, pattern, chunk=20_000):
 
 
 # location-voting parameters per workload: (D, V, max_winners)
-VOTE = {"illumina-100Mbp": (16, 3, 4), "uneven-1Gbp": (100, 3, 4)}
+VOTE = {"illumina-100Mbp": (16, 3, 4), "illumina-gapped-100Mbp": (16, 3, 4),
+        "uneven-1Gbp": (100, 3, 4)}
 
 
 def vote_rows(out, nw):
@@ -115,6 +117,12 @@ def main(which):
         ent, _ = seed_entry(d, "10")
         table["illumina-100Mbp/10"] = ent
         del d
+    if "gapped" in which:
+        d = datagen.workload_gapped()
+        log("gapped workload generated")
+        ent, _ = seed_entry(d, "10")
+        table["illumina-gapped-100Mbp/10"] = ent
+        del d
     if "uneven" in which or "lookups" in which:
         d = datagen.workload_uneven()
         log("uneven workload generated")
@@ -156,4 +164,4 @@ if __name__ == "__main__":
     if args[:1] == ["--out"]:
         OUT = args[1]
         args = args[2:]
-    main(set(args or ["illumina", "uneven", "lookups", "containment"]))
+    main(set(args or ["illumina", "gapped", "uneven", "lookups", "containment"]))

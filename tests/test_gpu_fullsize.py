@@ -6,7 +6,8 @@ part that differs when a check fails.
 
   * Illumina-like 100 Mbp reference, 1M x 150 bp reads, '10', k21 w11: the benchmark's
     own preallocated step (index build + seeding), with binary search and with the
-    learned index, then location voting on its anchors (D 16, V 3, 4 winners);
+    learned index, then location voting on its anchors (D 16, V 3, 4 winners); the same
+    with assembly gaps (about 5 % N) in the reference and N calls in the reads;
   * 1 Gbp reference with one mixed batch of 2M short + 20k HiFi-like + 20k ONT-like reads,
     '10' and '110': index build, then one HIP-graph-captured seeding pass with launch
     parameters from the autotuner, then location voting (D 100, V 3, 4 winners);
@@ -77,6 +78,28 @@ def test_illumina_100mbp_benchmark_step(gpu, golden):
         a = s.anchors[:4 * na].cpu().numpy().view(np.uint32)
         got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
         assert_digest(got, exp["anchors"], "anchors (learned index %s)" % learned)
+    check_votes(gpu, s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, exp["votes"])
+
+
+@pytest.mark.timeout(900)
+def test_illumina_gapped_100mbp_benchmark_step(gpu, golden):
+    # the same step on the workload with assembly gaps and N calls (N-aware path)
+    import bench
+    exp = want(golden, "illumina-gapped-100Mbp/10")
+    d = datagen.workload_gapped()
+    s = bench.Session(gpu, d, "10", K, W)
+    del d
+    assert s.ref.nmask is not None and s.reads.nmask is not None
+    for mode in ("binary_search", "learned_index"):
+        s.step(mode)
+        s.check()
+        n = s.n_index
+        got = fullsize.index_digest(host_u64(s.ikeys[:n]), host_vals(s.ivals[:n]))
+        assert_digest(got, exp["index"], "index")
+        na = s.n_anchors
+        a = s.anchors[:4 * na].cpu().numpy().view(np.uint32)
+        got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
+        assert_digest(got, exp["anchors"], "anchors (%s)" % mode)
     check_votes(gpu, s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, exp["votes"])
 
 
