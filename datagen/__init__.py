@@ -285,6 +285,23 @@ def workload_gapped(ref_len=100_000_000, n_reads=1_000_000):
     return d
 
 
+def workload_fig4(n_pairs=100_000, length=1000, max_rate=0.6, seed=5):
+    """Seed-matching experiment: n_pairs sequences of `length` bases cut from an i.i.d.
+    genome, each with a copy in which every base is substituted (by one of the three
+    other bases) with a per-pair probability drawn uniformly from [0, max_rate], so the
+    pairs span the whole range of differences.  Returns (original codes, offsets, copy
+    codes, offsets, substitutions per pair)."""
+    rng = np.random.default_rng(seed)
+    orig = random_genome(n_pairs * length, seed)
+    rate = rng.random(n_pairs) * max_rate
+    hit = rng.random((n_pairs, length)) < rate[:, None]
+    copy = orig.reshape(n_pairs, length).copy()
+    n_hit = int(hit.sum())
+    copy[hit] = (copy[hit] + rng.integers(1, 4, n_hit, dtype=np.uint8)) % 4
+    offs = np.arange(0, (n_pairs + 1) * length, length, dtype=np.int64)
+    return orig, offs, copy.reshape(-1), offs.copy(), hit.sum(axis=1).astype(np.int64)
+
+
 def workload_uneven(ref_len=1_000_000_000, n_short=2_000_000, n_hifi=20_000, n_ont=20_000):
     """1 Gbp reference (same repeat model); one mixed batch of short, HiFi-like and
     ONT-like reads; patterns '10' and '110'; k=21, w=11."""

@@ -73,6 +73,12 @@ def lib():
         L.gdo_wang64.argtypes = [u64, i32]
         L.gdo_wang64.restype = u64
         L.gdo_set_hash.argtypes = [i32]
+        L.gdo_seed_match.argtypes = [P, P, P, P, u32, ctypes.c_char_p, i32, i32, P]
+        L.gdo_seed_match.restype = i32
+        L.gdo_edit_distance.argtypes = [P, u64, P, u64]
+        L.gdo_edit_distance.restype = u64
+        L.gdo_accepted.argtypes = [P, P, P, u32, u32, P]
+        L.gdo_accepted.restype = None
         L.gdo_set_hash.restype = i32
         _lib = L
     return _lib
@@ -222,3 +228,36 @@ class use_hash:
     def __exit__(self, *exc):
         lib().gdo_set_hash(0)
         return False
+
+
+FIG4_ALGORITHMS = ("all", "minimizers", "spaced", "god")
+
+
+def seed_match(codes_a, offs_a, codes_b, offs_b, pattern, k, w):
+    """Seed matching of pairs (sequence i of a = original, of b = mutated copy): uint32
+    array (n_pairs, 4, 2) of (matched seeds of the copy, seeds of the copy) for the
+    algorithms FIG4_ALGORITHMS."""
+    ca, oa = _codes(codes_a, offs_a)
+    cb, ob = _codes(codes_b, offs_b)
+    n = oa.size - 1
+    if ob.size - 1 != n:
+        raise ValueError("both batches need the same number of sequences")
+    out = np.zeros((max(n, 1), 4, 2), np.uint32)
+    _check(lib().gdo_seed_match(_ptr(ca), _ptr(oa), _ptr(cb), _ptr(ob), n, pattern.encode(),
+                                k, w, _ptr(out)), "seed_match")
+    return out[:n]
+
+
+def edit_distance(a, b):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    return int(lib().gdo_edit_distance(_ptr(a), a.size, _ptr(b), b.size))
+
+
+def accepted(dist, matched, total, max_e):
+    d = np.ascontiguousarray(dist, dtype=np.uint32)
+    m = np.ascontiguousarray(matched, dtype=np.uint32)
+    t = np.ascontiguousarray(total, dtype=np.uint32)
+    out = np.zeros(max_e + 1, np.uint32)
+    lib().gdo_accepted(_ptr(d), _ptr(m), _ptr(t), d.size, max_e, _ptr(out))
+    return out

@@ -559,3 +559,142 @@ int64_t gdo_vote(const uint32_t *anchors, const uint64_t *read_off, uint32_t n_r
     }
     return total;
 }
+
+/* ---------------------------------------------------------------------------------
+ * Seed-matching experiment (Section 2.1.1, Fig. 4): a sequence and a copy with random
+ * substitutions; four seeding algorithms; seed matching rates and edit distance.
+ *
+ * Readings (the program itself is not in the paper):
+ *   - a seed is identified by the canonical code of its base string (the string and its
+ *     reverse complement are one seed); minimizer and Genome-on-Diet seeds by their hash,
+ *     which is a bijection of that code;
+ *   - all seeds: every k-mer; minimizers: the sketch with pattern '1'; Genome-on-Diet:
+ *     the sketch of the patterned sequence (shift 0); spaced seeds: at every start i the
+ *     bases i + j with M[j] == 1, M = the pattern repeated to span k (a pattern of
+ *     length k is used as it is);
+ *   - matching rate = (seeds of the copy, with multiplicity, found among the original's
+ *     seeds) / (seeds of the copy); a copy without seeds has rate 0.
+ * ------------------------------------------------------------------------------- */
+
+static uint64_t canon_code(const uint8_t *s, int n)
+{
+    uint64_t f = 0, r = 0;
+    for (int t = 0; t < n; t++) f = f * 4 + s[t];
+    for (int t = 0; t < n; t++) r = r * 4 + (uint64_t)(3 - s[n - 1 - t]);
+    return f < r ? f : r;
+}
+
+static int u64_cmp_plain(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Seeds of one sequence under algorithm alg (0 all, 1 minimizers, 2 spaced, 3
+ * Genome-on-Diet), appended to out[]; returns their number or a negative error. */
+static int64_t fig4_seeds(const uint8_t *S, uint64_t L, int alg, const gdo_pattern *P, int k,
+                          int w, uint64_t *out)
+{
+    if (alg == 0 || alg == 2) {
+        if (L < (uint64_t)k) return 0;
+        uint8_t buf[32];
+        for (uint64_t i = 0; i + (uint64_t)k <= L; i++) {
+            int n = 0;
+            for (int j = 0; j < k; j++)
+                if (alg == 0 || P->bit[j % P->p]) buf[n++] = S[i + (uint64_t)j];
+            out[i] = canon_code(buf, n);
+        }
+        return (int64_t)(L - (uint64_t)k + 1);
+    }
+    gdo_pattern one;
+    one.p = 1; one.x = 1; one.bit[0] = 1;
+    uint64_t *vals = (uint64_t *)malloc((L + 1) * sizeof(uint64_t));
+    if (!vals) return GDO_ENOMEM;
+    int64_t n = sketch_one(S, L, alg == 1 ? &one : P, 0, k, w, out, vals, L + 1);
+    free(vals);
+    return n;
+}
+
+/* For every pair i (sequence i of a = the original, of b = the mutated copy) and every
+ * algorithm g: out[8i + 2g] = matched seeds of the copy, out[8i + 2g + 1] = seeds of the
+ * copy.  Codes must be 0..3. */
+int gdo_seed_match(const uint8_t *ca, const uint64_t *oa, const uint8_t *cb, const uint64_t *ob,
+                   uint32_t n_pairs, const char *pattern, int k, int w, uint32_t *out)
+{
+    gdo_pattern P;
+    if (parse_pattern(pattern, &P) != GDO_OK || k < 1 || k > 32 || w < 1) return GDO_EINVAL;
+    for (uint32_t i = 0; i < n_pairs; i++) {
+        const uint64_t la = oa[i + 1] - oa[i], lb = ob[i + 1] - ob[i];
+        for (uint64_t j = 0; j < la; j++) if (ca[oa[i] + j] > 3) return GDO_EINVAL;
+        for (uint64_t j = 0; j < lb; j++) if (cb[ob[i] + j] > 3) return GDO_EINVAL;
+        uint64_t *sa = (uint64_t *)malloc((la + 1) * sizeof(uint64_t));
+        uint64_t *sb = (uint64_t *)malloc((lb + 1) * sizeof(uint64_t));
+        if (!sa || !sb) { free(sa); free(sb); return GDO_ENOMEM; }
+        for (int g = 0; g < 4; g++) {
+            int64_t na = fig4_seeds(ca + oa[i], la, g, &P, k, w, sa);
+            int64_t nb = fig4_seeds(cb + ob[i], lb, g, &P, k, w, sb);
+            if (na < 0 || nb < 0) { free(sa); free(sb); return GDO_ENOMEM; }
+            qsort(sa, (size_t)na, sizeof(uint64_t), u64_cmp_plain);
+            uint32_t hit = 0;
+            for (int64_t t = 0; t < nb; t++)
+                if (na > 0 && bsearch(&sb[t], sa, (size_t)na, sizeof(uint64_t), u64_cmp_plain))
+                    hit++;
+            out[8 * (uint64_t)i + 2 * g] = hit;
+            out[8 * (uint64_t)i + 2 * g + 1] = (uint32_t)nb;
+        }
+        free(sa);
+        free(sb);
+    }
+    return GDO_OK;
+}
+
+/* Levenshtein distance (unit-cost substitutions, insertions and deletions) by its
+ * recurrence D[i][j] = min(D[i-1][j] + 1, D[i][j-1] + 1, D[i-1][j-1] + [a_i != b_j]),
+ * row by row. */
+uint64_t gdo_edit_distance(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_t lb)
+{
+    uint64_t *prev = (uint64_t *)malloc((lb + 1) * sizeof(uint64_t));
+    uint64_t *cur = (uint64_t *)malloc((lb + 1) * sizeof(uint64_t));
+    if (!prev || !cur) { free(prev); free(cur); return UINT64_MAX; }
+    for (uint64_t j = 0; j <= lb; j++) prev[j] = j;
+    for (uint64_t i = 1; i <= la; i++) {
+        cur[0] = i;
+        for (uint64_t j = 1; j <= lb; j++) {
+            uint64_t d = prev[j - 1] + (a[i - 1] != b[j - 1] ? 1 : 0);
+            if (prev[j] + 1 < d) d = prev[j] + 1;
+            if (cur[j - 1] + 1 < d) d = cur[j - 1] + 1;
+            cur[j] = d;
+        }
+        uint64_t *t = prev; prev = cur; cur = t;
+    }
+    uint64_t r = prev[lb];
+    free(prev);
+    free(cur);
+    return r;
+}
+
+/* Accepted sequence pairs (Section 2.1.2): for every edit-distance threshold E in
+ * [0, max_e], the seed-matching-rate threshold is the smallest rate among pairs with
+ * distance <= E, and accepted[E] counts the pairs whose rate reaches it (0 when no pair
+ * is that close).  Rates matched/total are compared as exact fractions (total 0 counts
+ * as rate 0). */
+void gdo_accepted(const uint32_t *dist, const uint32_t *matched, const uint32_t *total,
+                  uint32_t n, uint32_t max_e, uint32_t *accepted)
+{
+    for (uint32_t E = 0; E <= max_e; E++) {
+        int have = 0;
+        uint64_t tm = 0, tt = 1;                     /* threshold fraction tm / tt */
+        for (uint32_t i = 0; i < n; i++) {
+            if (dist[i] > E) continue;
+            uint64_t m = total[i] ? matched[i] : 0, t = total[i] ? total[i] : 1;
+            if (!have || m * tt < tm * t) { tm = m; tt = t; have = 1; }
+        }
+        uint32_t c = 0;
+        if (have)
+            for (uint32_t i = 0; i < n; i++) {
+                uint64_t m = total[i] ? matched[i] : 0, t = total[i] ? total[i] : 1;
+                if (m * tt >= tm * t) c++;
+            }
+        accepted[E] = c;
+    }
+}

@@ -108,3 +108,41 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, t=0, max_occ=0):
             for iv in sorted(hits):
                 out.append((r, val >> 1, iv >> 1, (val ^ iv) & 1))
     return out, shifts
+
+
+def canonical(bases):
+    return min(numeral(bases), numeral([3 - b for b in reversed(bases)]))
+
+
+def fig4_seeds(seq, alg, pattern, k, w):
+    """Seed identities of one sequence for the seed-matching experiment: all k-mers,
+    minimizers, spaced seeds (pattern repeated to span k) or Genome-on-Diet minimizers."""
+    seq = [int(b) for b in seq]
+    if alg == "all":
+        return [canonical(seq[i:i + k]) for i in range(len(seq) - k + 1)]
+    if alg == "spaced":
+        mask = [pattern[j % len(pattern)] == "1" for j in range(k)]
+        return [canonical([seq[i + j] for j in range(k) if mask[j]])
+                for i in range(len(seq) - k + 1)]
+    return [key for key, _ in sketch(seq, "1" if alg == "minimizers" else pattern, 0, k, w)]
+
+
+def seed_match(orig, copy, alg, pattern, k, w):
+    stored = set(fig4_seeds(orig, alg, pattern, k, w))
+    seeds = fig4_seeds(copy, alg, pattern, k, w)
+    return sum(1 for s in seeds if s in stored), len(seeds)
+
+
+def edit_distance(a, b):
+    """Levenshtein distance by plain recursion with memoisation (tiny inputs only)."""
+    from functools import lru_cache
+
+    @lru_cache(maxsize=None)
+    def d(i, j):
+        if i == 0:
+            return j
+        if j == 0:
+            return i
+        return min(d(i - 1, j) + 1, d(i, j - 1) + 1, d(i - 1, j - 1) + (a[i - 1] != b[j - 1]))
+
+    return d(len(a), len(b))

@@ -65,6 +65,13 @@ MUTANTS = [
      "key = (~key + (key << 21));"),
     ("N does not end a run", "if (i < n && PS[i] != 4) continue;", "if (i < n) continue;"),
     ("run restarts at the N instead of after it", "        r0 = i + 1;", "        r0 = i;"),
+    ("edit distance: free substitutions", "uint64_t d = prev[j - 1] + (a[i - 1] != b[j - 1] ? 1 : 0);",
+     "uint64_t d = prev[j - 1];"),
+    ("spaced-seed mask off by one", "if (alg == 0 || P->bit[j % P->p]) buf[n++]",
+     "if (alg == 0 || P->bit[(j + 1) % P->p]) buf[n++]"),
+    ("minimizers sketched with the pattern", "alg == 1 ? &one : P", "P"),
+    ("accepted pairs need a strictly higher rate", "if (m * tt >= tm * t) c++;",
+     "if (m * tt > tm * t) c++;"),
     ("containment counts every genome hash",
      "if (bsearch(&gh[i].val, sample, (size_t)nu, sizeof(uint64_t), u64_cmp)) counts[g]++;",
      "if (1) counts[g]++;"),

@@ -587,3 +587,89 @@ def test_n_seed_matches_brute_force(pattern, k, w):
     exp, exp_sh = brute.seed(index, [r.tolist() for r in reads], pattern, k, w)
     assert [tuple(x) for x in a.tolist()] == exp and sh.tolist() == exp_sh
     assert len(exp) > 20
+
+
+# ---------------------------------------------------------------- seed-matching experiment
+
+def test_edit_distance_matches_recursion():
+    rng = np.random.default_rng(50)
+    for _ in range(300):
+        a = rng.integers(0, 4, int(rng.integers(0, 8)), dtype=np.uint8)
+        b = rng.integers(0, 4, int(rng.integers(0, 8)), dtype=np.uint8)
+        assert oracle.edit_distance(a, b) == brute.edit_distance(tuple(a), tuple(b))
+
+
+def test_edit_distance_properties():
+    rng = np.random.default_rng(51)
+    for _ in range(40):
+        a = rng.integers(0, 4, int(rng.integers(0, 300)), dtype=np.uint8)
+        b = rng.integers(0, 4, int(rng.integers(0, 300)), dtype=np.uint8)
+        c = rng.integers(0, 4, int(rng.integers(0, 300)), dtype=np.uint8)
+        dab = oracle.edit_distance(a, b)
+        assert oracle.edit_distance(a, a) == 0
+        assert dab == oracle.edit_distance(b, a)
+        assert abs(a.size - b.size) <= dab <= max(a.size, b.size)
+        assert oracle.edit_distance(a, c) <= dab + oracle.edit_distance(b, c)
+        if a.size:
+            i = int(rng.integers(0, a.size))
+            assert oracle.edit_distance(a, np.delete(a, i)) == 1
+            s = a.copy()
+            s[i] = (s[i] + 1) % 4
+            assert oracle.edit_distance(a, s) == 1
+            m = a.copy()
+            pos = rng.choice(a.size, min(a.size, 30), replace=False)
+            m[pos] = (m[pos] + rng.integers(1, 4, pos.size)) % 4
+            assert oracle.edit_distance(a, m) <= pos.size      # at most the Hamming distance
+
+
+FIG4 = [("110", 8, 6), ("10", 8, 6), ("101001", 8, 6), ("100", 8, 6), ("10", 13, 9),
+        ("1110110110111", 13, 9), ("111001011001010111", 18, 12), ("10", 21, 11)]
+
+
+@pytest.mark.parametrize("pattern,k,w", FIG4)
+def test_seed_match_matches_brute_force(pattern, k, w):
+    rng = np.random.default_rng(k * 7 + len(pattern))
+    pairs = []
+    for L in (0, k - 1, k, 60, 200, 200):
+        a = rng.integers(0, 4, L, dtype=np.uint8)
+        b = a.copy()
+        if L:
+            pos = rng.choice(L, int(rng.integers(0, L // 3 + 1)), replace=False)
+            b[pos] = (b[pos] + rng.integers(1, 4, pos.size)) % 4
+        pairs.append((a, b))
+    ca, oa = datagen.concat([(a, [0, a.size]) for a, _ in pairs])
+    cb, ob = datagen.concat([(b, [0, b.size]) for _, b in pairs])
+    got = oracle.seed_match(ca, oa, cb, ob, pattern, k, w)
+    for i, (a, b) in enumerate(pairs):
+        for g, alg in enumerate(oracle.FIG4_ALGORITHMS):
+            assert tuple(got[i, g]) == brute.seed_match(a, b, alg, pattern, k, w), (i, alg)
+
+
+def test_seed_match_identity_and_reductions():
+    rng = np.random.default_rng(52)
+    a = rng.integers(0, 4, 1000, dtype=np.uint8)
+    b = a.copy()
+    b[rng.choice(1000, 150, replace=False)] = rng.integers(0, 4, 150)
+    o = [0, 1000]
+    same = oracle.seed_match(a, o, a, o, "101001", 8, 6)[0]
+    assert np.array_equal(same[:, 0], same[:, 1])             # every seed matches itself
+    assert same[0, 1] == same[2, 1] == 1000 - 8 + 1            # all and spaced: every start
+    one = oracle.seed_match(a, o, b, o, "1", 8, 6)[0]
+    assert np.array_equal(one[0], one[2])                     # spaced with '1' = all seeds
+    assert np.array_equal(one[1], one[3])                     # GoD with '1' = minimizers
+
+
+def test_accepted_pairs_by_definition():
+    from fractions import Fraction
+    rng = np.random.default_rng(53)
+    n = 300
+    dist = rng.integers(0, 60, n).astype(np.uint32)
+    total = rng.integers(0, 50, n).astype(np.uint32)
+    matched = (total * rng.random(n)).astype(np.uint32)
+    got = oracle.accepted(dist, matched, total, 70)
+    rate = [Fraction(int(m), int(t)) if t else Fraction(0) for m, t in zip(matched, total)]
+    for E in range(71):
+        close = [rate[i] for i in range(n) if dist[i] <= E]
+        want = sum(1 for r in rate if r >= min(close)) if close else 0
+        assert got[E] == want
+    assert got[-1] == n                                       # every pair is close enough
