@@ -316,6 +316,43 @@ size_t godiet_trace_dump(char *buf, size_t len);
  * prefix; NULL or "" traces every kernel again.  The string is copied. */
 void godiet_trace_filter(const char *prefix);
 
+/* ---- Seed-matching experiment (Section 2.1.1, Fig. 4; Section 2.1.2) ----------------
+ * Pairs: sequence i of `orig` and sequence i of `copy` (a copy with substitutions), each
+ * at most 1,024 bases, no N mask.  Four seeding algorithms, in this order:
+ *   0 all seeds: every k-mer;  1 minimizers: (w,k)-minimizers (pattern '1');
+ *   2 spaced seeds: at every start i the bases i + j with M[j] == '1', M = the pattern
+ *     repeated to span k (a pattern of length k as it is);
+ *   3 Genome-on-Diet: (w,k)-minimizers of the patterned sequence (shift 0).
+ * A seed is identified by the canonical code of its bases (a string and its reverse
+ * complement are one seed); minimizer seeds by their hash (prm->hash), a bijection of
+ * that code.  The matching rate of a pair is (seeds of the copy, with multiplicity,
+ * present among the original's seeds) / (seeds of the copy). */
+#define GODIET_FIG4_ALGORITHMS 4
+
+/* counts[8i + 2g] = matched seeds of the copy, counts[8i + 2g + 1] = seeds of the copy,
+ * for pair i and algorithm g.  n_seq of both batches must be equal.  A pair longer than
+ * 1,024 bases gets zeros and sets GODIET_ST_RANGE. */
+godiet_status godiet_seed_match(const godiet_seqs *orig, const godiet_seqs *copy,
+                                const godiet_sketch_params *prm, uint32_t *counts,
+                                uint32_t *status, hipStream_t stream);
+
+/* Levenshtein distance (unit-cost substitution, insertion, deletion) of every pair into
+ * dist[i]; the original may have at most 1,024 bases (else 0 and GODIET_ST_RANGE). */
+godiet_status godiet_edit_distance(const godiet_seqs *orig, const godiet_seqs *copy,
+                                   uint32_t *dist, uint32_t *status, hipStream_t stream);
+
+/* [host] Workspace bytes of godiet_accepted_pairs for thresholds 0..max_e. */
+size_t godiet_accepted_ws_size(uint32_t max_e);
+
+/* Accepted sequence pairs (Section 2.1.2) for algorithm g: for every edit-distance
+ * threshold E in [0, max_e], the rate threshold is the smallest matching rate among the
+ * pairs with dist <= E, and accepted[E] is the number of pairs whose rate reaches it (0
+ * when no pair has dist <= E).  dist and counts as written by the two calls above;
+ * rates are compared exactly (totals stay below 2^16). */
+godiet_status godiet_accepted_pairs(const uint32_t *dist, const uint32_t *counts, uint32_t n_pairs,
+                                    int32_t g, uint32_t max_e, uint32_t *accepted, void *ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,14 @@ def lib():
         L.godiet_sparsify_bytes.restype = sz
         L.godiet_sparsify.argtypes = [S(Seqs), ctypes.c_char_p, P, P, P, P, P, sz, P, P]
         L.godiet_sparsify.restype = i32
+        L.godiet_seed_match.argtypes = [S(Seqs), S(Seqs), S(Params), P, P, P]
+        L.godiet_seed_match.restype = i32
+        L.godiet_edit_distance.argtypes = [S(Seqs), S(Seqs), P, P, P]
+        L.godiet_edit_distance.restype = i32
+        L.godiet_accepted_ws_size.argtypes = [u32]
+        L.godiet_accepted_ws_size.restype = sz
+        L.godiet_accepted_pairs.argtypes = [P, P, u32, i32, u32, P, P, sz, P]
+        L.godiet_accepted_pairs.restype = i32
         L.godiet_pack_bytes.argtypes = [u64]
         L.godiet_pack_bytes.restype = sz
         L.godiet_pack_ascii.argtypes = [P, u64, P, P, P]
@@ -505,3 +513,53 @@ def winners_rows(winners, n_win):
     r, j = np.nonzero(idx)
     return np.stack([w[r, j, 2].astype(np.int64), w[r, j, 3].astype(np.int64),
                      w[r, j, 4].astype(np.int64), w[r, j, 5].astype(np.int64), loc[r, j]], 1)
+
+
+FIG4_ALGORITHMS = ("all", "minimizers", "spaced", "god")
+
+
+def seed_match(orig, copy, pattern, k, w, hash="splitmix64"):
+    """Seed-matching experiment over pairs (sequence i of orig, sequence i of copy): int32
+    tensor (n_pairs, 4, 2) of (matched seeds of the copy, seeds of the copy) for the
+    algorithms FIG4_ALGORITHMS."""
+    torch = _torch()
+    if orig.n_seq != copy.n_seq:
+        raise ValueError("both batches need the same number of sequences")
+    a, b = orig.c(), copy.c()
+    counts = _empty(8 * orig.n_seq, torch.int32)
+    st = _empty(1, torch.int32)
+    _check(lib().godiet_seed_match(ctypes.byref(a), ctypes.byref(b),
+                                   ctypes.byref(_params(pattern, k, w, hash)), _ptr(counts),
+                                   _ptr(st), _stream()), "godiet_seed_match")
+    if _status_value(st) & STATUS_RANGE:
+        raise ValueError("a sequence of a pair is longer than 1,024 bases")
+    return counts[:8 * orig.n_seq].view(orig.n_seq, 4, 2)
+
+
+def edit_distance(orig, copy):
+    """Levenshtein distance of every pair: int32 tensor (n_pairs)."""
+    torch = _torch()
+    if orig.n_seq != copy.n_seq:
+        raise ValueError("both batches need the same number of sequences")
+    a, b = orig.c(), copy.c()
+    dist = _empty(orig.n_seq, torch.int32)
+    st = _empty(1, torch.int32)
+    _check(lib().godiet_edit_distance(ctypes.byref(a), ctypes.byref(b), _ptr(dist), _ptr(st),
+                                      _stream()), "godiet_edit_distance")
+    if _status_value(st) & STATUS_RANGE:
+        raise ValueError("an original sequence is longer than 1,024 bases")
+    return dist[:orig.n_seq]
+
+
+def accepted_pairs(dist, counts, algorithm, max_e):
+    """Accepted pairs per edit-distance threshold 0..max_e for one algorithm (name or
+    index): int32 tensor (max_e + 1)."""
+    torch = _torch()
+    g = FIG4_ALGORITHMS.index(algorithm) if isinstance(algorithm, str) else int(algorithm)
+    n = dist.numel()
+    L = lib()
+    ws = _empty(L.godiet_accepted_ws_size(max_e), torch.uint8)
+    acc = _empty(max_e + 1, torch.int32)
+    _check(L.godiet_accepted_pairs(_ptr(dist), _ptr(counts), n, g, max_e, _ptr(acc), _ptr(ws),
+                                   ws.numel(), _stream()), "godiet_accepted_pairs")
+    return acc[:max_e + 1]

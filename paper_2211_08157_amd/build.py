@@ -9,7 +9,8 @@ LIB = os.path.join(HERE, "libgodiet.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["gd_api.hip", "gd_scan.hip", "gd_sketch.hip", "gd_sort.hip", "gd_seed.hip",
-           "gd_trace.hip", "gd_rmi.hip", "gd_contain.hip", "gd_vote.hip", "gd_table.hip"]
+           "gd_trace.hip", "gd_rmi.hip", "gd_contain.hip", "gd_vote.hip", "gd_table.hip",
+           "gd_fig4.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

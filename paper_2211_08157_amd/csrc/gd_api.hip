@@ -325,6 +325,46 @@ godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const 
     return GODIET_OK;
 }
 
+godiet_status godiet_seed_match(const godiet_seqs *orig, const godiet_seqs *copy,
+                                const godiet_sketch_params *prm, uint32_t *counts,
+                                uint32_t *status, hipStream_t stream)
+{
+    Pattern P;
+    if (!valid_seqs(orig) || !valid_seqs(copy) || !valid_params(prm, &P) || !status)
+        return GODIET_E_INVAL;
+    if (orig->n_seq != copy->n_seq || (orig->n_seq > 0 && !counts)) return GODIET_E_INVAL;
+    if (orig->nmask || copy->nmask) return GODIET_E_UNSUPPORTED;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(launch_seed_match(orig, copy, P, prm->k, prm->w, prm->hash, counts, status, stream));
+    return GODIET_OK;
+}
+
+godiet_status godiet_edit_distance(const godiet_seqs *orig, const godiet_seqs *copy,
+                                   uint32_t *dist, uint32_t *status, hipStream_t stream)
+{
+    if (!valid_seqs(orig) || !valid_seqs(copy) || !status) return GODIET_E_INVAL;
+    if (orig->n_seq != copy->n_seq || (orig->n_seq > 0 && !dist)) return GODIET_E_INVAL;
+    if (orig->nmask || copy->nmask) return GODIET_E_UNSUPPORTED;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(launch_edit_distance(orig, copy, dist, status, stream));
+    return GODIET_OK;
+}
+
+size_t godiet_accepted_ws_size(uint32_t max_e) { return ((size_t)max_e + 1) * 8 + 256; }
+
+godiet_status godiet_accepted_pairs(const uint32_t *dist, const uint32_t *counts, uint32_t n_pairs,
+                                    int32_t g, uint32_t max_e, uint32_t *accepted, void *ws,
+                                    size_t ws_bytes, hipStream_t stream)
+{
+    if (g < 0 || g >= GODIET_FIG4_ALGORITHMS || !accepted || max_e >= (1u << 24))
+        return GODIET_E_INVAL;
+    if (n_pairs > 0 && (!dist || !counts)) return GODIET_E_INVAL;
+    if (!ws || ws_bytes < godiet_accepted_ws_size(max_e) || ((uintptr_t)ws & 7) != 0)
+        return GODIET_E_WORKSPACE;
+    GD_TRY(launch_accepted(dist, counts, n_pairs, g, max_e, (uint64_t *)ws, accepted, stream));
+    return GODIET_OK;
+}
+
 size_t godiet_pack_bytes(uint64_t n_chars) { return (size_t)((n_chars + 63) / 64) * 16; }
 
 godiet_status godiet_pack_ascii(const char *text, uint64_t n_chars, uint8_t *bases,

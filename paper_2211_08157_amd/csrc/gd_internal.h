@@ -196,4 +196,12 @@ hipError_t launch_contain(const AlignArgs &a, const uint32_t *shift_slot, const 
                           const uint64_t *ivals, uint64_t in, uint8_t *mark, uint32_t n_genomes,
                           uint32_t *counts, uint32_t *sizes, uint32_t *status, hipStream_t s);
 
+// ---- seed-matching experiment (gd_fig4.hip) ----
+hipError_t launch_seed_match(const godiet_seqs *a, const godiet_seqs *b, const Pattern &P, int k,
+                             int w, int hash, uint32_t *counts, uint32_t *status, hipStream_t s);
+hipError_t launch_edit_distance(const godiet_seqs *a, const godiet_seqs *b, uint32_t *dist,
+                                uint32_t *status, hipStream_t s);
+hipError_t launch_accepted(const uint32_t *dist, const uint32_t *counts, uint32_t n, int g,
+                           uint32_t max_e, uint64_t *minkey, uint32_t *acc, hipStream_t s);
+
 }  // namespace gd

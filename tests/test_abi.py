@@ -193,3 +193,22 @@ def test_pack_n_bit_layout():
     assert words.size == 4                               # 64 bits per 64 bases, padded
     got = [i for i in range(128) if (words[i // 32] >> (i % 32)) & 1]
     assert got == [0, 5, 31, 32, 63, 69]
+
+
+def test_seed_match_host_checks():
+    from paper_2211_08157_amd.api import Params, Seqs
+    L = _lib()
+    prm = Params(b"10", 8, 6, 0)
+    a = Seqs(0x1000, 0x2000, 3, 3000)
+    b = Seqs(0x1000, 0x2000, 4, 4000)
+    with_n = Seqs(0x1000, 0x2000, 3, 3000, 0x3000)
+    assert L.godiet_seed_match(ctypes.byref(a), ctypes.byref(b), ctypes.byref(prm), 0x4000,
+                               0x5000, None) == -1                # pair counts differ
+    assert L.godiet_seed_match(ctypes.byref(a), ctypes.byref(with_n), ctypes.byref(prm), 0x4000,
+                               0x5000, None) == -5                # N masks unsupported
+    assert L.godiet_edit_distance(ctypes.byref(a), ctypes.byref(a), None, 0x5000, None) == -1
+    assert L.godiet_accepted_ws_size(99) == 100 * 8 + 256
+    assert L.godiet_accepted_pairs(0x1000, 0x2000, 10, 4, 99, 0x3000, 0x4000, 2000,
+                                   None) == -1                    # algorithm 4 does not exist
+    assert L.godiet_accepted_pairs(0x1000, 0x2000, 10, 0, 99, 0x3000, 0x4000, 100,
+                                   None) == -3                    # workspace too small
