@@ -259,6 +259,65 @@ def gapped_step(gd, torch, steps, warmup):
                 pack_ascii_bytes_rule="text in + 2-bit codes + N bits out", kernels=kernels)
 
 
+FIG4_SETTINGS = [("10", 8, 6), ("100", 8, 6), ("1110110110111", 13, 9), ("10", 21, 11)]
+
+
+def fig4_experiment(gd, torch, reps=3, cpu=True):
+    """Seed-matching experiment on 100,000 pairs of 1,000 bases: device time of the seed
+    counts (four algorithms) per setting, of the edit distances and of the accepted-pairs
+    curves; the oracle on a sample of pairs for comparison."""
+    import datagen
+    o, oo, c, co, _ = datagen.workload_fig4()
+    n = oo.size - 1
+    so, sc = gd.to_device(o, oo), gd.to_device(c, co)
+    out = dict(workload="fig4-100k: 100,000 pairs of 1,000 bases, per-pair substitution "
+                        "rate uniform in [0, 0.6]", pairs=n)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        gd.trace_dump()
+        gd.trace_enable(True)
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        gd.trace_enable(False)
+        tr = gd.trace_dump()
+        return r, {kn: v[1] / reps for kn, v in tr.items() if not kn.startswith("k_fill")}
+
+    dist, kt = timed(lambda: gd.edit_distance(so, sc))
+    ms = sum(kt.values())
+    out["edit_distance"] = dict(ms=ms, pairs_per_s=n / (ms * 1e-3),
+                                cells_per_s=1000.0 * 1000.0 * n / (ms * 1e-3))
+    max_e = int(dist.max().item())
+    out["seed_match"] = {}
+    for pattern, k, w in FIG4_SETTINGS:
+        counts, kt = timed(lambda: gd.seed_match(so, sc, pattern, k, w))
+        ms = sum(kt.values())
+        flat = counts.reshape(-1)
+        _, ka = timed(lambda: [gd.accepted_pairs(dist, flat, g, max_e) for g in range(4)])
+        accepted = {alg: gd.accepted_pairs(dist, flat, alg, max_e).cpu().numpy()
+                    for alg in gd.FIG4_ALGORITHMS}
+        out["seed_match"]["%s/%d/%d" % (pattern, k, w)] = dict(
+            ms=ms, pairs_per_s=n / (ms * 1e-3), accepted_curves_ms=sum(ka.values()),
+            accepted_fraction_at_ed_138={a: float(v[min(138, max_e)]) / n
+                                        for a, v in accepted.items()})
+    if cpu:
+        import oracle
+        m = 500
+        t0 = time.perf_counter()
+        oracle.seed_match(o[:oo[m]], oo[:m + 1], c[:co[m]], co[:m + 1], "10", 8, 6)
+        t1 = time.perf_counter()
+        for i in range(m // 5):
+            oracle.edit_distance(o[oo[i]:oo[i + 1]], c[co[i]:co[i + 1]])
+        t2 = time.perf_counter()
+        out["cpu_oracle"] = dict(seed_match_pairs_per_s=m / (t1 - t0),
+                                 edit_distance_pairs_per_s=(m // 5) / (t2 - t1), cores=1,
+                                 sample="first 500 pairs (seed counts, 10/8/6), first 100 "
+                                        "pairs (edit distance)")
+    return out
+
+
 def cpu_baseline(data, pattern, k, w, sample_reads):
     """The oracle on the host: index build (one call), then seeding of a bounded sample of
     reads split over threads by read ranges (each read's anchors are independent; the
@@ -526,6 +585,10 @@ def main():
     gapped = gapped_step(gd, torch, args.steps, args.warmup)
     log("[bench] gapped workload: %.3f ms/step, %.3e reads/s; text packing %.1f GB/s"
         % (gapped["ms_per_step"], gapped["reads_per_s"], gapped["pack_ascii_GBps"]))
+    fig4 = fig4_experiment(gd, torch, cpu=not args.no_cpu_baseline)
+    log("[bench] seed-matching experiment: edit distance %.3f ms (%.2e cells/s), seed counts "
+        "10/8/6 %.3f ms" % (fig4["edit_distance"]["ms"], fig4["edit_distance"]["cells_per_s"],
+                            fig4["seed_match"]["10/8/6"]["ms"]))
     lookup_gather = gather_rate(torch, s.n_index, s.queries)
     gbps, sk_ms, sk_m, sk_kernels = sketch_gbps(gd, torch, s.ref, pattern, k, w)
     log("[bench] reference sketch %.3f ms, %.1f GB/s" % (sk_ms, gbps))
@@ -587,6 +650,7 @@ def main():
         "sketch_1Gbp": sketch_1g,
         "location_voting": vote,
         "n_aware_step": gapped,
+        "seed_matching_experiment": fig4,
         "uneven_batch_1Gbp": uneven,
         "measured_copy_GBps": copy_bw,
         "sketch_frac_of_measured_copy": gbps / copy_bw,

@@ -97,3 +97,15 @@ def lookup_queries(read_keys, n_total=500_000_000, absent_frac=0.2, seed=404):
 def diff_parts(got, want):
     """Indices of the parts whose count or digest differ."""
     return [i for i, (g, w) in enumerate(zip(got["parts"], want["parts"])) if g != w]
+
+
+def pairs_digest(per_pair):
+    """Per-pair outputs (one row per pair, any fixed width of uint32) of the
+    seed-matching experiment."""
+    a = np.ascontiguousarray(per_pair).astype(np.uint32)
+    a = a.reshape(a.shape[0], -1) if a.ndim > 1 else a.reshape(-1, 1)
+    n = a.shape[0]
+    cut = [i * n // PARTS for i in range(PARTS + 1)]
+    parts = [[int(a[cut[i]:cut[i + 1]].astype(np.uint64).sum()), _h(a[cut[i]:cut[i + 1]])[:16]]
+             for i in range(PARTS)]
+    return dict(n=int(n), sha256=_h(a), parts=parts)

@@ -4,8 +4,8 @@ Writes tests/golden/fullsize_oracle.json, which the full-size GPU tests compare 
 Every value in it comes from the oracle (oracle/) on inputs from datagen; nothing here
 calls the GPU library.  Run from the repository root:
 
-    python tests/golden/make_fullsize.py [--out FILE] [illumina] [gapped] [uneven] [lookups]
-        [containment]
+    python tests/golden/make_fullsize.py [--out FILE] [illumina] [gapped] [fig4] [uneven]
+        [lookups] [containment]
 
 (no argument: all).  It needs about 20 GB of memory and takes tens of minutes on 8 cores.
 Seeding and lookups are split over threads by read and query ranges (each read's anchors
@@ -105,6 +105,46 @@ def parallel_lookup(ik, q, chunk=10_000_000):
     return lb, occ
 
 
+# seed-matching experiment (Fig. 4): (pattern, k, w) settings recorded at full size
+FIG4 = [("10", 8, 6), ("100", 8, 6), ("1110110110111", 13, 9), ("10", 21, 11)]
+
+
+def fig4_entry():
+    """Oracle results on the 100,000-pair experiment: edit distances, per-pair seed counts
+    of every setting, and the accepted-pairs curves (thresholds 0..max distance)."""
+    o, oo, c, co, _ = datagen.workload_fig4()
+    n = oo.size - 1
+    log("fig4 workload generated")
+    dist = np.zeros(n, np.uint32)
+
+    def ed(lo):
+        for i in range(lo, min(lo + 2000, n)):
+            dist[i] = oracle.edit_distance(o[oo[i]:oo[i + 1]], c[co[i]:co[i + 1]])
+
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+        list(ex.map(ed, range(0, n, 2000)))
+    log("fig4: edit distances done (max %d)" % dist.max())
+    max_e = int(dist.max())
+    ent = dict(dist=fullsize.pairs_digest(dist), max_e=max_e, settings={})
+    for pattern, k, w in FIG4:
+        counts = np.zeros((n, 4, 2), np.uint32)
+
+        def sm(lo):
+            hi = min(lo + 5000, n)
+            counts[lo:hi] = oracle.seed_match(o[oo[lo]:oo[hi]], oo[lo:hi + 1] - oo[lo],
+                                              c[co[lo]:co[hi]], co[lo:hi + 1] - co[lo],
+                                              pattern, k, w)
+
+        with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+            list(ex.map(sm, range(0, n, 5000)))
+        acc = {alg: oracle.accepted(dist, counts[:, g, 0], counts[:, g, 1], max_e).tolist()
+               for g, alg in enumerate(oracle.FIG4_ALGORITHMS)}
+        ent["settings"]["%s/%d/%d" % (pattern, k, w)] = dict(
+            counts=fullsize.pairs_digest(counts.reshape(n, 8)), accepted=acc)
+        log("fig4 %s k%d w%d done" % (pattern, k, w))
+    return ent
+
+
 def main(which):
     table = {}
     if os.path.exists(OUT):
@@ -123,6 +163,8 @@ def main(which):
         ent, _ = seed_entry(d, "10")
         table["illumina-gapped-100Mbp/10"] = ent
         del d
+    if "fig4" in which:
+        table["fig4-100k"] = fig4_entry()
     if "uneven" in which or "lookups" in which:
         d = datagen.workload_uneven()
         log("uneven workload generated")
@@ -164,4 +206,4 @@ if __name__ == "__main__":
     if args[:1] == ["--out"]:
         OUT = args[1]
         args = args[2:]
-    main(set(args or ["illumina", "gapped", "uneven", "lookups", "containment"]))
+    main(set(args or ["illumina", "gapped", "fig4", "uneven", "lookups", "containment"]))

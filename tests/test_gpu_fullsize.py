@@ -15,7 +15,9 @@ part that differs when a check fails.
     1 Gbp '10' index: learned index (MLP and linear roots, 2^18 leaves) equals binary
     search equals the oracle; every result also satisfies the lower-bound property;
   * 1,000-genome containment database with 10M reads: 64-bit-value index and per-genome
-    shared-minimizer counts, with binary search and with the learned index.
+    shared-minimizer counts, with binary search and with the learned index;
+  * the seed-matching experiment on 100,000 pairs of 1,000 bases: edit distances, seed
+    counts of four settings and their accepted-pairs curves.
 """
 import json
 import os
@@ -101,6 +103,27 @@ def test_illumina_gapped_100mbp_benchmark_step(gpu, golden):
         got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
         assert_digest(got, exp["anchors"], "anchors (%s)" % mode)
     check_votes(gpu, s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, exp["votes"])
+
+
+@pytest.mark.timeout(900)
+def test_fig4_100k_pairs(gpu, golden):
+    # seed-matching experiment at full size: 100,000 pairs of 1,000 bases
+    exp = want(golden, "fig4-100k")
+    o, oo, c, co, _ = datagen.workload_fig4()
+    so, sc = gpu.to_device(o, oo), gpu.to_device(c, co)
+    dist = gpu.edit_distance(so, sc)
+    got = fullsize.pairs_digest(dist.cpu().numpy().view(np.uint32))
+    assert_digest(got, exp["dist"], "edit distances")
+    max_e = exp["max_e"]
+    for setting, ent in exp["settings"].items():
+        pattern, k, w = setting.split("/")
+        counts = gpu.seed_match(so, sc, pattern, int(k), int(w))
+        got = fullsize.pairs_digest(counts.cpu().numpy().view(np.uint32).reshape(-1, 8))
+        assert_digest(got, ent["counts"], "seed counts " + setting)
+        flat = counts.reshape(-1)
+        for alg, curve in ent["accepted"].items():
+            acc = gpu.accepted_pairs(dist, flat, alg, max_e).cpu().numpy()
+            assert acc.tolist() == curve, (setting, alg)
 
 
 def check_votes(gpu, anchors, read_off, exp):
