@@ -43,17 +43,19 @@
 #define GDO_ECAP (-2)
 #define GDO_ENOMEM (-3)
 
+#define GDO_MAX_PATTERN 256
+
 typedef struct {
     int p;                    /* pattern length */
     int x;                    /* weight = number of ones */
-    unsigned char bit[64];
+    unsigned char bit[GDO_MAX_PATTERN];
 } gdo_pattern;
 
 static int parse_pattern(const char *s, gdo_pattern *P)
 {
     if (!s) return GDO_EINVAL;
     size_t n = strlen(s);
-    if (n < 1 || n > 64) return GDO_EINVAL;
+    if (n < 1 || n > GDO_MAX_PATTERN) return GDO_EINVAL;
     P->p = (int)n;
     P->x = 0;
     for (size_t i = 0; i < n; i++) {

@@ -4,6 +4,7 @@ enumeration (tests/brute.py), library routines (numpy sort/searchsorted, Python 
 and invariants of the definitions (window coverage, the opening identity, strand
 symmetry, the expected minimizer density, recovery of the true pattern phase)."""
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -141,7 +142,7 @@ SWEEP = [("1", 1, 1), ("10", 3, 2), ("110", 4, 3), ("101", 5, 4), ("100", 2, 5),
 
 @pytest.mark.parametrize("pattern,k,w", SWEEP)
 def test_sketch_matches_brute_force(pattern, k, w):
-    rng = np.random.default_rng(hash((pattern, k, w)) & 0xFFFF)
+    rng = np.random.default_rng(zlib.crc32(("%s/%d/%d" % (pattern, k, w)).encode()))
     for trial in range(6):
         L = int(rng.integers(0, 260))
         if trial == 0:
@@ -673,3 +674,45 @@ def test_accepted_pairs_by_definition():
         want = sum(1 for r in rate if r >= min(close)) if close else 0
         assert got[E] == want
     assert got[-1] == n                                       # every pair is close enough
+
+
+
+# ---------------------------------------------------------------- patterns longer than 64
+
+def long_pattern(seed, p, density):
+    rng = np.random.default_rng(seed)
+    bits = rng.random(p) < density
+    bits[int(rng.integers(0, p))] = True
+    return "".join("1" if b else "0" for b in bits)
+
+
+LONG = [long_pattern(1, 65, 0.5), long_pattern(2, 100, 0.7), long_pattern(3, 129, 0.1),
+        long_pattern(4, 200, 0.5), "1" * 256, "0" * 255 + "1"]
+
+
+@pytest.mark.parametrize("pattern", LONG)
+def test_long_pattern_kept_count(pattern):
+    p = len(pattern)
+    rng = np.random.default_rng(p)
+    for L in [0, 1, p - 1, p, p + 1, 3 * p + 7, 5000] + rng.integers(0, 3000, 10).tolist():
+        for a in [0, 1, p // 2, p - 1]:
+            assert oracle.kept_count(L, pattern, a) == closed_form_kept(L, pattern, a)
+
+
+@pytest.mark.parametrize("pattern,k,w", [(LONG[0], 7, 5), (LONG[1], 11, 3), (LONG[2], 3, 2),
+                                         (LONG[3], 9, 9), (LONG[4], 15, 4)])
+def test_long_pattern_sketch_matches_brute_force(pattern, k, w):
+    p = len(pattern)
+    rng = np.random.default_rng(p + k)
+    for L in (0, 50, 700, 1500):
+        s = rng.integers(0, 4, L, dtype=np.uint8)
+        for a in sorted({0, 1, p // 3, p - 1, int(rng.integers(0, p))}):
+            keys, vals, _ = oracle.sketch(s, one(s), pattern, k, w, shifts=[a])
+            assert list(zip(keys.tolist(), vals.tolist())) == brute.sketch(s.tolist(), pattern,
+                                                                          a, k, w)
+
+
+def test_pattern_of_257_is_rejected():
+    assert oracle.kept_count(10, "1" * 257, 0) == 2**64 - 1
+    with pytest.raises(RuntimeError):
+        oracle.sketch(np.zeros(5, np.uint8), [0, 5], "1" * 257, 3, 2)
