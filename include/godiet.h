@@ -39,7 +39,7 @@
  *
  * The method (Section 3; Sections 3.1-3.3)
  * -----------------------------------------
- *  pattern P = p characters '0'/'1' (1 <= p <= 64, weight x >= 1 ones).  With shift a,
+ *  pattern P = p characters '0'/'1' (1 <= p <= 256, weight x >= 1 ones).  With shift a,
  *  base j of a sequence is kept iff P[(j - a) mod p] == '1' (the cyclic form of the
  *  paper's {Q[i+a] * P[i mod p]}).  The reference uses a = 0.
  *  k-mer code: 2k bits, first base most significant; canonical code = min(forward,
@@ -96,7 +96,7 @@ typedef struct {
 } godiet_seqs;
 
 typedef struct {
-    const char *pattern;      /* [host] NUL-terminated '0'/'1' string, 1..64 chars, >= one '1' */
+    const char *pattern;      /* [host] NUL-terminated '0'/'1' string, 1..256 chars, >= one '1' */
     int32_t k;                /* 1..32 */
     int32_t w;                /* 1..256 */
     int32_t hash;             /* k-mer hash: 0 = splitmix64 finalizer (default); 1 = Thomas

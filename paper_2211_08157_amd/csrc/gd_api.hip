@@ -11,13 +11,14 @@ namespace {
 bool parse_pattern(const char *s, Pattern *P)
 {
     if (!s) return false;
-    const size_t n = strnlen(s, 65);
-    if (n < 1 || n > 64) return false;
+    const size_t n = strnlen(s, kMaxPattern + 1);
+    if (n < 1 || n > kMaxPattern) return false;
     memset(P, 0, sizeof(*P));
     P->p = (uint32_t)n;
     for (size_t i = 0; i < n; i++) {
         if (s[i] == '1') {
-            P->mask |= 1ull << i;
+            if (i < 64) P->mask |= 1ull << i;
+            else P->hi[(i - 64) >> 6] |= 1ull << ((i - 64) & 63);
             P->ones[P->x++] = (uint8_t)i;
         } else if (s[i] != '0') {
             return false;

@@ -9,12 +9,45 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr uint64_t kMax64 = ~0ull;
 
-// A keep/skip pattern (Section 3: P[0..p-1], weight x).  Passed by value to kernels.
+constexpr uint32_t kMaxPattern = 256;
+
+// A keep/skip pattern (Section 3: P[0..p-1], weight x; 1 <= p <= 256).  Passed by value
+// to kernels.  Patterns of up to 64 characters (all the paper uses) live in `mask` and
+// take the bit-mask paths; longer ones also use `hi` and the rank-walking paths.
 struct Pattern {
-    uint64_t mask;     // bit t set iff P[t] == '1'
+    uint64_t mask;                // bit t set iff P[t] == '1', t < 64
+    uint64_t hi[3];               // bit t - 64 - 64i of hi[i] for P[64..256)
     uint32_t p, x;
-    uint8_t ones[64];  // positions of the ones in ascending order
+    uint8_t ones[kMaxPattern];    // positions of the ones in ascending order
 };
+
+__host__ __device__ __forceinline__ uint32_t popc64(uint64_t v)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return (uint32_t)__popcll(v);
+#else
+    return (uint32_t)__builtin_popcountll(v);
+#endif
+}
+
+__host__ __device__ __forceinline__ bool pattern_bit(const Pattern &P, uint32_t t)
+{
+    return t < 64 ? (P.mask >> t) & 1ull : (P.hi[(t - 64) >> 6] >> ((t - 64) & 63)) & 1ull;
+}
+
+// Ones of P among its first n characters (n <= p).
+__host__ __device__ __forceinline__ uint32_t ones_below(const Pattern &P, uint32_t n)
+{
+    if (n < 64) return popc64(P.mask & ((1ull << n) - 1));
+    uint32_t c = popc64(P.mask);
+    for (uint32_t i = 0; i < 3; i++) {
+        const uint32_t lo = 64 + 64 * i;
+        if (n <= lo) break;
+        const uint32_t take = n - lo >= 64 ? 64 : n - lo;
+        c += popc64(take == 64 ? P.hi[i] : (P.hi[i] & ((1ull << take) - 1)));
+    }
+    return c;
+}
 
 // splitmix64 output function (the k-mer hash; Steele, Lea, Flood 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
@@ -47,7 +80,7 @@ __device__ __forceinline__ uint64_t kmer_hash(uint64_t code, uint64_t mask)
     else return mix64(code);
 }
 
-// Pattern rotated right by a: bit t set iff P[(t - a) mod p] == '1'.
+// Pattern rotated right by a: bit t set iff P[(t - a) mod p] == '1' (p <= 64 only).
 __host__ __device__ __forceinline__ uint64_t rotated_mask(const Pattern &P, uint32_t a)
 {
     const uint64_t full = P.p == 64 ? kMax64 : ((1ull << P.p) - 1);
@@ -61,17 +94,33 @@ __device__ __forceinline__ uint64_t kept_count(const Pattern &P, uint64_t L, uin
 {
     const uint64_t q = L / P.p;
     const uint32_t rem = (uint32_t)(L - q * P.p);
+    if (P.p > 64) {
+        // phases t < rem map to pattern positions (t - a) mod p: [p - a, p - a + min(rem,
+        // a)) before the wrap, [0, rem - a) after it
+        if (a == 0) return q * P.x + ones_below(P, rem);
+        const uint32_t head = rem < a ? rem : a;
+        uint64_t c = ones_below(P, P.p - a + head) - ones_below(P, P.p - a);
+        if (rem > a) c += ones_below(P, rem - a);
+        return q * P.x + c;
+    }
     const uint64_t m = rotated_mask(P, a);
     const uint64_t low = rem == 64 ? m : (m & ((1ull << rem) - 1));
     return q * P.x + (uint64_t)__popcll(low);
+}
+
+// Ones of P with u < p - a (those that do not wrap under shift a); x when a == 0.
+__device__ __forceinline__ uint32_t kept_front(const Pattern &P, uint32_t a)
+{
+    if (a == 0) return P.x;
+    if (P.p > 64) return ones_below(P, P.p - a);
+    return (uint32_t)__popcll(P.mask & ((1ull << (P.p - a)) - 1));
 }
 
 // Offset within a period of the r-th kept phase under shift a (0 <= r < x).  The ones
 // u_i of P move to (u_i + a) mod p; those with u_i >= p - a wrap to the front.
 __device__ __forceinline__ uint32_t kept_phase(const Pattern &P, uint32_t a, uint32_t r)
 {
-    const uint32_t front = a == 0 ? P.x
-        : (uint32_t)__popcll(P.mask & ((1ull << (P.p - a)) - 1));   // ones with u < p - a
+    const uint32_t front = kept_front(P, a);
     uint32_t idx = r + front;
     if (idx >= P.x) idx -= P.x;
     uint32_t v = P.ones[idx] + a;

@@ -356,7 +356,7 @@ hipError_t launch_seed_match(const godiet_seqs *a, const godiet_seqs *b, const P
     A.kmask = k == 32 ? kMax64 : ((1ull << (2 * k)) - 1);
     A.spaced = 0;
     for (int j = 0; j < k; j++)
-        if ((P.mask >> (j % P.p)) & 1ull) A.spaced |= 1u << j;
+        if (pattern_bit(P, (uint32_t)j % P.p)) A.spaced |= 1u << j;
     A.counts = counts;
     A.status = status;
     const unsigned grid = a->n_seq < 65536u ? a->n_seq : 65536u;

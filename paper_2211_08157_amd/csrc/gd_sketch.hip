@@ -257,6 +257,21 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
             uint64_t per;
             uint32_t r;
             div_x(li, P.x, inv_x, &per, &r);
+            if (P.p > 64) {
+                // long pattern: the kept phases by rank, (ones[(r + front) mod x] + a) mod p
+                uint64_t pb = C.orig(s) + per * P.p;
+                uint32_t idx = r + kept_front(P, a);
+                if (idx >= P.x) idx -= P.x;
+                for (int i = 0; i < seg; i++) {
+                    uint32_t v = P.ones[idx] + a;
+                    if (v >= P.p) v -= P.p;
+                    word |= base_at(bases, pb + v) << (2 * (u + i));
+                    if (++r == P.x) { r = 0; pb += P.p; }
+                    if (++idx == P.x) idx = 0;
+                }
+                u += seg;
+                continue;
+            }
             const uint64_t rot = rotated_mask(P, a);
             uint64_t m = rot;                      // kept phases of the period not yet used
             for (uint32_t t = 0; t < r; t++) m &= m - 1;
@@ -358,6 +373,21 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
             uint64_t per;
             uint32_t r;
             div_x(j - beg, P.x, inv_x, &per, &r);
+            if (P.p > 64) {
+                uint64_t pb = C.orig(s) + per * P.p;
+                uint32_t idx = r + kept_front(P, a);
+                if (idx >= P.x) idx -= P.x;
+                for (int i = 0; i < seg; i++) {
+                    uint32_t v = P.ones[idx] + a;
+                    if (v >= P.p) v -= P.p;
+                    const uint64_t g = pb + v;
+                    bits |= ((nmask[g >> 5] >> (g & 31)) & 1u) << (u + i);
+                    if (++r == P.x) { r = 0; pb += P.p; }
+                    if (++idx == P.x) idx = 0;
+                }
+                u += seg;
+                continue;
+            }
             const uint64_t rot = rotated_mask(P, a);
             uint64_t m = rot;
             for (uint32_t t = 0; t < r; t++) m &= m - 1;

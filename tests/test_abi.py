@@ -52,7 +52,8 @@ def test_kept_bound_and_sparsify_bytes():
 
 @pytest.mark.parametrize("pattern,k,w,ok", [
     ("10", 21, 11, True), ("", 21, 11, False), ("000", 21, 11, False), ("1a", 21, 11, False),
-    ("1" * 64, 21, 11, True), ("1" * 65, 21, 11, False), ("10", 0, 11, False),
+    ("1" * 64, 21, 11, True), ("1" * 65, 21, 11, True), ("0" * 255 + "1", 21, 11, True),
+    ("1" * 256, 21, 11, True), ("1" * 257, 21, 11, False), ("10", 0, 11, False),
     ("10", 33, 11, False), ("10", 32, 11, True), ("10", 21, 0, False), ("10", 21, 257, False),
     ("10", 1, 256, True)])
 def test_workspace_size_validates_parameters(pattern, k, w, ok):
