@@ -4,16 +4,18 @@
 //
 //  * k_seed_match: one workgroup per pair.  Both sequences (at most 1,024 bases each)
 //    are unpacked into LDS; for each algorithm the original's seeds are built in LDS and
-//    sorted (bitonic), the copy's seeds are built and every one is looked up by binary
-//    search.  Minimizer selection marks, for every full window, the positions that
-//    attain its minimum (all ties), as the sketch does.
+//    inserted into an LDS hash set (2,048 slots, linear probing, 64-bit compare-and-swap),
+//    then the copy's seeds are built and each one probes the set.  Minimizer selection
+//    marks, for every full window, the positions that attain its minimum (all ties), as
+//    the sketch does.
 //  * k_edit_distance: one thread per pair, the bit-vector form of the edit-distance
 //    recurrence (Myers 1999, in Hyyrö's 2003 formulation for Levenshtein distance) over
 //    16 words of 64 rows, with the per-letter match masks in LDS.
 //  * accepted pairs: a matching rate m/t becomes the integer floor(m * 2^32 / t), which
 //    orders rates exactly while totals stay below 2^16; per-distance minima by atomic
 //    min, a prefix minimum over distances, then every pair adds one to the first
-//    distance threshold it passes and a prefix sum gives the counts.
+//    distance threshold it passes (counted in LDS per workgroup, then added to the global
+//    counts) and a prefix sum gives the counts.
 #include "gd_internal.h"
 
 namespace gd {
@@ -21,6 +23,9 @@ namespace gd {
 namespace {
 
 constexpr int kFig4MaxLen = 1024;     // bases per sequence of a pair
+constexpr int kSetSlots = 2048;       // LDS hash-set slots (load <= 1/2)
+static_assert(4 * kBlock >= kFig4MaxLen, "4 k-mers per thread cover a sequence");
+constexpr uint64_t kEmpty = ~0ull;    // an empty slot; the key ~0 itself is kept aside
 constexpr int kEdBlock = 64;          // threads per workgroup of k_edit_distance
 constexpr int kEdWords = kFig4MaxLen / 64;
 
@@ -44,8 +49,10 @@ struct MatchArgs {
 struct MatchLds {
     uint8_t sa[kFig4MaxLen], sb[kFig4MaxLen], ps[kFig4MaxLen];
     uint8_t use[kFig4MaxLen], sel[kFig4MaxLen];
-    uint64_t ka[kFig4MaxLen], kb[kFig4MaxLen], hv[kFig4MaxLen];
+    unsigned long long set[kSetSlots];
+    uint64_t kb[kFig4MaxLen], hv[kFig4MaxLen];
     uint32_t n;
+    uint32_t has_max;       // the original has a seed equal to kEmpty
     uint32_t red[kBlock / kWave];
 };
 
@@ -64,6 +71,26 @@ __device__ __forceinline__ uint64_t canon_at(const uint8_t *s, int i, int k, uin
     return f < r ? f : r;
 }
 
+// Forward and reverse-complement codes of the k-mer at i: built from its k bases when
+// `fresh`, otherwise rolled on from the k-mer at i - 1.
+__device__ __forceinline__ void roll_kmer(const uint8_t *s, int i, int k, uint64_t kmask,
+                                          bool fresh, uint64_t &f, uint64_t &r)
+{
+    if (fresh) {
+        f = 0;
+        r = 0;
+        for (int j = 0; j < k; j++) {
+            const uint64_t b = s[i + j];
+            f = (f << 2) | b;
+            r |= (3ull - b) << (2 * j);
+        }
+        return;
+    }
+    const uint64_t b = s[i + k - 1];
+    f = ((f << 2) | b) & kmask;
+    r = (r >> 2) | ((3ull - b) << (2 * (k - 1)));
+}
+
 // Seeds of sequence s (length L) under algorithm g into out[]; returns their number
 // (the same in every thread).  All threads of the workgroup call it.
 template <int HK>
@@ -71,10 +98,20 @@ __device__ uint32_t fig4_seeds(const MatchArgs &A, MatchLds &M, const uint8_t *s
                                uint64_t *out)
 {
     const int t = threadIdx.x, k = A.k, w = A.w;
-    if (g == 0 || g == 2) {
-        const uint32_t sel = g == 0 ? (k == 32 ? ~0u : ((1u << k) - 1u)) : A.spaced;
+    if (g == 2) {
         const int n = L >= k ? L - k + 1 : 0;
-        for (int i = t; i < n; i += kBlock) out[i] = canon_at(s, i, k, sel);
+        for (int i = t; i < n; i += kBlock) out[i] = canon_at(s, i, k, A.spaced);
+        __syncthreads();
+        return (uint32_t)n;
+    }
+    if (g == 0) {
+        const int n = L >= k ? L - k + 1 : 0;
+        // positions [4t, 4t + 4) of the (at most 1,024) k-mers: one k-mer built, 3 rolled
+        uint64_t f = 0, r = 0;
+        for (int i = 4 * t; i < 4 * t + 4 && i < n; i++) {
+            roll_kmer(s, i, k, A.kmask, i == 4 * t, f, r);
+            out[i] = f < r ? f : r;
+        }
         __syncthreads();
         return (uint32_t)n;
     }
@@ -89,13 +126,9 @@ __device__ uint32_t fig4_seeds(const MatchArgs &A, MatchLds &M, const uint8_t *s
     }
     const int nk = n >= k ? n - k + 1 : 0;
     if (nk < w) return 0;
-    for (int i = t; i < nk; i += kBlock) {
-        uint64_t f = 0, r = 0;
-        for (int j = 0; j < k; j++) {
-            const uint64_t b = src[i + j];
-            f = (f << 2) | b;
-            r |= (3ull - b) << (2 * j);
-        }
+    uint64_t f = 0, r = 0;
+    for (int i = 4 * t; i < 4 * t + 4 && i < nk; i++) {
+        roll_kmer(src, i, k, A.kmask, i == 4 * t, f, r);
         const bool pal = f == r;
         M.hv[i] = pal ? kMax64 : kmer_hash<HK>(f < r ? f : r, A.kmask);
         M.use[i] = pal ? 0 : 1;
@@ -119,27 +152,39 @@ __device__ uint32_t fig4_seeds(const MatchArgs &A, MatchLds &M, const uint8_t *s
     return M.n;
 }
 
-// Ascending bitonic sort of a[0, n) in LDS (n <= kFig4MaxLen), padded with kMax64.
-__device__ void lds_sort(uint64_t *a, uint32_t n)
+__device__ __forceinline__ uint32_t set_slot(uint64_t key)
 {
-    uint32_t n2 = 1;
-    while (n2 < n) n2 <<= 1;
-    for (uint32_t i = n + threadIdx.x; i < n2; i += kBlock) a[i] = kMax64;
-    __syncthreads();
-    for (uint32_t size = 2; size <= n2; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t c = threadIdx.x; c < n2 / 2; c += kBlock) {
-                const uint32_t lo = (c / stride) * stride * 2 + (c % stride);
-                const uint32_t hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const uint64_t x = a[lo], y = a[hi];
-                if ((x > y) == asc) {
-                    a[lo] = y;
-                    a[hi] = x;
-                }
-            }
-            __syncthreads();
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53);        // 11 bits
+}
+
+// Inserts keys[0, n) into the LDS hash set (cleared by the caller).
+__device__ void set_insert(MatchLds &M, const uint64_t *keys, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+        const uint64_t key = keys[i];
+        if (key == kEmpty) {
+            M.has_max = 1;
+            continue;
         }
+        uint32_t slot = set_slot(key);
+        while (true) {
+            const unsigned long long old = atomicCAS(&M.set[slot], (unsigned long long)kEmpty,
+                                                     (unsigned long long)key);
+            if (old == kEmpty || old == key) break;     // claimed, or already present
+            slot = (slot + 1) & (kSetSlots - 1);
+        }
+    }
+}
+
+__device__ __forceinline__ bool set_has(const MatchLds &M, uint64_t key)
+{
+    if (key == kEmpty) return M.has_max != 0;
+    uint32_t slot = set_slot(key);
+    while (true) {
+        const uint64_t v = M.set[slot];
+        if (v == key) return true;
+        if (v == kEmpty) return false;
+        slot = (slot + 1) & (kSetSlots - 1);
     }
 }
 
@@ -160,19 +205,14 @@ __global__ __launch_bounds__(kBlock) void k_seed_match(MatchArgs A)
         for (int i = t; i < (int)lb; i += kBlock) M.sb[i] = (uint8_t)base_of(A.bb, b0 + i);
         __syncthreads();
         for (int g = 0; g < 4; g++) {
-            const uint32_t na = fig4_seeds<HK>(A, M, M.sa, (int)la, g, M.ka);
-            lds_sort(M.ka, na);
+            for (int i = t; i < kSetSlots; i += kBlock) M.set[i] = kEmpty;
+            if (t == 0) M.has_max = 0;
+            const uint32_t na = fig4_seeds<HK>(A, M, M.sa, (int)la, g, M.kb);   // syncs
+            set_insert(M, M.kb, na);
+            __syncthreads();
             const uint32_t nb = fig4_seeds<HK>(A, M, M.sb, (int)lb, g, M.kb);
             uint32_t hit = 0;
-            for (uint32_t i = t; i < nb; i += kBlock) {
-                const uint64_t q = M.kb[i];
-                uint32_t lo = 0, hi = na;                     // first index with ka >= q
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (M.ka[mid] < q) lo = mid + 1; else hi = mid;
-                }
-                hit += (lo < na && M.ka[lo] == q) ? 1u : 0u;
-            }
+            for (uint32_t i = t; i < nb; i += kBlock) hit += set_has(M, M.kb[i]) ? 1u : 0u;
             hit = wave_sum<uint32_t>(hit);
             if ((t & (kWave - 1)) == 0) M.red[t / kWave] = hit;
             __syncthreads();
@@ -320,12 +360,19 @@ __global__ __launch_bounds__(kBlock) void k_acc_prefix(T *e, uint32_t n)
     }
 }
 
+constexpr uint32_t kAccLds = 8192;
+
 // Every pair adds one at the first threshold its rate reaches (thresholds do not rise).
 __global__ __launch_bounds__(kBlock) void k_acc_count(const uint32_t *counts, uint32_t n, int g,
                                                       uint32_t max_e,
                                                       const unsigned long long *thr,
                                                       uint32_t *acc)
 {
+    __shared__ uint32_t hist[kAccLds];          // per-workgroup counts when they fit
+    if (max_e < kAccLds) {
+        for (uint32_t e = threadIdx.x; e <= max_e; e += kBlock) hist[e] = 0;
+        __syncthreads();
+    }
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const uint64_t key = rate_key(counts[8 * (uint64_t)i + 2 * g],
                                       counts[8 * (uint64_t)i + 2 * g + 1]);
@@ -334,7 +381,15 @@ __global__ __launch_bounds__(kBlock) void k_acc_count(const uint32_t *counts, ui
             const uint32_t mid = (lo + hi) >> 1;
             if (thr[mid] <= key) hi = mid; else lo = mid + 1;
         }
-        if (lo <= max_e) atomicAdd(&acc[lo], 1u);
+        if (lo <= max_e) {
+            if (max_e < kAccLds) atomicAdd(&hist[lo], 1u);
+            else atomicAdd(&acc[lo], 1u);
+        }
+    }
+    if (max_e < kAccLds) {
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e <= max_e; e += kBlock)
+            if (hist[e]) atomicAdd(&acc[e], hist[e]);
     }
 }
 
