@@ -329,6 +329,7 @@ def cpu_baseline(data, pattern, k, w, sample_reads):
     ik, iv = oracle.index_build(data["ref"], data["ref_offsets"], pattern, k, w)
     t1 = time.perf_counter()
     ro = np.asarray(data["read_offsets"], np.int64)
+    sample_reads = min(sample_reads, ro.size - 1)
     chunk = max(1, sample_reads // (4 * threads))
     starts = list(range(0, sample_reads, chunk))
 
@@ -499,7 +500,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-reads", type=int, default=200_000)
+    ap.add_argument("--cpu-sample-reads", type=int, default=1_000_000)
     ap.add_argument("--no-1gbp", action="store_true",
                     help="skip the 1 Gbp reference sketch and the uneven 1 Gbp batch")
     ap.add_argument("--calibrate-copy", action="store_true",
