@@ -94,7 +94,13 @@ class Session:
                                  device=dev)
         self.cix_table = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
                                    None, 0, self.table.data_ptr(), self.table.numel())
-        self.opts = api.SeedOpts(-1, 0, 0, 0, 0, 0)
+        self.opts = api.SeedOpts(-1, 0, 0, 0, 0, 0, None)
+        # index construction runs on a side stream (default priority) and overlaps the
+        # read sketches of seeding; events order the two streams both ways
+        self.overlap = True
+        self.side = torch.cuda.Stream()
+        self.ev_index = torch.cuda.Event()
+        self.ev_seed = torch.cuda.Event()
         del ix, a, off
         # per-shift query counts (minimizers of the reads at every shift) for byte accounting
         self.queries = 0
@@ -112,25 +118,36 @@ class Session:
         if mode is True or mode is False:
             mode = "learned_index" if mode else "binary_search"
         L = self.api.lib()
-        st = ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+        main = self.torch.cuda.current_stream()
+        st = ctypes.c_void_p(main.cuda_stream)
+        if self.overlap:
+            self.side.wait_event(self.ev_seed)      # the last step's seeding has read the index
+            st_i = ctypes.c_void_p(self.side.cuda_stream)
+        else:
+            st_i = st
         r = L.godiet_index_build(ctypes.byref(self.cref), ctypes.byref(self.prm),
                                  ctypes.c_void_p(self.ikeys.data_ptr()),
                                  ctypes.c_void_p(self.ivals.data_ptr()), 32, self.capacity,
                                  ctypes.c_void_p(self.n_out.data_ptr()),
                                  ctypes.c_void_p(self.ws_i.data_ptr()), self.ws_i.numel(),
-                                 ctypes.c_void_p(self.st_i.data_ptr()), st)
+                                 ctypes.c_void_p(self.st_i.data_ptr()), st_i)
         if r != 0:
             raise RuntimeError("godiet_index_build failed: %d" % r)
         if mode == "learned_index":
             r = L.godiet_rmi_train(ctypes.byref(self.cix), 1, self.log2_leaves,
-                                   ctypes.c_void_p(self.rmi.data_ptr()), self.rmi.numel(), st)
+                                   ctypes.c_void_p(self.rmi.data_ptr()), self.rmi.numel(), st_i)
             if r != 0:
                 raise RuntimeError("godiet_rmi_train failed: %d" % r)
         elif mode == "hash_table":
             r = L.godiet_table_build(ctypes.byref(self.cix), ctypes.c_void_p(self.table.data_ptr()),
-                                     self.table.numel(), st)
+                                     self.table.numel(), st_i)
             if r != 0:
                 raise RuntimeError("godiet_table_build failed: %d" % r)
+        if self.overlap:
+            self.ev_index.record(self.side)
+            self.opts.index_ready = self.ev_index.cuda_event
+        else:
+            self.opts.index_ready = None
         cix = {"learned_index": self.cix_rmi, "hash_table": self.cix_table}.get(mode, self.cix)
         r = L.godiet_seed(ctypes.byref(cix), ctypes.byref(self.creads), ctypes.byref(self.prm),
                           ctypes.byref(self.opts), ctypes.c_void_p(self.anchors.data_ptr()),
@@ -140,6 +157,8 @@ class Session:
                           ctypes.c_void_p(self.st_s.data_ptr()), st)
         if r != 0:
             raise RuntimeError("godiet_seed failed: %d" % r)
+        if self.overlap:
+            self.ev_seed.record(main)
 
     def check(self):
         self.torch.cuda.synchronize()

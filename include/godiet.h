@@ -132,6 +132,12 @@ typedef struct {
                                  shifts) than this get a wave each instead of a thread */
     uint32_t lookup_blocks;   /* workgroups of each lookup launch */
     uint32_t long_blocks;     /* workgroups of the long-read alignment/expansion launches */
+    /* NULL, or an event the caller records after building the index on another stream:
+       the call enqueues the read sketches of every shift first (they need no index),
+       then makes `stream` wait on this event before the first index lookup, so index
+       construction and read sketching overlap.  The caller keeps the index alive and
+       unmodified until this call's work has finished. */
+    hipEvent_t index_ready;
 } godiet_seed_opts;
 
 typedef struct {

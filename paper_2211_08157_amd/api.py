@@ -44,7 +44,8 @@ class Index(ctypes.Structure):
 class SeedOpts(ctypes.Structure):
     _fields_ = [("shift_mode", ctypes.c_int32), ("align_t", ctypes.c_uint32),
                 ("max_occ", ctypes.c_uint32), ("long_records", ctypes.c_uint32),
-                ("lookup_blocks", ctypes.c_uint32), ("long_blocks", ctypes.c_uint32)]
+                ("lookup_blocks", ctypes.c_uint32), ("long_blocks", ctypes.c_uint32),
+                ("index_ready", ctypes.c_void_p)]
 
 
 class VoteOpts(ctypes.Structure):
@@ -419,9 +420,11 @@ def index_build(ref, pattern, k, w, val_bits=32, capacity=None, hash="splitmix64
 
 
 def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capacity=None,
-         tuning=None, hash="splitmix64"):
+         tuning=None, hash="splitmix64", index_ready=None):
     """Pattern alignment + compressed seeding.  Returns (anchors int32 tensor (n, 4) of
-    read_id, qpos, rpos, strand; read_anchor_off int64 tensor; shift uint8 tensor)."""
+    read_id, qpos, rpos, strand; read_anchor_off int64 tensor; shift uint8 tensor).
+    index_ready: a torch.cuda.Event recorded after the index was built on another stream
+    (the read sketches then run before waiting on it)."""
     torch = _torch()
     s = reads.c()
     L = lib()
@@ -429,7 +432,8 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capac
     ix = index.c()
     t = tuning or {}
     opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), int(t.get("long_records", 0)),
-                    int(t.get("lookup_blocks", 0)), int(t.get("long_blocks", 0)))
+                    int(t.get("lookup_blocks", 0)), int(t.get("long_blocks", 0)),
+                    index_ready.cuda_event if index_ready is not None else None)
     ws = _empty(workspace_size(OP_SEED, reads, pattern, k, w, index.n), torch.uint8)
     off = _empty(reads.n_seq + 1, torch.int64)
     shift = _empty(reads.n_seq, torch.uint8)

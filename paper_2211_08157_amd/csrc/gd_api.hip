@@ -197,6 +197,8 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     const size_t nr = reads->n_seq;
     GD_TRY(fill_u32(status, 0, 1, stream));
+    // every shift's sketch first (they need no index), then the lookups, so that an index
+    // built on another stream can overlap the sketches
     for (uint32_t si = 0; si < n_shift; si++) {
         const uint32_t a = opts->shift_mode >= 0 ? (uint32_t)opts->shift_mode : si;
         GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, status, stream));
@@ -207,9 +209,13 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, W.sk.pnw, npb,
                              prm->k, prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi,
                              status, stream));
-        GD_TRY(launch_lookup(index->keys, index->n, qk, mz + nr, W.stride, W.lb + si * W.stride,
-                             W.occ + si * W.stride, index->rmi, index->table,
-                             opts->lookup_blocks, stream));
+    }
+    if (opts->index_ready) GD_TRY(hipStreamWaitEvent(stream, opts->index_ready, 0));
+    for (uint32_t si = 0; si < n_shift; si++) {
+        const uint64_t *mz = W.mzofs + si * (nr + 1);
+        GD_TRY(launch_lookup(index->keys, index->n, W.qkeys + si * W.stride, mz + nr, W.stride,
+                             W.lb + si * W.stride, W.occ + si * W.stride, index->rmi,
+                             index->table, opts->lookup_blocks, stream));
     }
     AlignArgs &A = *Ap;
     A.mzofs = W.mzofs;

@@ -182,3 +182,27 @@ def test_capacity_status_and_retry(gpu):
     a, off, _ = gpu.seed(ix, dev(gpu, d["reads"], d["read_offsets"]), "10", 15, 10, capacity=10)
     assert a.shape[0] == int(off[-1].item()) > 10
     torch.cuda.synchronize()
+
+
+def test_seed_waits_for_an_index_built_on_another_stream(gpu):
+    # the index is built on a side stream while seeding sketches the reads on the main
+    # stream and waits on the index event before its lookups
+    import torch
+    d = datagen.workload_tiny()
+    ref = dev(gpu, d["ref"], d["ref_offsets"])
+    reads = dev(gpu, d["reads"], d["read_offsets"])
+    ek, ev = oracle.index_build(d["ref"], d["ref_offsets"], "10", 15, 10)
+    ea, eoff, esh = oracle.seed(ek, ev, d["reads"], d["read_offsets"], "10", 15, 10)
+    side = torch.cuda.Stream()
+    ready = torch.cuda.Event()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(side):
+            ix = gpu.index_build(ref, "10", 15, 10)
+            ix = gpu.rmi_train(ix, root="mlp", log2_leaves=12)
+            ready.record(side)
+        a, off, sh = gpu.seed(ix, reads, "10", 15, 10, index_ready=ready)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(a).reshape(-1, 4), ea)
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), eoff)
+        assert np.array_equal(sh.cpu().numpy().astype(np.uint32), esh)
