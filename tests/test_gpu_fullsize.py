@@ -70,7 +70,10 @@ def test_illumina_100mbp_benchmark_step(gpu, golden):
     d = datagen.workload_illumina()
     s = bench.Session(gpu, d, "10", K, W)
     del d
-    for learned in (False, True):
+    # binary search, learned index, and the learned-index step with index construction on
+    # a second stream overlapping the read sketches
+    for learned, overlap in ((False, False), (True, False), (True, True)):
+        s.overlap = overlap
         s.step(learned)
         s.check()
         n = s.n_index
@@ -79,7 +82,9 @@ def test_illumina_100mbp_benchmark_step(gpu, golden):
         na = s.n_anchors
         a = s.anchors[:4 * na].cpu().numpy().view(np.uint32)
         got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
-        assert_digest(got, exp["anchors"], "anchors (learned index %s)" % learned)
+        assert_digest(got, exp["anchors"], "anchors (learned index %s, overlap %s)"
+                      % (learned, overlap))
+    s.overlap = False
     check_votes(gpu, s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, exp["votes"])
 
 
