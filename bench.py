@@ -278,6 +278,49 @@ def gapped_step(gd, torch, steps, warmup):
                 pack_ascii_bytes_rule="text in + 2-bit codes + N bits out", kernels=kernels)
 
 
+def location_sorts(gd, torch, s, data, reps=3):
+    """Sorting each read's retrieved locations before voting (a synthetic analogue of
+    Table 10): the adaptive default, one digit sort of the whole batch, a per-read merge of
+    the runs the anchors already form, a per-read heapsort; on the step's Illumina-like
+    anchors and on HiFi- and ONT-like reads seeded against the same index.  Every way gives
+    the same winners (checked here)."""
+    import datagen
+    rng = np.random.default_rng(1205)
+    ix = gd.index_build(s.ref, s.pattern, s.k, s.w)
+    batches = {"illumina": (s.anchors[:4 * s.n_anchors].view(-1, 4), s.roff, 16)}
+    for name, lens, err in (("hifi", datagen.hifi_lengths(2000, rng), (0.005, 0.0025, 0.0025)),
+                            ("ont", datagen.ont_lengths(2000, rng), (0.04, 0.02, 0.02))):
+        codes, offs = datagen.variable_reads(data["ref"], lens, 1206, *err)[:2]
+        a, off, _ = gd.seed(ix, gd.to_device(codes, offs), s.pattern, s.k, s.w)
+        batches[name] = (a, off, 100)
+    out = {}
+    sort_kernels = ("k_vote_read_sort", "k_vote_long_sort", "k_digit", "k_hist", "k_scatter",
+                    "k_bucket_sort", "k_coarse_starts", "k_scan")
+    for name, (a, off, D) in batches.items():
+        res = dict(reads=int(off.numel() - 1), locations=int(a.shape[0]), D=D, V=3)
+        ref_rows = None
+        for sort in ("adaptive", "radix", "merge", "heap"):
+            w, nw = gd.vote(a, off, D, 3, 4, sort=sort)
+            rows = gd.winners_rows(w, nw)
+            if ref_rows is None:
+                ref_rows = rows
+            elif not np.array_equal(rows, ref_rows):
+                raise RuntimeError("location sort %s changed the winners" % sort)
+            torch.cuda.synchronize()
+            gd.trace_dump()
+            gd.trace_enable(True)
+            for _ in range(reps):
+                gd.vote(a, off, D, 3, 4, sort=sort)
+            torch.cuda.synchronize()
+            gd.trace_enable(False)
+            tr = gd.trace_dump()
+            total = sum(v[1] for v in tr.values()) / reps
+            srt = sum(v[1] for kn, v in tr.items() if kn.startswith(sort_kernels)) / reps
+            res[sort] = dict(sort_ms=srt, vote_ms=total)
+        out[name] = res
+    return out
+
+
 FIG4_SETTINGS = [("10", 8, 6), ("100", 8, 6), ("1110110110111", 13, 9), ("10", 21, 11)]
 
 
@@ -644,8 +687,13 @@ def main():
     vote = voting(gd, torch, s, args.steps, cpu=not args.no_cpu_baseline)
     log("[bench] location voting: %.3f ms per pass, %.3e reads/s" % (vote["ms_per_pass"],
                                                                     vote["reads_per_s"]))
-    gapped = fig4 = None
+    gapped = fig4 = sorts = None
     if not args.no_extras:
+        sorts = location_sorts(gd, torch, s, data)
+        log("[bench] location sorts (ms, adaptive/radix/merge/heap): " + "; ".join(
+            "%s %.3f/%.3f/%.3f/%.3f" % (n, v["adaptive"]["sort_ms"], v["radix"]["sort_ms"],
+                                        v["merge"]["sort_ms"], v["heap"]["sort_ms"])
+            for n, v in sorts.items()))
         gapped = gapped_step(gd, torch, args.steps, args.warmup)
         log("[bench] gapped workload: %.3f ms/step, %.3e reads/s; text packing %.1f GB/s"
             % (gapped["ms_per_step"], gapped["reads_per_s"], gapped["pack_ascii_GBps"]))
@@ -715,6 +763,7 @@ def main():
         "sketch_kernels_ms": sk_kernels,
         "sketch_1Gbp": sketch_1g,
         "location_voting": vote,
+        "location_sorts": sorts,
         "n_aware_step": gapped,
         "seed_matching_experiment": fig4,
         "uneven_batch_1Gbp": uneven,

@@ -149,6 +149,16 @@ typedef struct {
     uint32_t max_dist;        /* D: votes of L0 are the locations in [L0, L0 + D] */
     uint32_t min_votes;       /* V: a location wins with >= V votes */
     uint32_t max_winners;     /* 1..16: winners kept per read */
+    uint32_t sort;            /* how each read's adjusted locations are sorted before the
+                                 sweep (Section 3.6.2); every choice gives the same winners:
+                                 0 adaptive (default): a register sorting network for
+                                   reads with at most 16 locations, one workgroup per longer
+                                   read;
+                                 1 one digit (radix-style) sort of the whole batch;
+                                 2 per read, a natural merge sort merging the ascending runs
+                                   that the anchors already form (the index keeps every
+                                   minimizer's locations sorted);
+                                 3 per read, heapsort */
 } godiet_vote_opts;
 
 /* One winning (or rescue) mapping location, 24 bytes.  loc is the adjusted location:

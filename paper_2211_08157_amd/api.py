@@ -50,7 +50,10 @@ class SeedOpts(ctypes.Structure):
 
 class VoteOpts(ctypes.Structure):
     _fields_ = [("max_dist", ctypes.c_uint32), ("min_votes", ctypes.c_uint32),
-                ("max_winners", ctypes.c_uint32)]
+                ("max_winners", ctypes.c_uint32), ("sort", ctypes.c_uint32)]
+
+
+VOTE_SORTS = {"adaptive": 0, "radix": 1, "merge": 2, "heap": 3}
 
 
 _lib = None
@@ -475,7 +478,7 @@ def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, ma
     return counts[:n_genomes], sizes[:n_genomes]
 
 
-def vote(anchors, read_off, max_dist, min_votes, max_winners, capacity=None):
+def vote(anchors, read_off, max_dist, min_votes, max_winners, capacity=None, sort="adaptive"):
     """Location voting over seeding anchors (int32 tensor (n, 4), read_off int64 tensor
     [n_reads+1]).  Returns (winners int32 tensor (n_reads, max_winners, 6): the 24-byte
     records loc (two words), read_id, strand, votes, flags; n_win int32 tensor)."""
@@ -492,7 +495,9 @@ def vote(anchors, read_off, max_dist, min_votes, max_winners, capacity=None):
     out = _empty(max(n_reads, 1) * max_winners * 6, torch.int32)
     nw = _empty(max(n_reads, 1), torch.int32)
     st = _empty(1, torch.int32)
-    opts = VoteOpts(int(max_dist), int(min_votes), int(max_winners))
+    if sort not in VOTE_SORTS:
+        raise ValueError("sort must be one of %s" % sorted(VOTE_SORTS))
+    opts = VoteOpts(int(max_dist), int(min_votes), int(max_winners), VOTE_SORTS[sort])
     _check(L.godiet_vote(_ptr(anchors) if anchors.numel() else None, _ptr(read_off), n_reads,
                          int(capacity), ctypes.byref(opts), _ptr(out), _ptr(nw), _ptr(ws),
                          ws.numel(), _ptr(st), _stream()), "godiet_vote")

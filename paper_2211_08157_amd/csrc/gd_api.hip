@@ -481,7 +481,8 @@ godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anc
                           const godiet_vote_opts *opts, godiet_winner *out, uint32_t *n_win,
                           void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream)
 {
-    if (!opts || !status || opts->max_winners < 1 || opts->max_winners > 16) return GODIET_E_INVAL;
+    if (!opts || !status || opts->max_winners < 1 || opts->max_winners > 16 || opts->sort > 3)
+        return GODIET_E_INVAL;
     if (n_reads > 0 && (!read_anchor_off || !out || !n_win)) return GODIET_E_INVAL;
     if (anchor_capacity > 0 && !anchors) return GODIET_E_INVAL;
     if (n_reads >= (1u << 31) || anchor_capacity >= (1ull << 32)) return GODIET_E_RANGE;
@@ -493,6 +494,7 @@ godiet_status godiet_vote(const godiet_anchor *anchors, const uint64_t *read_anc
     A.max_dist = opts->max_dist;
     A.min_votes = opts->min_votes;
     A.max_win = opts->max_winners;
+    A.sort = (int)opts->sort;
     int rb = 0;                                   // bits of the largest read id
     while (rb < 31 && ((uint64_t)(n_reads > 0 ? n_reads - 1 : 0) >> rb) != 0) rb++;
     A.lz = 64 - 33 - rb;

@@ -144,6 +144,7 @@ hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void
 struct VoteArgs {
     uint32_t max_dist, min_votes, max_win;
     int lz;                 // key shift that puts the read id at the top of the key
+    int sort;               // 0 adaptive, 1 batch digit sort, 2 per-read merge, 3 per-read heap
 };
 hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *read_off,
                        uint32_t n_reads, uint64_t capacity, const SortPlan &sp,

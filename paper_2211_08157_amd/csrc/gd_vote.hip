@@ -9,6 +9,12 @@
 // with its anchor index as the value.  One sort of the whole batch (the index sort)
 // orders every read's adjusted locations by strand and location, and since the read id
 // is the top of the key each read keeps its own range [read_off[r], read_off[r+1]).
+// Alternatively each read's range is sorted on its own by one thread, by a natural merge
+// sort over the runs the anchors already form, or by heapsort (Section 3.6.2 compares
+// such choices); the default sorts reads with at most 16 locations in registers (a
+// bitonic network) and gives every longer read a workgroup (LDS bitonic chunks, then
+// merge-path merges).  The sweep
+// reads only the keys, so every choice gives the same winners.
 // The sweep then walks each read's run: the first key is the temporary location L0, its
 // votes are the keys up to L0 + D of the same read and strand, and the first key beyond
 // becomes the next L0.  Reads with few anchors are swept by one thread each; reads with
@@ -38,6 +44,206 @@ __global__ __launch_bounds__(kBlock) void k_vote_keys(const uint4 *anchors, cons
         const uint32_t d = st ? a.z + a.y : a.z - a.y + 0x80000000u;
         keys[i] = (((uint64_t)a.x << 33) | ((uint64_t)st << 32) | d) << lz;
         vals[i] = (uint32_t)i;
+    }
+}
+
+// Per-read sorts of the keys (one thread per read), the alternatives to the batch sort.
+// Keys of read r occupy [read_off[r], read_off[r + 1]) in anchor order.
+
+// Heapsort of a[0, n) ascending (sift-down heap, then repeated extraction).
+__device__ void heap_sort(uint64_t *a, uint64_t n)
+{
+    if (n < 2) return;
+    auto sift = [&](uint64_t root, uint64_t end) {
+        const uint64_t v = a[root];
+        while (true) {
+            uint64_t c = 2 * root + 1;
+            if (c >= end) break;
+            if (c + 1 < end && a[c + 1] > a[c]) c++;
+            if (a[c] <= v) break;
+            a[root] = a[c];
+            root = c;
+        }
+        a[root] = v;
+    };
+    for (uint64_t i = n / 2; i-- > 0;) sift(i, n);
+    for (uint64_t end = n - 1; end > 0; end--) {
+        const uint64_t t = a[0];
+        a[0] = a[end];
+        a[end] = t;
+        sift(0, end);
+    }
+}
+
+// Natural merge sort of a[0, n) with scratch t[0, n): every pass merges adjacent
+// ascending runs pairwise; a read's anchors come as per-minimizer runs sorted by
+// reference position, so few passes are needed.  The result ends in a.
+__device__ void natural_merge_sort(uint64_t *a, uint64_t *t, uint64_t n)
+{
+    uint64_t *src = a, *dst = t;
+    while (true) {
+        uint64_t i = 0, runs = 0;
+        while (i < n) {
+            uint64_t m = i + 1;                           // end of the first run
+            while (m < n && src[m - 1] <= src[m]) m++;
+            uint64_t e = m;                               // end of the second run
+            if (e < n) {
+                e++;
+                while (e < n && src[e - 1] <= src[e]) e++;
+            }
+            uint64_t x = i, y = m, o = i;
+            while (x < m && y < e) dst[o++] = src[y] < src[x] ? src[y++] : src[x++];
+            while (x < m) dst[o++] = src[x++];
+            while (y < e) dst[o++] = src[y++];
+            runs++;
+            i = e;
+        }
+        uint64_t *sw = src;
+        src = dst;
+        dst = sw;
+        if (runs <= 1) break;
+    }
+    if (src != a)
+        for (uint64_t i = 0; i < n; i++) a[i] = src[i];
+}
+
+// kind 2: natural merge sort, 3: heapsort, 0 (adaptive): reads with at most kRegSort keys
+// sorted in registers by a fixed bitonic network, longer reads listed for
+// k_vote_long_sort (one workgroup each).  Serial sorts in global memory wait on one load
+// after another, so beyond a few keys a read is better served by a whole workgroup.
+constexpr int kRegSort = 16;
+
+__device__ __forceinline__ void reg_sort16(uint64_t *a, uint32_t n)
+{
+    uint64_t v[kRegSort];
+#pragma unroll
+    for (int i = 0; i < kRegSort; i++) v[i] = (uint32_t)i < n ? a[i] : kMax64;
+#pragma unroll
+    for (int k = 2; k <= kRegSort; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < kRegSort; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool asc = (i & k) == 0;
+                    const uint64_t x = v[i], y = v[l];
+                    const bool sw = (x > y) == asc;
+                    v[i] = sw ? y : x;
+                    v[l] = sw ? x : y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kRegSort; i++)
+        if ((uint32_t)i < n) a[i] = v[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_vote_read_sort(uint64_t *keys, uint64_t *scratch,
+                                                           const uint64_t *read_off,
+                                                           uint32_t n_reads, uint64_t capacity,
+                                                           int kind, uint32_t *long_ids,
+                                                           uint32_t *long_n)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n_reads || read_off[n_reads] > capacity) return;
+    const uint64_t b = read_off[r], e = read_off[r + 1];
+    if (kind == 2) {
+        natural_merge_sort(keys + b, scratch + b, e - b);
+    } else if (kind == 3) {
+        heap_sort(keys + b, e - b);
+    } else if (e - b > (uint64_t)kRegSort) {
+        long_ids[atomicAdd(long_n, 1u)] = r;
+    } else if (e - b > 1) {
+        reg_sort16(keys + b, (uint32_t)(e - b));
+    }
+}
+
+constexpr uint32_t kSortChunk = 4096;        // keys sorted at once in LDS (32 KB)
+
+// Ascending bitonic sort of the LDS array a[0, n2) (n2 a power of two <= kSortChunk).
+__device__ void lds_bitonic(uint64_t *a, uint32_t n2)
+{
+    for (uint32_t size = 2; size <= n2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t c = threadIdx.x; c < n2 / 2; c += kBlock) {
+                const uint32_t lo = (c / stride) * stride * 2 + (c % stride);
+                const uint32_t hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                if ((x > y) == asc) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Elements of A among the first d outputs of merge(A, B), A first on ties (merge path).
+__device__ __forceinline__ uint64_t co_rank(uint64_t d, const uint64_t *A, uint64_t na,
+                                            const uint64_t *B, uint64_t nb)
+{
+    uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+    while (lo < hi) {
+        const uint64_t i = (lo + hi) >> 1;
+        if (A[i] <= B[d - i - 1]) lo = i + 1; else hi = i;
+    }
+    return lo;
+}
+
+// One workgroup per listed (long) read: sorted chunks of kSortChunk keys in LDS, then
+// pairwise merges of sorted runs in global memory, every thread merging its own share of
+// the output found by a merge-path split.  The result ends in keys.
+__global__ __launch_bounds__(kBlock) void k_vote_long_sort(uint64_t *keys, uint64_t *scratch,
+                                                           const uint64_t *read_off,
+                                                           uint32_t n_reads, uint64_t capacity,
+                                                           const uint32_t *long_ids,
+                                                           const uint32_t *long_n)
+{
+    __shared__ uint64_t sh[kSortChunk];
+    if (read_off[n_reads] > capacity) return;
+    const uint32_t nl = *long_n;
+    for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+        const uint32_t r = long_ids[li];
+        const uint64_t b = read_off[r], n = read_off[r + 1] - b;
+        uint64_t *a = keys + b, *t = scratch + b;
+        for (uint64_t c0 = 0; c0 < n; c0 += kSortChunk) {
+            const uint32_t m = (uint32_t)(n - c0 < kSortChunk ? n - c0 : kSortChunk);
+            uint32_t n2 = 1;
+            while (n2 < m) n2 <<= 1;
+            for (uint32_t i = threadIdx.x; i < n2; i += kBlock) sh[i] = i < m ? a[c0 + i] : kMax64;
+            __syncthreads();
+            lds_bitonic(sh, n2);
+            for (uint32_t i = threadIdx.x; i < m; i += kBlock) a[c0 + i] = sh[i];
+            __syncthreads();
+        }
+        uint64_t *src = a, *dst = t;
+        for (uint64_t width = kSortChunk; width < n; width *= 2) {
+            for (uint64_t p0 = 0; p0 < n; p0 += 2 * width) {
+                const uint64_t na = n - p0 < width ? n - p0 : width;
+                const uint64_t nb = n - p0 - na < width ? n - p0 - na : width;
+                const uint64_t *A = src + p0, *B = src + p0 + na;
+                const uint64_t len = na + nb;
+                const uint64_t d0 = len * threadIdx.x / kBlock;
+                const uint64_t d1 = len * (threadIdx.x + 1) / kBlock;
+                uint64_t i = co_rank(d0, A, na, B, nb), j = d0 - i;
+                for (uint64_t d = d0; d < d1; d++) {
+                    const bool take_a = j >= nb || (i < na && A[i] <= B[j]);
+                    dst[p0 + d] = take_a ? A[i++] : B[j++];
+                }
+            }
+            __syncthreads();                          // the pass is complete
+            uint64_t *sw = src;
+            src = dst;
+            dst = sw;
+        }
+        if (src != a) {
+            for (uint64_t i = threadIdx.x; i < n; i += kBlock) a[i] = src[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -216,8 +422,21 @@ hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *
         if (blocks > 8192) blocks = 8192;
         GD_LAUNCH(k_vote_keys, dim3((unsigned)blocks), dim3(kBlock), 0, s, anchors, n_ptr,
                   capacity, A.lz, keys, vals);
-        e = launch_sort(sp, sw, keys, vals, 4, n_ptr, capacity, s);
-        if (e != hipSuccess) return e;
+        if (A.sort == 1) {
+            e = launch_sort(sp, sw, keys, vals, 4, n_ptr, capacity, s);
+            if (e != hipSuccess) return e;
+        } else {
+            GD_LAUNCH(k_vote_read_sort, dim3((n_reads + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                      keys, (uint64_t *)sw.trec, read_off, n_reads, capacity, A.sort, long_ids,
+                      long_n);
+            if (A.sort == 0) {
+                GD_LAUNCH(k_vote_long_sort, dim3(1024), dim3(kBlock), 0, s, keys,
+                          (uint64_t *)sw.trec, read_off, n_reads, capacity,
+                          (const uint32_t *)long_ids, (const uint32_t *)long_n);
+            }
+            e = fill_u32(long_n, 0, 1, s);                // the sweep lists its own reads
+            if (e != hipSuccess) return e;
+        }
     }
     GD_LAUNCH(k_vote_sweep, dim3((n_reads + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
               (const uint64_t *)keys, read_off, n_reads, capacity, A, out, n_win, long_ids,

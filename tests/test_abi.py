@@ -213,3 +213,12 @@ def test_seed_match_host_checks():
                                    None) == -1                    # algorithm 4 does not exist
     assert L.godiet_accepted_pairs(0x1000, 0x2000, 10, 0, 99, 0x3000, 0x4000, 100,
                                    None) == -3                    # workspace too small
+
+
+def test_vote_rejects_unknown_sort():
+    from paper_2211_08157_amd.api import VoteOpts
+    L = _lib()
+    dummy = ctypes.c_void_p(0x1000)
+    r = L.godiet_vote(dummy, dummy, 4, 10, ctypes.byref(VoteOpts(16, 3, 4, 4)), dummy, dummy,
+                      dummy, 1 << 30, dummy, None)
+    assert r == -1

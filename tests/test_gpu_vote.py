@@ -2,7 +2,9 @@
 workload and of a mixed short/long-read batch, end to end after GPU seeding, on
 synthetic anchor sets built to exercise clusters, both strands, reads swept by a wave
 (more than 256 anchors), empty reads, every parameter edge (D = 0, V = 0, caps 1 and 16),
-and the status bits for a too-small capacity and anchors not grouped by read."""
+and the status bits for a too-small capacity and anchors not grouped by read; with each
+of the ways of sorting the locations (adaptive, batch digit sort, per-read merge of the
+presorted runs, per-read heapsort)."""
 import numpy as np
 import pytest
 import torch
@@ -18,10 +20,10 @@ def oracle_rows(out, nw):
                     np.int64).reshape(-1, 5)
 
 
-def gpu_vote(gpu, anchors_np, off_np, D, V, cap, capacity=None):
+def gpu_vote(gpu, anchors_np, off_np, D, V, cap, capacity=None, sort="adaptive"):
     a = torch.from_numpy(np.ascontiguousarray(anchors_np, np.uint32).view(np.int32)).cuda()
     o = torch.from_numpy(np.asarray(off_np, np.int64)).cuda()
-    w, nw = gpu.vote(a, o, D, V, cap, capacity=capacity)
+    w, nw = gpu.vote(a, o, D, V, cap, capacity=capacity, sort=sort)
     return gpu.winners_rows(w, nw)
 
 
@@ -53,8 +55,9 @@ def synthetic(seed, n_reads, long_every=0):
 def test_vote_on_synthetic_anchors(gpu, D, V, cap):
     a, off = synthetic(3 + D, 4000, long_every=97)
     want = oracle_rows(*oracle.vote(a, off, D, V, cap))
-    got = gpu_vote(gpu, a, off, D, V, cap)
-    assert np.array_equal(got, want)
+    for sort in ("adaptive", "radix", "merge", "heap"):
+        got = gpu_vote(gpu, a, off, D, V, cap, sort=sort)
+        assert np.array_equal(got, want), sort
 
 
 def test_vote_on_oracle_anchors_of_tiny_workload(gpu):
@@ -76,12 +79,12 @@ def test_vote_end_to_end_after_gpu_seeding_mixed_batch(gpu):
     codes, offs = datagen.concat([short[:2], hifi[:2], ont[:2]])
     ix = gpu.index_build(gpu.to_device(ref, roffs), "10", 15, 10)
     a, off, _ = gpu.seed(ix, gpu.to_device(codes, offs), "10", 15, 10)
-    w, nw = gpu.vote(a, off, 100, 3, 4)
-    got = gpu.winners_rows(w, nw)
     ek, ev = oracle.index_build(ref, roffs, "10", 15, 10)
     ea, eoff, _ = oracle.seed(ek, ev, codes, offs, "10", 15, 10)
     want = oracle_rows(*oracle.vote(ea, eoff, 100, 3, 4))
-    assert np.array_equal(got, want)
+    for sort in ("adaptive", "radix", "merge", "heap"):
+        w, nw = gpu.vote(a, off, 100, 3, 4, sort=sort)
+        assert np.array_equal(gpu.winners_rows(w, nw), want), sort
     assert (np.diff(eoff.astype(np.int64)) > 256).any()     # some reads took the wave path
 
 
@@ -98,3 +101,26 @@ def test_vote_empty_and_status(gpu):
     bad[int(off[first]), 0] = first + 1                      # one anchor claims the next read
     with pytest.raises(ValueError):
         gpu_vote(gpu, bad, off, 10, 2, 4)
+
+
+def test_vote_sorts_on_reads_with_many_locations(gpu):
+    # reads beyond one 4,096-key LDS chunk: the adaptive sort's merge passes run
+    rng = np.random.default_rng(31)
+    rows, off = [], [0]
+    for r, m in enumerate([0, 4095, 4096, 4097, 9000, 20_000, 3, 300, 257, 8192, 12_345]):
+        base = int(rng.integers(1000, 1 << 29))
+        read = []
+        for _ in range(m):
+            q = int(rng.integers(0, 1 << 20))
+            st = int(rng.integers(0, 2))
+            rp = (base + q if st == 0 else base - q) + int(rng.integers(-50, 50)) \
+                if rng.random() < 0.5 else int(rng.integers(0, (1 << 31) - 1))
+            read.append((q, max(rp, 0), st))
+        read.sort()
+        rows += [[r, q, rp, st] for q, rp, st in read]
+        off.append(len(rows))
+    a = np.array(rows, np.uint32).reshape(-1, 4)
+    off = np.array(off, np.uint64)
+    want = oracle_rows(*oracle.vote(a, off, 100, 3, 4))
+    for sort in ("adaptive", "radix", "merge", "heap"):
+        assert np.array_equal(gpu_vote(gpu, a, off, 100, 3, 4, sort=sort), want), sort
