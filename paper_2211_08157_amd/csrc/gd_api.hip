@@ -63,9 +63,9 @@ struct SketchWs {
     uint64_t *kept, *scan, *pofs;
     uint32_t *psw;
     uint32_t *pnw;        // N bits of the patterned stream (null without an N mask)
-    uint64_t *tiles;
-    uint32_t *counter;
-    uint32_t *lohi;       // per-window sequence ranges (sparsify blocks, then sketch tiles)
+    uint64_t *tiles;      // tile states + the tile ticket counter
+    uint32_t *lohi;       // sequence ranges of the sparsify workgroups
+    uint32_t *lohi_sk;    // sequence ranges of the sketch tiles
 };
 
 void plan_sketch_ws(Bump &b, const godiet_seqs *q, uint64_t npb, int w, SketchWs *o)
@@ -76,24 +76,28 @@ void plan_sketch_ws(Bump &b, const godiet_seqs *q, uint64_t npb, int w, SketchWs
     o->pofs = b.take<uint64_t>((size_t)n_seq + 1);
     o->psw = b.take<uint32_t>(psw_words(npb));
     o->pnw = q->nmask ? b.take<uint32_t>(pnw_words(npb)) : nullptr;
-    o->tiles = b.take<uint64_t>(sketch_tiles_bound(npb, w));
-    o->counter = b.take<uint32_t>(1);
-    const size_t a = sparsify_lohi(psw_words(npb)), t = 2 * sketch_tiles_bound(npb, w);
-    o->lohi = b.take<uint32_t>(a > t ? a : t);
+    o->tiles = b.take<uint64_t>(sketch_tiles_bound(npb, w) + 1);
+    o->lohi = b.take<uint32_t>(sparsify_lohi(psw_words(npb)));
+    o->lohi_sk = b.take<uint32_t>(2 * sketch_tiles_bound(npb, w));
 }
 
-// kept counts -> pofs -> patterned stream, for a per-sequence or uniform shift
+// kept counts -> pofs -> sequence ranges (sparsify and sketch of window w) -> patterned
+// stream, for a per-sequence or uniform shift
 hipError_t sparsify_to_stream(const godiet_seqs *in, const Pattern &P, const uint32_t *shift,
-                              uint32_t uniform, const SketchWs &W, uint64_t npb, uint32_t *status,
-                              hipStream_t s)
+                              uint32_t uniform, const SketchWs &W, uint64_t npb, int w,
+                              uint32_t *status, hipStream_t s)
 {
     const Batch bt = batch_of(in);
     hipError_t e = launch_kept(bt, P, shift, uniform, W.kept, status, s);
     if (e != hipSuccess) return e;
     e = exclusive_scan_u64(W.kept, W.pofs, in->n_seq, W.scan, s);
     if (e != hipSuccess) return e;
+    if (in->n_seq > 0) {
+        e = launch_window_ranges(W.pofs, in->n_seq, psw_words(npb), npb, w, W.lohi, W.lohi_sk, s);
+        if (e != hipSuccess) return e;
+    }
     return launch_sparsify(bt, P, shift, uniform, W.pofs, W.psw, W.pnw, psw_words(npb), W.lohi,
-                           s);
+                           in->n_seq > 0, s);
 }
 
 struct IndexWs {
@@ -201,14 +205,14 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
     // built on another stream can overlap the sketches
     for (uint32_t si = 0; si < n_shift; si++) {
         const uint32_t a = opts->shift_mode >= 0 ? (uint32_t)opts->shift_mode : si;
-        GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, status, stream));
+        GD_TRY(sparsify_to_stream(reads, P, nullptr, a, W.sk, npb, prm->w, status, stream));
         uint64_t *mz = W.mzofs + si * (nr + 1);
         uint64_t *qk = W.qkeys + si * W.stride;
         uint32_t *qv = W.qvals + si * W.stride;
         SketchOut o{qk, qv, VAL_LOCAL32, mz, (uint64_t)W.stride, nullptr};
         GD_TRY(launch_sketch(batch_of(reads), P, nullptr, a, W.sk.pofs, W.sk.psw, W.sk.pnw, npb,
-                             prm->k, prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi,
-                             status, stream));
+                             prm->k, prm->w, prm->hash, o, W.sk.tiles, W.sk.lohi_sk,
+                             reads->n_seq > 0, status, stream));
     }
     if (opts->index_ready) GD_TRY(hipStreamWaitEvent(stream, opts->index_ready, 0));
     for (uint32_t si = 0; si < n_shift; si++) {
@@ -328,7 +332,7 @@ godiet_status godiet_sparsify(const godiet_seqs *in, const char *pattern, const 
     GD_TRY(launch_kept(bt, P, shift, 0, kept, status, stream));
     GD_TRY(exclusive_scan_u64(kept, out_offsets, in->n_seq, scan, stream));
     GD_TRY(launch_sparsify(bt, P, shift, 0, out_offsets, (uint32_t *)out_bases, out_nmask,
-                           psw_words(npb), lohi, stream));
+                           psw_words(npb), lohi, false, stream));
     return GODIET_OK;
 }
 
@@ -398,10 +402,10 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
     plan_sketch_ws(b, in, npb, prm->w, &W);
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     GD_TRY(fill_u32(status, 0, 1, stream));
-    GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, status, stream));
+    GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, prm->w, status, stream));
     SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
     GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, W.pnw, npb, prm->k, prm->w,
-                         prm->hash, o, W.tiles, W.counter, W.lohi, status, stream));
+                         prm->hash, o, W.tiles, W.lohi_sk, in->n_seq > 0, status, stream));
     return GODIET_OK;
 }
 
@@ -423,10 +427,10 @@ godiet_status godiet_index_build(const godiet_seqs *ref, const godiet_sketch_par
     plan_index_ws(b, ref, P, prm->w, capacity, vb, &W);
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
     GD_TRY(fill_u32(status, 0, 1, stream));
-    GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, status, stream));
+    GD_TRY(sparsify_to_stream(ref, P, nullptr, 0, W.sk, npb, prm->w, status, stream));
     SketchOut o{keys, vals, val_bits == 32 ? VAL_GLOBAL32 : VAL_SEQ64, nullptr, capacity, n_out};
     GD_TRY(launch_sketch(batch_of(ref), P, nullptr, 0, W.sk.pofs, W.sk.psw, W.sk.pnw, npb, prm->k,
-                         prm->w, prm->hash, o, W.sk.tiles, W.sk.counter, W.sk.lohi, status,
+                         prm->w, prm->hash, o, W.sk.tiles, W.sk.lohi_sk, ref->n_seq > 0, status,
                          stream));
     if (capacity > 0) GD_TRY(launch_sort(W.sp, W.so, keys, vals, vb, n_out, capacity, stream));
     return GODIET_OK;

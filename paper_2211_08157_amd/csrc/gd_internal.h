@@ -84,9 +84,16 @@ hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
                        uint32_t uniform_shift, uint64_t *kept, uint32_t *status, hipStream_t s);
 // Patterned stream (uint32 words, 16 bases each) of `words` words from pofs; with b.nmask
 // and pnw set, also the N bits of the kept bases (pnw: `words` 16-bit halves).
+// lohi: per-workgroup sequence ranges, computed here unless ranges_ready.
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           uint32_t *pnw, size_t words, uint32_t *lohi, hipStream_t s);
+                           uint32_t *pnw, size_t words, uint32_t *lohi, bool ranges_ready,
+                           hipStream_t s);
+// Sequence ranges of the sparsify workgroups (sparsify_lohi(words) entries) and of the
+// sketch tiles for window w (2 * sketch_tiles_bound(np_bound, w) entries) in one launch.
+hipError_t launch_window_ranges(const uint64_t *pofs, uint32_t n_seq, size_t words,
+                                uint64_t np_bound, int w, uint32_t *lohi_sp, uint32_t *lohi_sk,
+                                hipStream_t s);
 // Text to 2-bit codes and N bits (godiet_pack_ascii).
 hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint16_t *nmask,
                              hipStream_t s);
@@ -101,14 +108,14 @@ struct SketchOut {
     uint64_t capacity;
     uint64_t *n_out;        // may be null
 };
-// Minimizers of the patterned stream; tile_state holds tiles_bound(np_bound) words.
+// Minimizers of the patterned stream; tile_state holds sketch_tiles_bound(np_bound) + 1
+// words (the last one is the tile ticket counter).
 size_t sketch_tiles_bound(uint64_t np_bound, int w);
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
                          const uint32_t *pnw, uint64_t np_bound, int k, int w, int hash,
-                         const SketchOut &o,
-                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
-                         uint32_t *status, hipStream_t s);
+                         const SketchOut &o, uint64_t *tile_state, uint32_t *lohi,
+                         bool ranges_ready, uint32_t *status, hipStream_t s);
 
 // Words of the patterned stream buffer for an upper bound on kept bases.
 inline size_t psw_words(uint64_t np_bound) { return (size_t)(np_bound / 16) + 8; }

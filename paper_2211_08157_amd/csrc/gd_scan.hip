@@ -86,10 +86,46 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const Tin *in, uint64_t *
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = bsum[nb];
 }
 
+// Small inputs: one workgroup walks the tiles in order with a running carry (one launch
+// instead of three).
+template <typename Tin>
+__global__ __launch_bounds__(kBlock) void k_scan_single(const Tin *in, uint64_t *out, size_t n)
+{
+    __shared__ uint64_t sh[kBlock / kWave];
+    uint64_t carry = 0;
+    for (size_t base0 = 0; base0 < n; base0 += kTile) {
+        const size_t base = base0 + (size_t)threadIdx.x * kItems;
+        uint64_t v[kItems];
+        uint64_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const size_t idx = base + i;
+            v[i] = idx < n ? (uint64_t)in[idx] : 0;
+            acc += v[i];
+        }
+        uint64_t tot;
+        uint64_t run = block_excl_scan<uint64_t>(acc, sh, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const size_t idx = base + i;
+            if (idx < n) out[idx] = run;
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+constexpr size_t kSingleScan = 16 * kTile;      // 65,536 inputs
+
 template <typename Tin>
 hipError_t scan(const Tin *in, uint64_t *out, size_t n, uint64_t *scratch, hipStream_t s)
 {
     if (n == 0) return fill<uint64_t>(out, 0, 1, s);
+    if (n <= kSingleScan) {
+        GD_LAUNCH(k_scan_single<Tin>, dim3(1), dim3(kBlock), 0, s, in, out, n);
+        return hipGetLastError();
+    }
     const size_t nb = (n + kTile - 1) / kTile;
     GD_LAUNCH(k_scan_reduce<Tin>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
     GD_LAUNCH(k_scan_top, dim3(1), dim3(kBlock), 0, s, scratch, nb);

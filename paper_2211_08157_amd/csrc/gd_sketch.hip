@@ -84,14 +84,10 @@ struct SeqCache {
 // search over the batch's offsets.  Window i covers [max(i*stride - before, 0),
 // i*stride - before + span] clamped to the stream; lohi[2i] and lohi[2i+1] are the first and
 // last sequence (both n_seq when the window lies past the stream's end).
-__global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, uint32_t n_seq,
-                                                        uint64_t stride, uint64_t before,
-                                                        uint64_t span, uint64_t count,
-                                                        uint32_t *lohi)
+__device__ __forceinline__ void window_range(const uint64_t *pofs, uint32_t n_seq, uint64_t np,
+                                             uint64_t i, uint64_t stride, uint64_t before,
+                                             uint64_t span, uint32_t *lohi)
 {
-    const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
-    if (i >= count) return;
-    const uint64_t np = pofs[n_seq];
     const int64_t a0 = (int64_t)(i * stride) - (int64_t)before;
     const uint64_t a = a0 > 0 ? (uint64_t)a0 : 0;
     const int64_t b0 = a0 + (int64_t)span;
@@ -104,6 +100,31 @@ __global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, ui
     }
     lohi[2 * i] = lo;
     lohi[2 * i + 1] = hi;
+}
+
+__global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, uint32_t n_seq,
+                                                        uint64_t stride, uint64_t before,
+                                                        uint64_t span, uint64_t count,
+                                                        uint32_t *lohi)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    if (i >= count) return;
+    window_range(pofs, n_seq, pofs[n_seq], i, stride, before, span, lohi);
+}
+
+// The ranges of the sparsify workgroups (4,096 positions each) and of the sketch tiles of
+// the same stream in one launch.
+__global__ __launch_bounds__(kBlock) void k_window_seqs2(const uint64_t *pofs, uint32_t n_seq,
+                                                         uint64_t count_sp, uint32_t *lohi_sp,
+                                                         uint64_t T, uint64_t H,
+                                                         uint64_t count_sk, uint32_t *lohi_sk)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    const uint64_t np = pofs[n_seq];
+    if (i < count_sp)
+        window_range(pofs, n_seq, np, i, (uint64_t)kBlock * 16, 0, (uint64_t)kBlock * 16 - 1,
+                     lohi_sp);
+    if (i < count_sk) window_range(pofs, n_seq, np, i, T, H, T + 2 * H + 48, lohi_sk);
 }
 
 // Fill the cache with the boundaries of sequences lo..hi from k_window_seqs (all threads
@@ -1074,15 +1095,31 @@ hipError_t launch_kept(const Batch &b, const Pattern &P, const uint32_t *shift,
     return hipGetLastError();
 }
 
+hipError_t launch_window_ranges(const uint64_t *pofs, uint32_t n_seq, size_t words,
+                                uint64_t np_bound, int w, uint32_t *lohi_sp, uint32_t *lohi_sk,
+                                hipStream_t s)
+{
+    const size_t blocks = (words + kBlock - 1) / kBlock;
+    const TileGeom g = tile_geom(w);
+    const size_t tiles = sketch_tiles_bound(np_bound, w);
+    const size_t count = blocks > tiles ? blocks : tiles;
+    GD_LAUNCH(k_window_seqs2, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+              pofs, n_seq, (uint64_t)blocks, lohi_sp, (uint64_t)g.T, (uint64_t)g.H,
+              (uint64_t)tiles, lohi_sk);
+    return hipGetLastError();
+}
+
 hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shift,
                            uint32_t uniform_shift, const uint64_t *pofs, uint32_t *psw,
-                           uint32_t *pnw, size_t words, uint32_t *lohi, hipStream_t s)
+                           uint32_t *pnw, size_t words, uint32_t *lohi, bool ranges_ready,
+                           hipStream_t s)
 {
     const size_t blocks = (words + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
-    GD_LAUNCH(k_window_seqs, dim3((unsigned)((blocks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-              pofs, b.n_seq, (uint64_t)kBlock * 16, (uint64_t)0, (uint64_t)kBlock * 16 - 1,
-              (uint64_t)blocks, lohi);
+    if (!ranges_ready)
+        GD_LAUNCH(k_window_seqs, dim3((unsigned)((blocks + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                  s, pofs, b.n_seq, (uint64_t)kBlock * 16, (uint64_t)0, (uint64_t)kBlock * 16 - 1,
+                  (uint64_t)blocks, lohi);
     // 16 consecutive kept bases lie in at most ceil(15/x) + 1 periods; with that span
     // <= 48 bases every base of a word's segment is inside a 64-base window that starts
     // at most 15 bases before the segment's first kept base
@@ -1111,20 +1148,20 @@ hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint
 hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift,
                          uint32_t uniform_shift, const uint64_t *pofs, const uint32_t *psw,
                          const uint32_t *pnw, uint64_t np_bound, int k, int w, int hash,
-                         const SketchOut &o,
-                         uint64_t *tile_state, uint32_t *tile_counter, uint32_t *lohi,
-                         uint32_t *status, hipStream_t s)
+                         const SketchOut &o, uint64_t *tile_state, uint32_t *lohi,
+                         bool ranges_ready, uint32_t *status, hipStream_t s)
 {
     const TileGeom g = tile_geom(w);
     const size_t tiles = sketch_tiles_bound(np_bound, w);
-    hipError_t e = fill_u64(tile_state, 0, tiles, s);
+    // tile states and, in the word after them, the tile ticket counter: one fill
+    hipError_t e = fill_u64(tile_state, 0, tiles + 1, s);
     if (e != hipSuccess) return e;
+    uint32_t *tile_counter = (uint32_t *)(tile_state + tiles);
     // tile t covers [t*T - H, t*T + T + H + 48] (the last 48 for the record loop's lookups)
-    GD_LAUNCH(k_window_seqs, dim3((unsigned)((tiles + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-              pofs, b.n_seq, (uint64_t)g.T, (uint64_t)g.H, (uint64_t)(g.T + 2 * g.H + 48),
-              (uint64_t)tiles, lohi);
-    e = fill_u32(tile_counter, 0, 1, s);
-    if (e != hipSuccess) return e;
+    if (!ranges_ready)
+        GD_LAUNCH(k_window_seqs, dim3((unsigned)((tiles + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                  s, pofs, b.n_seq, (uint64_t)g.T, (uint64_t)g.H, (uint64_t)(g.T + 2 * g.H + 48),
+                  (uint64_t)tiles, lohi);
     SketchArgs A;
     A.psw = psw;
     A.pnw = pnw;
