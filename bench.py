@@ -585,8 +585,9 @@ def main():
                     help="end with a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for "
-              "how the path would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the index is "
+              "replicated and reads split by range when it is sharded); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

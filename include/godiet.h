@@ -71,7 +71,7 @@ typedef int32_t godiet_status;
 #define GODIET_E_RANGE      (-2)  /* sizes do not fit the value encoding */
 #define GODIET_E_WORKSPACE  (-3)  /* ws NULL or smaller than godiet_workspace_size() */
 #define GODIET_E_HIP        (-4)  /* a HIP launch failed */
-#define GODIET_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+#define GODIET_E_UNSUPPORTED (-5) /* valid request the library does not handle */
 
 /* bits of the device status word */
 #define GODIET_ST_CAPACITY 1u  /* output larger than capacity; required count written */
