@@ -488,12 +488,42 @@ def uneven_batch(gd, torch, steps):
         plan.check()
         ms = e0.elapsed_time(e1) / steps
         n_anch = int(plan.read_off[-1].item())
+        # per-kernel device time of one eager pass with the same launch parameters
+        gd.trace_dump()
+        gd.trace_enable(True)
+        gd.seed(ix, reads, pat, 21, 11, tuning=tuning, capacity=n_anch)
+        torch.cuda.synchronize()
+        gd.trace_enable(False)
+        kern = {kn: dict(launches=c, ms=t) for kn, (c, t) in
+                sorted(gd.trace_dump().items(), key=lambda kv: -kv[1][1])[:12]}
+        # the same graph with the hash-table index form (one 16-byte slot per lookup; this
+        # index is several times the Infinity Cache, so lookups go to HBM)
+        digest = hashlib.sha256(plan.anchors[:4 * n_anch].cpu().numpy().tobytes()).hexdigest()
+        del plan
+        tix = gd.table_build(ix.with_rmi(None))
+        tplan = SeedPlan(tix, reads, pat, 21, 11, tuning=tuning)
+        tplan.capture()
+        tplan.replay()
+        tplan.check()
+        e0.record()
+        for _ in range(steps):
+            tplan.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        tplan.check()
+        ms_t = e0.elapsed_time(e1) / steps
+        if hashlib.sha256(tplan.anchors[:4 * n_anch].cpu().numpy().tobytes()).hexdigest() != digest:
+            raise RuntimeError("hash-table anchors differ from learned-index anchors")
+        del tplan, tix
         out[pat] = dict(ms_per_pass=ms, reads_per_s=n_reads / (ms * 1e-3),
                         bases_per_s=n_bases / (ms * 1e-3), anchors=n_anch, index_records=ix.n,
-                        log2_leaves=leaves, tuning=tuning)
+                        log2_leaves=leaves, tuning=tuning, kernels_eager_pass=kern,
+                        hash_table=dict(ms_per_pass=ms_t, reads_per_s=n_reads / (ms_t * 1e-3)))
+        log("[bench] uneven 1 Gbp batch, pattern %s, hash-table index: %.2f ms per graph replay"
+            % (pat, ms_t))
         log("[bench] uneven 1 Gbp batch, pattern %s: %.2f ms per graph replay, %.3e reads/s"
             % (pat, ms, n_reads / (ms * 1e-3)))
-        del plan, ix
+        del ix
         torch.cuda.empty_cache()
     out["reads"] = n_reads
     out["bases"] = n_bases
