@@ -995,70 +995,112 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             }
         }
     }
-    // own hashes to LDS (every read of the exchange array finished before the scan's
-    // barriers), so the record loop below can index them by position
+    // Records leave the tile in position order.  When they fit in the exchange array
+    // (12 or 16 bytes each, which every tile does unless w is tiny), the keys are compacted
+    // there straight from registers and the values after them, and the workgroup then
+    // writes the tile's contiguous record range with coalesced stores; otherwise the
+    // hashes go to LDS by position and each thread writes its own records.  Every read of
+    // the exchange array finished before the scan's barriers.
+    const int vbytes = A.val_mode == VAL_SEQ64 ? 8 : 4;
+    const bool staged = total * (uint64_t)(8 + vbytes) <= (uint64_t)kE * 8;   // workgroup-uniform
+    if (staged) {
+        uint32_t loc = (uint32_t)excl;
 #pragma unroll
-    for (int u = 0; u < 16; u++) ex[u * kBlock + t] = hv[u];
-    __syncthreads();
-    const uint64_t base = *sh_base_p + excl;
-
-    if (!owner || (uint64_t)jc > np) return;
-
-    // per-sequence record offsets of the sequences that start inside this chunk
-    if (A.mz_offsets) {
-        uint32_t s = (uint64_t)jc < np ? seq0 : first_ge(A.pofs, A.n_seq, (uint64_t)jc);
-        while (s > 0 && C.at(s - 1) >= (uint64_t)jc) s--;       // empty sequences
-        while (s <= A.n_seq && C.at(s) < (uint64_t)jc) s++;
-        while (s <= A.n_seq && C.at(s) < (uint64_t)jc + 16) {
-            const uint32_t below = (uint32_t)(C.at(s) - (uint64_t)jc);
-            A.mz_offsets[s] = base + __popc(sel & ((1u << below) - 1u));
-            s++;
-        }
+        for (int u = 0; u < 16; u++)
+            if ((sel >> u) & 1u) ex[loc++] = hv[u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; u++) ex[u * kBlock + t] = hv[u];
     }
-    if (sel == 0) return;
+    __syncthreads();
+    const uint64_t tile_base = *sh_base_p;
+    const uint64_t base = tile_base + excl;
+    uint32_t *sv32 = (uint32_t *)(ex + total);          // staged values, after the keys
+    uint64_t *sv64 = ex + total;
 
-    // records, in position order.  The original coordinate of patterned position li of a
-    // sequence is (li / x) * p + phase(li % x); the division is done once per chunk (or
-    // per sequence start) and then advanced by small offsets with a reciprocal multiply.
-    uint32_t seq = seq0;
-    uint64_t seq_beg = beg0, seq_end = end0;
-    uint32_t a = seq_shift(A.shift, A.uniform, seq);
-    if (a >= A.P.p) a = 0;
-    uint64_t per0;
-    uint32_t r0;
-    div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
-    uint64_t jb = (uint64_t)jc;                // position whose rank is (per0, r0)
-    const uint32_t magic = (65536u + A.P.x - 1) / A.P.x;
-    uint64_t idx = base;
-    uint32_t bits = sel;
-    while (bits) {
-        const int u = __ffs(bits) - 1;
-        bits &= bits - 1;
-        const uint64_t j = (uint64_t)jc + u;
-        if (j >= seq_end) {
-            while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
-            a = seq_shift(A.shift, A.uniform, seq);
-            if (a >= A.P.p) a = 0;
-            per0 = 0;
-            r0 = 0;
-            jb = seq_beg;
-        }
-        const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
-        const uint32_t q = (rr * magic) >> 16;
-        const uint64_t local = (per0 + q) * A.P.p + kept_phase(A.P, a, rr - q * A.P.x);
-        const uint32_t strand = (smask >> u) & 1u;
-        if (idx < A.capacity) {
-            A.keys[idx] = ex[u * kBlock + t];
-            if (A.val_mode == VAL_SEQ64) {
-                if (local >= (1ull << 31)) set_status(A.status, 2u);
-                ((uint64_t *)A.vals)[idx] = ((uint64_t)seq << 32) | (local << 1) | strand;
-            } else {
-                const uint64_t pos = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] + local : local;
-                if (pos >= (1ull << 31)) set_status(A.status, 2u);
-                ((uint32_t *)A.vals)[idx] = (uint32_t)((pos << 1) | strand);
+    if (owner && (uint64_t)jc <= np) {
+        // per-sequence record offsets of the sequences that start inside this chunk
+        if (A.mz_offsets) {
+            uint32_t s = (uint64_t)jc < np ? seq0 : first_ge(A.pofs, A.n_seq, (uint64_t)jc);
+            while (s > 0 && C.at(s - 1) >= (uint64_t)jc) s--;       // empty sequences
+            while (s <= A.n_seq && C.at(s) < (uint64_t)jc) s++;
+            while (s <= A.n_seq && C.at(s) < (uint64_t)jc + 16) {
+                const uint32_t below = (uint32_t)(C.at(s) - (uint64_t)jc);
+                A.mz_offsets[s] = base + __popc(sel & ((1u << below) - 1u));
+                s++;
             }
         }
-        idx++;
+        if (sel != 0) {
+            // The original coordinate of patterned position li of a sequence is
+            // (li / x) * p + phase(li % x); the division is done once per chunk (or per
+            // sequence start) and then advanced by small offsets with a reciprocal multiply.
+            uint32_t seq = seq0;
+            uint64_t seq_beg = beg0, seq_end = end0;
+            uint32_t a = seq_shift(A.shift, A.uniform, seq);
+            if (a >= A.P.p) a = 0;
+            uint64_t per0;
+            uint32_t r0;
+            div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
+            uint64_t jb = (uint64_t)jc;                // position whose rank is (per0, r0)
+            const uint32_t magic = (65536u + A.P.x - 1) / A.P.x;
+            uint64_t idx = excl;                       // record index within the tile
+            uint32_t bits = sel;
+            while (bits) {
+                const int u = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const uint64_t j = (uint64_t)jc + u;
+                if (j >= seq_end) {
+                    while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
+                    a = seq_shift(A.shift, A.uniform, seq);
+                    if (a >= A.P.p) a = 0;
+                    per0 = 0;
+                    r0 = 0;
+                    jb = seq_beg;
+                }
+                const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
+                const uint32_t q = (rr * magic) >> 16;
+                const uint64_t local = (per0 + q) * A.P.p + kept_phase(A.P, a, rr - q * A.P.x);
+                const uint32_t strand = (smask >> u) & 1u;
+                if (A.val_mode == VAL_SEQ64) {
+                    if (local >= (1ull << 31)) set_status(A.status, 2u);
+                    const uint64_t v = ((uint64_t)seq << 32) | (local << 1) | strand;
+                    if (staged) {
+                        sv64[idx] = v;
+                    } else if (tile_base + idx < A.capacity) {
+                        A.keys[tile_base + idx] = ex[u * kBlock + t];
+                        ((uint64_t *)A.vals)[tile_base + idx] = v;
+                    }
+                } else {
+                    const uint64_t pos = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] + local : local;
+                    if (pos >= (1ull << 31)) set_status(A.status, 2u);
+                    const uint32_t v = (uint32_t)((pos << 1) | strand);
+                    if (staged) {
+                        sv32[idx] = v;
+                    } else if (tile_base + idx < A.capacity) {
+                        A.keys[tile_base + idx] = ex[u * kBlock + t];
+                        ((uint32_t *)A.vals)[tile_base + idx] = v;
+                    }
+                }
+                idx++;
+            }
+        }
+    }
+    if (staged) {
+        __syncthreads();
+        const uint64_t n = tile_base + total <= A.capacity
+                               ? total
+                               : (tile_base < A.capacity ? A.capacity - tile_base : 0);
+        if (A.val_mode == VAL_SEQ64) {
+            for (uint64_t i = t; i < n; i += kBlock) {
+                A.keys[tile_base + i] = ex[i];
+                ((uint64_t *)A.vals)[tile_base + i] = sv64[i];
+            }
+        } else {
+            for (uint64_t i = t; i < n; i += kBlock) {
+                A.keys[tile_base + i] = ex[i];
+                ((uint32_t *)A.vals)[tile_base + i] = sv32[i];
+            }
+        }
     }
 }
 

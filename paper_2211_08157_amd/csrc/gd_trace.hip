@@ -88,8 +88,8 @@ size_t godiet_trace_dump(char *buf, size_t len)
             e.first += 1;
             e.second += ms;
             if (consume) {
-                hipEventDestroy(r.a);
-                hipEventDestroy(r.b);
+                (void)hipEventDestroy(r.a);      // nothing to do if destroying fails
+                (void)hipEventDestroy(r.b);
             }
         }
         if (consume) g_recs.clear();

@@ -98,6 +98,49 @@ def test_sketch_many_tiles_and_reads(gpu):
         assert np.array_equal(u32(vals).astype(np.uint64), ev)
 
 
+@pytest.mark.parametrize("w", [1, 2, 4])
+def test_index_64bit_values_dense_windows(gpu, w):
+    # with w = 1 every k-mer is a minimizer: more records per tile than the exchange array
+    # can stage at 16 bytes each, so those tiles write their records directly
+    codes, offs = ragged_batch(13, [40_000, 0, 9, 151, 12_000])
+    for pattern, k in [("1", 11), ("10", 9)]:
+        ix = gpu.index_build(dev(gpu, codes, offs), pattern, k, w, val_bits=64)
+        ek, ev = oracle.index_build(codes, offs, pattern, k, w, val_bits=64)
+        assert np.array_equal(u64(ix.keys), ek)
+        assert np.array_equal(u64(ix.vals), ev)
+
+
+@pytest.mark.parametrize("w", [1, 11])
+def test_sketch_capacity_short_writes_prefix_only(gpu, w):
+    # an output buffer shorter than the sketch: the first `capacity` records are written,
+    # nothing past them, the capacity status is raised and mz_offsets hold the full count
+    import ctypes
+    import torch
+    from paper_2211_08157_amd import api
+    codes, offs = ragged_batch(14, [30_000, 5, 2_000, 151])
+    ek, ev, em = oracle.sketch(codes, offs, "1", 15, w)
+    seqs = dev(gpu, codes, offs)
+    cap = int(ek.size) * 2 // 3 + 5
+    pad = 4096
+    keys = torch.full((cap + pad,), -1, dtype=torch.int64, device="cuda")
+    vals = torch.full((cap + pad,), -1, dtype=torch.int32, device="cuda")
+    mz = torch.zeros(len(offs), dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(api.workspace_size(api.OP_SKETCH, seqs, "1", 15, w), dtype=torch.uint8,
+                     device="cuda")
+    prm = api._params("1", 15, w)
+    s = seqs.c()
+    api._check(api.lib().godiet_sketch(ctypes.byref(s), ctypes.byref(prm), None, api._ptr(keys),
+                                       api._ptr(vals), api._ptr(mz), cap, api._ptr(ws),
+                                       ws.numel(), api._ptr(st), api._stream()), "godiet_sketch")
+    torch.cuda.synchronize()
+    assert int(st.item()) & api.STATUS_CAPACITY
+    assert np.array_equal(mz.cpu().numpy().view(np.uint64), em)
+    assert np.array_equal(u64(keys)[:cap], ek[:cap])
+    assert np.array_equal(u32(vals)[:cap].astype(np.uint64), ev[:cap])
+    assert (keys[cap:] == -1).all() and (vals[cap:] == -1).all()
+
+
 def test_sketch_empty_batch_and_no_sequences(gpu):
     codes, offs = ragged_batch(5, [0, 0, 3])
     keys, vals, mz = gpu.sketch(dev(gpu, codes, offs), "10", 15, 10)
