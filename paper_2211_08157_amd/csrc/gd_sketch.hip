@@ -817,7 +817,8 @@ __device__ __forceinline__ void run_masks(const NB &nb, const SeqCache &C, int64
 template <int W, int HK>
 __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
                                             uint64_t n_tiles, uint64_t *ex, uint64_t *sh_scan,
-                                            uint64_t *sh_base_p, const SeqCache &C)
+                                            uint64_t *sh_base_p, const SeqCache &C,
+                                            const uint8_t *ones)
 {
     const int t = threadIdx.x;
     const int H = A.H, T = A.T, w = W > 0 ? W : A.w, k = A.k;
@@ -1038,6 +1039,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             uint64_t seq_beg = beg0, seq_end = end0;
             uint32_t a = seq_shift(A.shift, A.uniform, seq);
             if (a >= A.P.p) a = 0;
+            uint32_t front = kept_front(A.P, a);
             uint64_t per0;
             uint32_t r0;
             div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
@@ -1053,13 +1055,19 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                     while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
                     a = seq_shift(A.shift, A.uniform, seq);
                     if (a >= A.P.p) a = 0;
+                    front = kept_front(A.P, a);
                     per0 = 0;
                     r0 = 0;
                     jb = seq_beg;
                 }
                 const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
                 const uint32_t q = (rr * magic) >> 16;
-                const uint64_t local = (per0 + q) * A.P.p + kept_phase(A.P, a, rr - q * A.P.x);
+                // offset in the period of kept phase r under shift a (ones[] in LDS)
+                uint32_t oi = rr - q * A.P.x + front;
+                if (oi >= A.P.x) oi -= A.P.x;
+                uint32_t ph = ones[oi] + a;
+                if (ph >= A.P.p) ph -= A.P.p;
+                const uint64_t local = (per0 + q) * A.P.p + ph;
                 const uint32_t strand = (smask >> u) & 1u;
                 if (A.val_mode == VAL_SEQ64) {
                     if (local >= (1ull << 31)) set_status(A.status, 2u);
@@ -1112,17 +1120,19 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     __shared__ uint64_t sh_base;
     __shared__ uint32_t sh_tile;
     __shared__ uint64_t sh_pofs[kSeqCache];
+    __shared__ uint8_t sh_ones[kMaxPattern];   // the pattern's kept offsets, read per record
 
     const uint64_t np = A.pofs[A.n_seq];
     const uint64_t n_tiles = np / (uint64_t)A.T + 1;    // the last tile covers position np
     // tiles are numbered in the order workgroups start, so every predecessor a tile looks
     // back on is already running
     if (threadIdx.x == 0) sh_tile = atomicAdd(A.tile_counter, 1u);
+    for (uint32_t i = threadIdx.x; i < A.P.x; i += kBlock) sh_ones[i] = A.P.ones[i];
     __syncthreads();
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
     const SeqCache C = seq_cache(A.pofs, A.n_seq, A.lohi, tile, sh_pofs);
-    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C);
+    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C, sh_ones);
 }
 
 }  // namespace
