@@ -858,6 +858,9 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                         seq_end - seq_beg >= L;
         if (interior && n_near)
             interior = first_n(A.pnw, (uint64_t)jc, (uint64_t)jc + 15 + L) == (uint64_t)jc + 15 + L;
+        // One path per wave: the masked path below is exact for interior chunks too, and a
+        // wave whose lanes split between the two would execute both.
+        interior = __ballot(!interior) == 0;
         if (interior && (k & 1)) {
             // odd k: a k-mer never equals its reverse complement
             selm = winm = 0xFFFFu;
@@ -893,6 +896,8 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             // loop per sequence overlapping the chunk; then all 16 positions are hashed
             // as in the interior and masked, without per-position branches.
             uint32_t kv = 0, wv = 0, okm = 0;
+            // the N-aware masks are exact without an N too: one branch per wave
+            n_near = __ballot(n_near) != 0;
             if (n_near && L <= 48) {
                 // N bits of [jc - 64, jc + 64) from five words loaded at once
                 const int64_t q0 = jc >> 5;
