@@ -629,8 +629,10 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
             mw[s] = x;
         }
     }
+    if (__ballot(winm != 0xFFFFu) != 0) {       // skipped by waves whose windows are all valid
 #pragma unroll
-    for (int s = 0; s < 16; s++) mw[s] = ((winm >> s) & 1u) ? mw[s] : 0;
+        for (int s = 0; s < 16; s++) mw[s] = ((winm >> s) & 1u) ? mw[s] : 0;
+    }
 
     // opening
     uint64_t SM[16], PM[16], op[16];
@@ -671,11 +673,10 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
             op[u] = x;
         }
     }
-    uint32_t sel = 0;
+    uint32_t eq = 0;
 #pragma unroll
-    for (int u = 0; u < 16; u++)
-        if (owner && ((selm >> u) & 1u) && v[u] == op[u]) sel |= 1u << u;
-    return sel;
+    for (int u = 0; u < 16; u++) eq |= (v[u] == op[u] ? 1u : 0u) << u;
+    return owner ? eq & selm : 0u;
 }
 
 // Any w: window minima and the opening by doubling in LDS (ex holds kE words).
