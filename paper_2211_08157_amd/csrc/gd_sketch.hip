@@ -1046,6 +1046,8 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             uint32_t a = seq_shift(A.shift, A.uniform, seq);
             if (a >= A.P.p) a = 0;
             uint32_t front = kept_front(A.P, a);
+            // original offset of the sequence (global positions only), reloaded per sequence
+            uint64_t obase = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] : 0;
             uint64_t per0;
             uint32_t r0;
             div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
@@ -1062,6 +1064,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                     a = seq_shift(A.shift, A.uniform, seq);
                     if (a >= A.P.p) a = 0;
                     front = kept_front(A.P, a);
+                    if (A.val_mode == VAL_GLOBAL32) obase = A.offsets[seq];
                     per0 = 0;
                     r0 = 0;
                     jb = seq_beg;
@@ -1085,7 +1088,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                         ((uint64_t *)A.vals)[tile_base + idx] = v;
                     }
                 } else {
-                    const uint64_t pos = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] + local : local;
+                    const uint64_t pos = obase + local;
                     if (pos >= (1ull << 31)) set_status(A.status, 2u);
                     const uint32_t v = (uint32_t)((pos << 1) | strand);
                     if (staged) {
