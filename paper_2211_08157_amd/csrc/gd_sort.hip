@@ -28,7 +28,8 @@
 // a global atomic or a random global read.  The densest digit then holds about six times
 // the mean (~3.2K records at 8M), so coarse buckets target 512 records (at most 512 plus
 // one digit, within the LDS capacity); each is binned again in LDS by the next key bits
-// and its records placed by rank (k_digit_bucket_sort).
+// and its records placed by rank (k_digit_bucket_sort, in two launches sized for the
+// common and the dense buckets).
 #include "gd_internal.h"
 
 namespace gd {
@@ -261,9 +262,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
 // two records each on average), the sub-bins are scanned and filled from registers, and
 // every record is then placed by its rank inside its sub-bin, as in k_bucket_sort.
 // Buckets spanning too many digits, or holding a long sub-bin, are bitonic-sorted.
-constexpr int kSub = 4096;
-
-template <typename V>
+// Two launches share the buckets: most hold about the 512-record target and are sorted
+// by workgroups sized for half the LDS capacity (twice as many fit on a CU); the larger
+// ones (dense digits at the low end of the hash range) by full-capacity workgroups, which
+// also list the buckets beyond the capacity for the fallback.
+template <typename V, bool kFull>
 __global__ __launch_bounds__(kBlock) void k_digit_bucket_sort(const ulonglong2 *trec,
                                                               const uint64_t *fofs,
                                                               const uint32_t *cstart, int Bd,
@@ -271,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_digit_bucket_sort(const ulonglong2 *
                                                               uint32_t *overflow,
                                                               uint32_t *overflow_n)
 {
-    constexpr int kCap = Cap<V>::value;
+    constexpr int kCap = kFull ? Cap<V>::value : Cap<V>::value / 2;
+    constexpr int kSub = kCap;                  // sub-bins
     constexpr int kPer = kCap / kBlock;
     __shared__ uint64_t K[kCap];
     __shared__ V Vv[kCap];
@@ -282,6 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_digit_bucket_sort(const ulonglong2 *
     const uint64_t base = fofs[d0];
     const uint64_t n64 = fofs[d1] - base;
     if (n64 == 0) return;
+    if (!kFull && n64 > (uint64_t)kCap) return;             // left to the full-size launch
+    if (kFull && n64 <= (uint64_t)(kCap / 2)) return;        // done by the half-size launch
     if (n64 > (uint64_t)kCap) {
         if (threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
         return;
@@ -484,9 +490,14 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
               (const uint64_t *)w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, w.cstart,
               (uint64_t)sp.ncoarse + 1);
     if (sp.digits)
-        GD_LAUNCH(k_digit_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
+    {
+        GD_LAUNCH((k_digit_bucket_sort<V, false>), dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
                   (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
                   (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
+        GD_LAUNCH((k_digit_bucket_sort<V, true>), dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
+                  (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
+                  (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
+    }
     else
         GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
                   (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
