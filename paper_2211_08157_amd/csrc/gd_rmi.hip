@@ -65,7 +65,9 @@ __global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint6
 }
 
 // Leaf boundaries: leaf l starts at the first key routed to a leaf >= l.  Stored in the
-// leaves' base field for the fitting pass.
+// leaves' base field for the fitting pass.  The FP32 root can step back by one leaf
+// between neighbouring keys, so a leaf may be claimed by several keys: the smallest index
+// wins (the bases start at all ones), which keeps the model independent of store order.
 __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
                                                        const RmiHeader *Hp, RmiLeaf *leaves)
 {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
         const uint32_t cur = i < n ? route(H, keys[i]) : L;          // past the end: L
         const uint32_t prv = i > 0 ? route(H, keys[i - 1]) : 0;
         const uint32_t from = i > 0 ? prv + 1 : 0;
-        for (uint32_t l = from; l <= cur && l < L; l++) leaves[l].base = (uint32_t)i;
+        for (uint32_t l = from; l <= cur && l < L; l++) atomicMin(&leaves[l].base, (uint32_t)i);
     }
 }
 
@@ -162,6 +164,8 @@ hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t
     RmiLeaf *leaves = (RmiLeaf *)((char *)rmi + sizeof(RmiHeader));
     const uint32_t L = 1u << log2_leaves;
     GD_LAUNCH(k_rmi_root, dim3(1), dim3(kBlock), 0, s, keys, n, kind, log2_leaves, H);
+    hipError_t e = fill_u32((uint32_t *)leaves, ~0u, (size_t)L * (sizeof(RmiLeaf) / 4), s);
+    if (e != hipSuccess) return e;
     uint64_t blocks = (n + 1 + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     GD_LAUNCH(k_rmi_bounds, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n,

@@ -52,6 +52,19 @@ def test_rmi_lookup_equals_binary_search(gpu, ref_index, root, leaves):
     assert np.array_equal(u32(occ_r), u32(occ_b))
 
 
+@pytest.mark.parametrize("root", ["mlp", "linear"])
+def test_rmi_training_is_deterministic(gpu, ref_index, root):
+    # every leaf's base is the first key routed to it or past it, whatever order the
+    # claims land in: two trainings give the same bytes and the bases never decrease
+    ref, offs, ek, ev, ix = ref_index
+    a = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
+    b = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
+    assert np.array_equal(a, b)
+    base = a[320:].view(np.uint32).reshape(-1, 4)[:, 1]     # header 320 B, 16-B leaves
+    assert base.size == 1 << 18 and base[0] == 0
+    assert np.all(np.diff(base.astype(np.int64)) >= 0) and base[-1] <= ek.size
+
+
 def test_rmi_corrupted_model_falls_back(gpu, ref_index):
     ref, offs, ek, ev, ix = ref_index
     q = queries_from(ek)
