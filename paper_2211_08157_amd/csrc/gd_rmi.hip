@@ -82,17 +82,22 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
     }
 }
 
-// One thread per leaf: least-squares line through ((key >> 32) - khi, position) in FP64,
-// then the largest under- and over-prediction over the leaf's keys with the lookup's own
-// prediction function (saturated at 255: a larger miss only sends those lookups to the
-// binary-search fallback).  The key loops take 8 keys per step so that 8 loads are in
-// flight per thread.
+// Eight lanes per leaf (a group never straddles a wave): least-squares line through
+// ((key >> 32) - khi, position) in FP64, the lanes taking every eighth key so that a
+// group reads consecutive keys, then the largest under- and over-prediction over the
+// leaf's keys with the lookup's own prediction function (saturated at 255: a larger miss
+// only sends those lookups to the binary-search fallback).  The butterfly sums add the
+// same pairs in every lane, so all eight lanes hold identical totals.
+constexpr int kFitLanes = 8;
+
 __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64_t n,
                                                     const RmiHeader *Hp, RmiLeaf *leaves)
 {
     const uint32_t L = 1u << Hp->log2_leaves;
-    const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
-    if (l >= L) return;
+    const uint64_t g = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    const uint64_t l = g / kFitLanes;
+    const int j = (int)(g % kFitLanes);
+    if (l >= L) return;                       // whole groups only
     const uint64_t lo = leaves[l].base;
     const uint64_t hi = l + 1 < L ? leaves[l + 1].base : n;
     RmiLeaf lf;
@@ -105,20 +110,16 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     const uint64_t m = hi > lo ? hi - lo : 0;
     if (m >= 2) {
         double sx = 0, sy = 0, sxx = 0, sxy = 0;
-        uint64_t i = lo;
-        for (; i + 8 <= hi; i += 8) {
-            uint64_t kk[8];
-#pragma unroll
-            for (int u = 0; u < 8; u++) kk[u] = keys[i + u];
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const double x = (double)((uint32_t)(kk[u] >> 32) - lf.khi), y = (double)(i + u - lo);
-                sx += x; sy += y; sxx += x * x; sxy += x * y;
-            }
-        }
-        for (; i < hi; i++) {
+        for (uint64_t i = lo + j; i < hi; i += kFitLanes) {
             const double x = (double)((uint32_t)(keys[i] >> 32) - lf.khi), y = (double)(i - lo);
             sx += x; sy += y; sxx += x * x; sxy += x * y;
+        }
+#pragma unroll
+        for (int o = 1; o < kFitLanes; o <<= 1) {
+            sx += __shfl_xor(sx, o, kFitLanes);
+            sy += __shfl_xor(sy, o, kFitLanes);
+            sxx += __shfl_xor(sxx, o, kFitLanes);
+            sxy += __shfl_xor(sxy, o, kFitLanes);
         }
         const double var = sxx - sx * sx / (double)m;
         const double sl = var > 0 ? (sxy - sx * sy / (double)m) / var : 0.0;
@@ -127,27 +128,31 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
         lf.slope = (float)(sl > 0 ? sl : 0.0);
         lf.icpt = (_Float16)(float)ic;
     }
-    // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]
-    int64_t elo = 0, ehi = 0;
-    uint64_t prev = 0;
-    for (uint64_t i0 = lo; i0 < hi; i0 += 8) {
-        uint64_t kk[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) kk[u] = i0 + u < hi ? keys[i0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const uint64_t i = i0 + u;
-            if (i < hi && (i == lo || kk[u] != prev)) {
-                const int64_t d = (int64_t)i - predict(lf, kk[u]);
-                if (d > ehi) ehi = d;
-                if (-d > elo) elo = -d;
-            }
-            prev = kk[u];
+    // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]; a lane's
+    // previous key is the lane below's (lane 0: the last key of the group's previous step)
+    long long elo = 0, ehi = 0;
+    unsigned long long carry = 0;
+    for (uint64_t i0 = lo; i0 < hi; i0 += kFitLanes) {           // uniform in the group
+        const uint64_t i = i0 + j;
+        const unsigned long long k = i < hi ? keys[i] : 0;
+        unsigned long long prev = __shfl_up(k, 1, kFitLanes);
+        if (j == 0) prev = carry;
+        if (i < hi && (i == lo || k != prev)) {
+            const long long d = (long long)i - (long long)predict(lf, k);
+            if (d > ehi) ehi = d;
+            if (-d > elo) elo = -d;
         }
+        carry = __shfl(k, kFitLanes - 1, kFitLanes);
+    }
+#pragma unroll
+    for (int o = 1; o < kFitLanes; o <<= 1) {
+        const long long a = __shfl_xor(elo, o, kFitLanes), b = __shfl_xor(ehi, o, kFitLanes);
+        elo = a > elo ? a : elo;
+        ehi = b > ehi ? b : ehi;
     }
     lf.err_lo = (uint8_t)(elo < 255 ? elo : 255);
     lf.err_hi = (uint8_t)(ehi < 255 ? ehi : 255);
-    leaves[l] = lf;
+    if (j == 0) leaves[l] = lf;
 }
 
 }  // namespace
@@ -170,7 +175,8 @@ hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t
     if (blocks > 8192) blocks = 8192;
     GD_LAUNCH(k_rmi_bounds, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n,
               (const RmiHeader *)H, leaves);
-    GD_LAUNCH(k_rmi_fit, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, keys, n,
+    GD_LAUNCH(k_rmi_fit, dim3((unsigned)(((uint64_t)L * kFitLanes + kBlock - 1) / kBlock)),
+              dim3(kBlock), 0, s, keys, n,
               (const RmiHeader *)H, leaves);
     return hipGetLastError();
 }
