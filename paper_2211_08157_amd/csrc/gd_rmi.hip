@@ -73,10 +73,21 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
 {
     const RmiHeader H = *Hp;
     const uint32_t L = 1u << H.log2_leaves;
-    for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i <= n;
-         i += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t cur = i < n ? route(H, keys[i]) : L;          // past the end: L
-        const uint32_t prv = i > 0 ? route(H, keys[i - 1]) : 0;
+    // A wave takes 63 new indices per step: lane t routes index s - 1 + t, so every lane
+    // but the first finds its predecessor's leaf in the lane below (each key is routed
+    // about once instead of twice).  Indices run to n inclusive (index n routes past the
+    // end, to L).
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    for (uint64_t s = wave * (kWave - 1); s <= n; s += waves * (kWave - 1)) {   // wave-uniform
+        const uint64_t i = s + lane - 1;                 // s - 1 for lane 0 (wraps at s = 0)
+        uint32_t cur = 0;
+        if (lane == 0 && s == 0) cur = 0;                // no predecessor of index 0
+        else if (i < n) cur = route(H, keys[i]);
+        else cur = L;                                    // index n (and past it)
+        const uint32_t prv = __shfl_up(cur, 1);
+        if (lane == 0 || i > n) continue;
         const uint32_t from = i > 0 ? prv + 1 : 0;
         for (uint32_t l = from; l <= cur && l < L; l++) atomicMin(&leaves[l].base, (uint32_t)i);
     }
