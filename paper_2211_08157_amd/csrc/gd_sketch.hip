@@ -79,6 +79,45 @@ struct SeqCache {
     }
 };
 
+// Last s in [0, n] with a[s] <= v, as last_le, for a[0] <= v < np = a[n]: the search
+// starts where v would fall if the positions were spread evenly over the sequences (as
+// they nearly are in a read batch) and gallops outwards to a bracket, so a batch of
+// similar reads needs a few loads instead of log2(n) dependent ones.
+__device__ __forceinline__ uint32_t last_le_guess(const uint64_t *a, uint32_t n, uint64_t v,
+                                                  uint64_t np)
+{
+    const double f = (double)v / (double)np * (double)n;
+    uint32_t g = f < (double)n ? (uint32_t)f : n - 1;
+    if (g >= n) g = n - 1;
+    uint32_t lo, hi;                 // a[lo] <= v, and a[hi] > v or hi == n + 1
+    if (a[g] <= v) {
+        lo = g;
+        uint64_t step = 1;
+        while (true) {
+            const uint64_t nx = (uint64_t)lo + step;
+            if (nx > n) { hi = n + 1; break; }
+            if (a[nx] > v) { hi = (uint32_t)nx; break; }
+            lo = (uint32_t)nx;
+            step <<= 1;
+        }
+    } else {
+        hi = g;
+        uint64_t step = 1;
+        while (true) {
+            if (hi < step) { lo = 0; break; }          // a[0] <= v
+            const uint32_t nx = (uint32_t)(hi - step);
+            if (a[nx] <= v) { lo = nx; break; }
+            hi = nx;
+            step <<= 1;
+        }
+    }
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Sequences holding the first and last position of window i of the patterned stream,
 // for all windows at once (one thread each), so that no workgroup starts with a serial
 // search over the batch's offsets.  Window i covers [max(i*stride - before, 0),
@@ -95,8 +134,8 @@ __device__ __forceinline__ void window_range(const uint64_t *pofs, uint32_t n_se
     uint32_t lo = n_seq, hi = n_seq;
     if (a < np) {
         if (b >= np) b = np - 1;
-        lo = last_le(pofs, n_seq, a);
-        hi = last_le(pofs, n_seq, b);
+        lo = last_le_guess(pofs, n_seq, a, np);
+        hi = last_le_guess(pofs, n_seq, b, np);
     }
     lohi[2 * i] = lo;
     lohi[2 * i + 1] = hi;
@@ -200,6 +239,14 @@ __device__ __forceinline__ uint32_t unzip_even(uint64_t y)
     return (uint32_t)y;
 }
 
+// Offset within the period of the only kept phase of a one-one pattern under shift a
+// (kept_phase(P, a, 0) for x == 1, read without a per-lane table index).
+__device__ __forceinline__ uint32_t phase1(const Pattern &P, uint32_t a)
+{
+    const uint32_t v = P.ones[0] + a;
+    return v >= P.p ? v - P.p : v;
+}
+
 // One thread per output word: gathers the 16 kept bases [16q, 16q+16) of the batch.
 // nbytes = ceil(n_bases / 4), the readable size of `bases`.  Three paths:
 //  * period 2 with one kept base, word inside one sequence: the 16 kept bases are every
@@ -240,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                 const uint32_t hi = __builtin_amdgcn_alignbit(W2, W1, sh);
                 return unzip_even(((uint64_t)hi << 32) | lo);
             };
-            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + kept_phase(P, a, 0);   // x == 1
+            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + phase1(P, a);   // x == 1
             if (j0 + 16 <= end && ((o0 >> 4) + 3) * 4 <= nbytes) {
                 psw[q] = run16(o0);
                 return;
@@ -254,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                 const uint64_t end2 = C.at(s2 + 1);
                 uint32_t a2 = seq_shift(shift, uniform, s2);
                 if (a2 >= P.p) a2 = 0;
-                const uint64_t o2 = C.orig(s2) + kept_phase(P, a2, 0);
+                const uint64_t o2 = C.orig(s2) + phase1(P, a2);
                 if (j0 + 16 <= end2 && ((o0 >> 4) + 3) * 4 <= nbytes &&
                     ((o2 >> 4) + 3) * 4 <= nbytes) {
                     const int n1 = (int)(end - j0);           // 1..15
@@ -363,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
             };
             uint32_t a = seq_shift(shift, uniform, s);
             if (a >= P.p) a = 0;
-            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + kept_phase(P, a, 0);
+            const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + phase1(P, a);
             if (j0 + 16 <= end) {
                 pnw[q] = (uint16_t)run16(o0);
                 return;
@@ -373,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
                 while (C.at(s2 + 1) == C.at(s2)) s2++;        // skip empty sequences
                 uint32_t a2 = seq_shift(shift, uniform, s2);
                 if (a2 >= P.p) a2 = 0;
-                const uint64_t o2 = C.orig(s2) + kept_phase(P, a2, 0);
+                const uint64_t o2 = C.orig(s2) + phase1(P, a2);
                 // both runs' reads stay inside the mask (ceil(n_bases / 32) words)
                 if (j0 + 16 <= C.at(s2 + 1) && ((o0 + 30) >> 5) < nwords &&
                     ((o2 + 30) >> 5) < nwords) {
