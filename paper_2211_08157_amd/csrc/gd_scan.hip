@@ -1,5 +1,5 @@
 // Fill kernels (used instead of memset so calls stay safe to capture in a HIP graph) and a
-// three-phase device-wide exclusive scan.
+// device-wide exclusive scan (one launch for small inputs, two up to 4M, three beyond).
 #include "gd_internal.h"
 
 namespace gd {
@@ -86,6 +86,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const Tin *in, uint64_t *
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = bsum[nb];
 }
 
+// Phases 2 and 3 in one launch for up to kFusedBlocks blocks: each block adds up the sums of
+// the blocks before it (a few hundred values) instead of waiting for a separate top scan.
+template <typename Tin>
+__global__ __launch_bounds__(kBlock) void k_scan_apply_fused(const Tin *in, uint64_t *out,
+                                                             size_t n, const uint64_t *bsum,
+                                                             size_t nb)
+{
+    __shared__ uint64_t sh[kBlock / kWave];
+    uint64_t off = 0;
+    for (size_t b0 = 0; b0 < blockIdx.x; b0 += kBlock) {        // uniform in the block
+        const size_t i = b0 + threadIdx.x;
+        uint64_t part;
+        block_excl_scan<uint64_t>(i < blockIdx.x ? bsum[i] : 0, sh, &part);
+        off += part;
+    }
+    const size_t base = blockIdx.x * kTile + (size_t)threadIdx.x * kItems;   // contiguous
+    uint64_t v[kItems];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const size_t idx = base + i;
+        v[i] = idx < n ? (uint64_t)in[idx] : 0;
+        acc += v[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan<uint64_t>(acc, sh, &tot) + off;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const size_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = off + tot;
+}
+
 // Small inputs: one workgroup walks the tiles in order with a running carry (one launch
 // instead of three).
 template <typename Tin>
@@ -117,6 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_single(const Tin *in, uint64_t 
 }
 
 constexpr size_t kSingleScan = 16 * kTile;      // 65,536 inputs
+constexpr size_t kFusedBlocks = 1024;           // up to 4M inputs: two launches
 
 template <typename Tin>
 hipError_t scan(const Tin *in, uint64_t *out, size_t n, uint64_t *scratch, hipStream_t s)
@@ -128,6 +164,11 @@ hipError_t scan(const Tin *in, uint64_t *out, size_t n, uint64_t *scratch, hipSt
     }
     const size_t nb = (n + kTile - 1) / kTile;
     GD_LAUNCH(k_scan_reduce<Tin>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
+    if (nb <= kFusedBlocks) {
+        GD_LAUNCH(k_scan_apply_fused<Tin>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+                  (const uint64_t *)scratch, nb);
+        return hipGetLastError();
+    }
     GD_LAUNCH(k_scan_top, dim3(1), dim3(kBlock), 0, s, scratch, nb);
     GD_LAUNCH(k_scan_apply<Tin>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
                        (const uint64_t *)scratch, nb);
