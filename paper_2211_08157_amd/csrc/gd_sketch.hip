@@ -53,16 +53,16 @@ struct SeqCache {
     const uint64_t *sh;     // LDS copy of pofs[lo .. lo + n]
     const uint64_t *offs;   // original offsets (global) and, if osh, their LDS copy
     const uint64_t *osh;
-    uint32_t lo, n;         // n == 0: no cache
+    uint32_t lo, n;         // n == 0: no cache (nothing was loaded into sh / osh)
     __device__ __forceinline__ uint64_t at(uint32_t s) const
     {
         const uint32_t d = s - lo;
-        return d <= n ? sh[d] : pofs[s];
+        return (n > 0 && d <= n) ? sh[d] : pofs[s];
     }
     __device__ __forceinline__ uint64_t orig(uint32_t s) const
     {
         const uint32_t d = s - lo;
-        return (osh && d <= n) ? osh[d] : offs[s];
+        return (osh && n > 0 && d <= n) ? osh[d] : offs[s];
     }
     // last s with pofs[s] <= j (j < pofs[n_seq])
     __device__ __forceinline__ uint32_t find(uint64_t j) const

@@ -51,6 +51,34 @@ def test_sparsify_matches_oracle(gpu, pattern):
         assert np.array_equal(got, ec)
 
 
+@pytest.mark.parametrize("n_seq", [70_000, 4_300_000])
+def test_sparsify_many_sequences(gpu, n_seq):
+    # sequence counts past one workgroup's scan (two launches) and past 4M (three launches)
+    rng = np.random.default_rng(n_seq)
+    lens = rng.integers(0, 9, n_seq)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    codes = rng.integers(0, 4, int(offs[-1]), dtype=np.uint8)
+    shifts = rng.integers(0, 3, n_seq).astype(np.uint32)
+    out, po = gpu.sparsify(dev(gpu, codes, offs), "110", shift=shifts)
+    ec, eo, _ = oracle.sparsify(codes, offs, "110", shifts=shifts)
+    assert np.array_equal(po.cpu().numpy(), eo.astype(np.int64))
+    assert np.array_equal(unpack(out.cpu().numpy(), ec.size), ec)
+
+
+def test_sketch_many_tiny_sequences(gpu):
+    # more sequences per tile than the tile's sequence cache holds (it is then bypassed)
+    rng = np.random.default_rng(77)
+    lens = rng.integers(0, 13, 70_000)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    codes = rng.integers(0, 4, int(offs[-1]), dtype=np.uint8)
+    for pattern, k, w in [("1", 3, 2), ("10", 3, 1)]:
+        keys, vals, mz = gpu.sketch(dev(gpu, codes, offs), pattern, k, w)
+        ek, ev, em = oracle.sketch(codes, offs, pattern, k, w)
+        assert np.array_equal(mz.cpu().numpy().view(np.uint64), em)
+        assert np.array_equal(u64(keys), ek)
+        assert np.array_equal(u32(vals).astype(np.uint64), ev)
+
+
 SKETCH_CASES = [("10", 15, 10), ("10", 21, 11), ("110", 21, 11), ("1", 15, 12), ("1", 19, 19),
                 ("1", 28, 40), ("101001", 13, 5), ("1", 4, 1), ("10", 2, 3), ("1", 32, 2),
                 ("1110", 31, 17), ("100", 8, 6), ("1" * 64, 21, 11), ("1", 6, 256),
