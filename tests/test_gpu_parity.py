@@ -216,6 +216,27 @@ def _seed_compare(gpu, ref, roffs, reads, offs, pattern, k, w, **kw):
     return ea
 
 
+def test_seed_many_short_reads(gpu):
+    # 100,000 reads of 0-40 bases (many without a single window) against 200 kbp, and a
+    # reference of 70,000 tiny sequences for the 64-bit index: more sequences per tile
+    # and per sparsify workgroup than the sequence cache holds
+    ref = datagen.random_genome(200_000, 61)
+    rng = np.random.default_rng(62)
+    lens = rng.integers(0, 41, 100_000)
+    starts = rng.integers(0, ref.size - 41, lens.size)
+    reads = np.concatenate([ref[s:s + n] for s, n in zip(starts, lens)]).astype(np.uint8)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    ea = _seed_compare(gpu, ref, np.array([0, ref.size], np.int64), reads, offs, "10", 9, 5)
+    assert ea.shape[0] > 50_000
+    tl = rng.integers(0, 13, 70_000)
+    toffs = np.concatenate([[0], np.cumsum(tl)]).astype(np.int64)
+    tcodes = rng.integers(0, 4, int(toffs[-1]), dtype=np.uint8)
+    ix = gpu.index_build(dev(gpu, tcodes, toffs), "1", 5, 3, val_bits=64)
+    ek, ev = oracle.index_build(tcodes, toffs, "1", 5, 3, val_bits=64)
+    assert np.array_equal(u64(ix.keys), ek)
+    assert np.array_equal(u64(ix.vals), ev)
+
+
 def test_seed_tiny_workload_full(gpu):
     d = datagen.workload_tiny()
     ea = _seed_compare(gpu, d["ref"], d["ref_offsets"], d["reads"], d["read_offsets"], "10", 15, 10)
