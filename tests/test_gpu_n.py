@@ -74,6 +74,25 @@ def test_sparsify_carries_the_n_mask(gpu, pattern):
         assert np.array_equal(got[~isn], ec[~isn])
 
 
+@pytest.mark.parametrize("pattern", ["10", "110"])
+def test_n_mask_of_many_tiny_sequences(gpu, pattern):
+    # more sequences per sparsify workgroup and per sketch tile than the sequence cache holds
+    rng = np.random.default_rng(91)
+    codes, offs = gapped_batch(90, rng.integers(0, 13, 70_000), runs=20, singles=20_000)
+    shifts = rng.integers(0, len(pattern), 70_000).astype(np.uint32)
+    out, po, pn = gpu.sparsify(gpu.to_device(codes, offs), pattern, shift=shifts, with_nmask=True)
+    ec, eo, _ = oracle.sparsify(codes, offs, pattern, shifts=shifts)
+    assert np.array_equal(po.cpu().numpy(), eo.astype(np.int64))
+    isn = bits(pn.cpu().numpy(), ec.size)
+    assert np.array_equal(isn, ec == 4)
+    assert np.array_equal(unpack(out.cpu().numpy(), ec.size)[~isn], ec[~isn])
+    keys, vals, mz = gpu.sketch(gpu.to_device(codes, offs), pattern, 3, 2)
+    ek, ev, em = oracle.sketch(codes, offs, pattern, 3, 2)
+    assert np.array_equal(mz.cpu().numpy().view(np.uint64), em)
+    assert np.array_equal(u64(keys), ek)
+    assert np.array_equal(u32(vals).astype(np.uint64), ev)
+
+
 CASES = [("10", 21, 11), ("110", 21, 11), ("1", 15, 10), ("1", 16, 5), ("10", 2, 3),
          ("1", 19, 19), ("1", 28, 40), ("101001", 13, 5), ("1", 6, 256), ("1", 4, 1),
          ("1110", 31, 17), ("1", 32, 2)]
