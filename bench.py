@@ -456,6 +456,49 @@ def gather_rate(torch, n_keys, n_q, reps=5):
     return n_q / (ms * 1e-3)
 
 
+def lookups_1gbp(gd, torch, ref, reads, reps):
+    """Learned index against binary search on the 1 Gbp index (pattern 10, k=21, w=11):
+    500M queries, 80 % drawn from the mixed batch's read minimizers and 20 % random 64-bit
+    keys (seeded device generator), two-stage FP32 model with an MLP root and 2^18 leaves.
+    Both must return identical (lower bound, run length) for every query."""
+    ix = gd.index_build(ref, "10", 21, 11)
+    rk, _, _ = gd.sketch(reads, "10", 21, 11)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(404)
+    n_total = 500_000_000
+    n_abs = n_total // 5
+    n_pres = n_total - n_abs
+    q = torch.empty(n_total, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, rk.numel(), (n_pres,), device="cuda", generator=g)
+    q[:n_pres] = rk[idx]
+    del idx, rk
+    q[n_pres:] = torch.randint(-2**63, 2**63 - 1, (n_abs,), dtype=torch.int64, device="cuda",
+                               generator=g)
+    out = dict(queries=n_total, index_records=ix.n)
+    ref_lb = ref_occ = None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, index in (("binary_search", ix),
+                        ("learned_index", gd.rmi_train(ix, root="mlp", log2_leaves=18))):
+        lb, occ = gd.lookup(index, q)
+        e0.record()
+        for _ in range(reps):
+            lb, occ = gd.lookup(index, q)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if ref_lb is None:
+            ref_lb, ref_occ = lb, occ
+        elif not (torch.equal(lb, ref_lb) and torch.equal(occ, ref_occ)):
+            raise RuntimeError("learned-index lookups differ from binary search")
+        out[name] = dict(ms=ms, lookups_per_s=n_total / (ms * 1e-3))
+        del lb, occ
+    out["found"] = int((ref_occ != 0).sum().item())
+    out["learned_vs_binary_speedup"] = out["binary_search"]["ms"] / out["learned_index"]["ms"]
+    del q, ref_lb, ref_occ, ix
+    torch.cuda.empty_cache()
+    return out
+
+
 def uneven_batch(gd, torch, steps):
     """The 1 Gbp reference with the mixed batch of 2M short, 20k HiFi-like and 20k
     ONT-like reads: one seeding pass (learned index sized at ~32 keys per leaf) captured
@@ -527,6 +570,9 @@ def uneven_batch(gd, torch, steps):
         torch.cuda.empty_cache()
     out["reads"] = n_reads
     out["bases"] = n_bases
+    out["lookups_500M"] = lookups_1gbp(gd, torch, ref, reads, max(2, steps // 2))
+    log("[bench] 500M lookups in the 1 Gbp index: binary search %.1f ms, learned index %.1f ms"
+        % (out["lookups_500M"]["binary_search"]["ms"], out["lookups_500M"]["learned_index"]["ms"]))
     return out
 
 
