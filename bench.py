@@ -499,6 +499,43 @@ def lookups_1gbp(gd, torch, ref, reads, reps):
     return out
 
 
+def containment(gd, torch, reps):
+    """Containment-style search: the 1,000-genome database (pattern 10, k=21, w=11, values
+    carrying the genome id) and 10M x 150 bp reads drawn from 50 of its genomes; one call
+    gives every genome's count of distinct minimizers shared with the reads, through binary
+    search and through the learned index (identical counts required)."""
+    import datagen
+    d = datagen.workload_containment()
+    ng = d["ref_offsets"].size - 1
+    db = gd.to_device(d["ref"], d["ref_offsets"])
+    reads = gd.to_device(d["reads"], d["read_offsets"])
+    n_reads, db_bases = reads.n_seq, db.n_bases
+    del d
+    ix = gd.index_build(db, "10", 21, 11, val_bits=64)
+    del db
+    out = dict(genomes=ng, database_bases=db_bases, index_records=ix.n, reads=n_reads)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ref_counts = None
+    for name, index in (("binary_search", ix),
+                        ("learned_index", gd.rmi_train(ix, root="mlp", log2_leaves=18))):
+        counts, sizes = gd.contain(index, reads, "10", 21, 11, ng)
+        e0.record()
+        for _ in range(reps):
+            counts, sizes = gd.contain(index, reads, "10", 21, 11, ng)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if ref_counts is None:
+            ref_counts = counts.clone()
+        elif not torch.equal(counts, ref_counts):
+            raise RuntimeError("learned-index containment counts differ from binary search")
+        out[name] = dict(ms=ms, reads_per_s=n_reads / (ms * 1e-3))
+    out["genomes_with_shared_minimizers"] = int((ref_counts != 0).sum().item())
+    del ix, reads, ref_counts
+    torch.cuda.empty_cache()
+    return out
+
+
 def uneven_batch(gd, torch, steps):
     """The 1 Gbp reference with the mixed batch of 2M short, 20k HiFi-like and 20k
     ONT-like reads: one seeding pass (learned index sized at ~32 keys per leaf) captured
@@ -654,7 +691,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1_000_000)
     ap.add_argument("--no-1gbp", action="store_true",
-                    help="skip the 1 Gbp reference sketch and the uneven 1 Gbp batch")
+                    help="skip the 1 Gbp reference sketch, the uneven 1 Gbp batch, the 500M lookups "
+                         "and the 1,000-genome containment search")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gapped-workload step and the seed-matching experiment")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -802,8 +840,15 @@ def main():
         del bseq
         torch.cuda.empty_cache()
         uneven = uneven_batch(gd, torch, max(3, args.steps // 4))
+        torch.cuda.empty_cache()
+        log("[bench] generating the 1,000-genome containment database and 10M reads")
+        contain = containment(gd, torch, max(2, args.steps // 4))
+        log("[bench] containment, 1,000 genomes / 10M reads: binary search %.2f ms, learned "
+            "index %.2f ms (%.3e reads/s)" % (contain["binary_search"]["ms"],
+                                              contain["learned_index"]["ms"],
+                                              contain["learned_index"]["reads_per_s"]))
     else:
-        uneven = None
+        uneven = contain = None
     copy_bw = copy_gbps(torch)
     log("[bench] device copy %.0f GB/s; random gathers %.3e per s" % (copy_bw, lookup_gather))
 
@@ -844,6 +889,7 @@ def main():
         "n_aware_step": gapped,
         "seed_matching_experiment": fig4,
         "uneven_batch_1Gbp": uneven,
+        "containment_1000_genomes": contain,
         "measured_copy_GBps": copy_bw,
         "sketch_frac_of_measured_copy": gbps / copy_bw,
         "random_gather_per_s": lookup_gather,
