@@ -11,7 +11,12 @@ substitutions, 0.05 % indels, both strands), pattern "10", k=21, w=11.
 
 Prints one JSON line: reads/s of the whole step, the dominant kernel's roofline
 (timed live with HIP events on the stream the kernels run on), sketch GB/s of the
-reference, and the CPU oracle timed on a bounded sample.
+reference, and the CPU oracle timed on a bounded sample.  Beside the headline: the same
+step with binary search, with the hash-table index and with index construction on a
+second stream; location voting and its per-read sorts; the step on a workload with
+ambiguous bases; the seed-matching experiment; and (skipped with --no-1gbp) the 1 Gbp
+sketch, the uneven-length batch as one graph replay, 500M lookups in the 1 Gbp index and
+the 1,000-genome containment search.
 """
 import argparse
 import ctypes
