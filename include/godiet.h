@@ -185,6 +185,16 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs,
  * pattern. */
 uint64_t godiet_kept_bound(const godiet_seqs *seqs, const char *pattern);
 
+/* [host] Upper bound on the number of minimizer records a sketch of the batch can emit
+ * (Section 3.1 step 3: every minimizer is a k-mer of a patterned sequence): the sum over
+ * sequences s of max(0, K_s - k + 1), where K_s is the largest kept count of sequence s
+ * under any shift (so the bound holds for the reference at shift 0 and for reads at every
+ * shift of pattern alignment).  Unlike every other call, this one reads seqs->offsets on
+ * the HOST: pass a godiet_seqs whose offsets array (n_seq + 1 entries) is host memory;
+ * bases and nmask are not read (ambiguous bases only remove k-mers).  Returns UINT64_MAX
+ * on invalid arguments (bad pattern or k, NULL offsets, decreasing offsets). */
+uint64_t godiet_sketch_bound(const godiet_seqs *seqs, const godiet_sketch_params *prm);
+
 /* [host] Bytes godiet_sparsify writes to out_bases (a multiple of 4, including zero
  * padding), or 0 on a bad pattern. */
 size_t godiet_sparsify_bytes(const godiet_seqs *seqs, const char *pattern);

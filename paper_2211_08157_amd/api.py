@@ -75,6 +75,8 @@ def lib():
         L.godiet_workspace_size.restype = sz
         L.godiet_kept_bound.argtypes = [S(Seqs), ctypes.c_char_p]
         L.godiet_kept_bound.restype = u64
+        L.godiet_sketch_bound.argtypes = [S(Seqs), S(Params)]
+        L.godiet_sketch_bound.restype = u64
         L.godiet_sparsify_bytes.argtypes = [S(Seqs), ctypes.c_char_p]
         L.godiet_sparsify_bytes.restype = sz
         L.godiet_sparsify.argtypes = [S(Seqs), ctypes.c_char_p, P, P, P, P, P, sz, P, P]

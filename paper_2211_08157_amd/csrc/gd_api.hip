@@ -262,6 +262,34 @@ uint64_t godiet_kept_bound(const godiet_seqs *seqs, const char *pattern)
     return kept_bound(seqs, P);
 }
 
+uint64_t godiet_sketch_bound(const godiet_seqs *seqs, const godiet_sketch_params *prm)
+{
+    Pattern P;
+    if (!seqs || !seqs->offsets || !prm || !parse_pattern(prm->pattern, &P) || prm->k < 1 ||
+        prm->k > 32)
+        return UINT64_MAX;
+    // most[r]: the largest number of ones among r consecutive characters of the cyclic
+    // pattern, i.e. the largest kept count of the first r bases of a period over all shifts
+    uint32_t most[kMaxPattern + 1];
+    for (uint32_t r = 0; r <= P.p; r++) {
+        uint32_t best = 0;
+        for (uint32_t a = 0; a < P.p; a++) {
+            uint32_t c = 0;
+            for (uint32_t t = 0; t < r; t++) c += pattern_bit(P, (a + t) % P.p) ? 1u : 0u;
+            best = c > best ? c : best;
+        }
+        most[r] = best;
+    }
+    uint64_t total = 0;
+    for (uint32_t s = 0; s < seqs->n_seq; s++) {
+        if (seqs->offsets[s + 1] < seqs->offsets[s]) return UINT64_MAX;
+        const uint64_t L = seqs->offsets[s + 1] - seqs->offsets[s];
+        const uint64_t K = (L / P.p) * P.x + most[L % P.p];
+        if (K >= (uint64_t)prm->k) total += K - (uint64_t)prm->k + 1;
+    }
+    return total;
+}
+
 size_t godiet_sparsify_bytes(const godiet_seqs *seqs, const char *pattern)
 {
     Pattern P;

@@ -222,3 +222,37 @@ def test_vote_rejects_unknown_sort():
     r = L.godiet_vote(dummy, dummy, 4, 10, ctypes.byref(VoteOpts(16, 3, 4, 4)), dummy, dummy,
                       dummy, 1 << 30, dummy, None)
     assert r == -1
+
+
+@pytest.mark.parametrize("pattern", ["1", "10", "110", "101001", "1000101001", "0" * 70 + "1" * 3])
+def test_sketch_bound_against_brute_force(pattern):
+    """godiet_sketch_bound = sum over sequences of max(0, K - k + 1), K the largest kept
+    count over all shifts, each kept count counted base by base (Section 3.1 step 3)."""
+    from paper_2211_08157_amd.api import Params, Seqs
+    L = _lib()
+    rng = np.random.default_rng(7)
+    lens = np.concatenate([[0, 1, 2, 20, 21, 22, 23], rng.integers(0, 400, 40)]).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    p = len(pattern)
+    for k in (1, 15, 21):
+        want = 0
+        for n in lens:
+            K = max(sum(pattern[(j - a) % p] == "1" for j in range(int(n))) for a in range(p))
+            want += max(0, K - k + 1)
+        s = Seqs(0x1000, offs.ctypes.data, lens.size, int(offs[-1]))
+        got = L.godiet_sketch_bound(ctypes.byref(s), ctypes.byref(Params(pattern.encode(), k, 11, 0)))
+        assert got == want, (pattern, k)
+
+
+def test_sketch_bound_rejects_bad_arguments():
+    from paper_2211_08157_amd.api import Params, Seqs
+    L = _lib()
+    offs = np.array([0, 10, 5], np.uint64)                 # decreasing
+    s = Seqs(0x1000, offs.ctypes.data, 2, 5)
+    assert L.godiet_sketch_bound(ctypes.byref(s), ctypes.byref(Params(b"10", 15, 11, 0))) == 2**64 - 1
+    ok = np.array([0, 10], np.uint64)
+    s = Seqs(0x1000, ok.ctypes.data, 1, 10)
+    assert L.godiet_sketch_bound(ctypes.byref(s), ctypes.byref(Params(b"12", 15, 11, 0))) == 2**64 - 1
+    assert L.godiet_sketch_bound(ctypes.byref(s), ctypes.byref(Params(b"10", 33, 11, 0))) == 2**64 - 1
+    assert L.godiet_sketch_bound(ctypes.byref(Seqs(0x1000, None, 1, 10)),
+                                 ctypes.byref(Params(b"10", 15, 11, 0))) == 2**64 - 1
