@@ -149,6 +149,67 @@ def index_build(codes, offsets, pattern, k, w, val_bits=32):
     return keys[:n].copy(), vals[:n].copy()
 
 
+def chunk_margin(pattern, k, w):
+    """Original bases on each side of a chunk that decide its minimizers: a k-mer at kept
+    position i is selected through the windows starting at i - w + 1 .. i, whose k-mers
+    cover kept positions i - w + 1 .. i + w + k - 2; w + k kept bases lie within
+    ceil((w + k) / x) + 1 periods.  A whole number of periods, so a chunk keeps the
+    sequence's pattern phase."""
+    p, x = len(pattern), pattern.count("1")
+    return p * (-(-(w + k) // x) + 2)
+
+
+def index_build_chunked(codes, pattern, k, w, threads, n_chunks=None):
+    """The seed index of ONE sequence built chunk by chunk on `threads` threads (harness
+    around index_build; the arithmetic is the oracle's): chunk c covers original
+    positions [a_c, b_c) (multiples of the period), is indexed as a sequence of its own
+    with chunk_margin() bases of context on both sides, and keeps the records whose
+    position lies in [a_c, b_c).  The sorted chunks are then merged by key ranges on the
+    threads (every chunk holds smaller positions than the next, so a stable sort by key
+    of the chunks in order is the (key, value) order).  32-bit values."""
+    from concurrent.futures import ThreadPoolExecutor
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    L = codes.size
+    p = len(pattern)
+    h = chunk_margin(pattern, k, w)
+    n_chunks = n_chunks or 4 * threads
+    step = max(p, -(-L // n_chunks) // p * p)
+    bounds = list(range(0, L, step)) + [L]
+
+    def one(c):
+        a, b = bounds[c], bounds[c + 1]
+        lo, hi = max(0, a - h), min(L, b + h)
+        ik, iv = index_build(codes[lo:hi], np.array([0, hi - lo], np.int64), pattern, k, w)
+        iv = iv + np.uint64(2 * lo)
+        pos = iv >> np.uint64(1)
+        keep = (pos >= np.uint64(a)) & (pos < np.uint64(b))
+        return ik[keep], iv[keep]
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(one, range(len(bounds) - 1)))
+    # key-range merge: cut points from one chunk's keys, each range sorted on a thread
+    cuts = np.unique(np.quantile(np.concatenate([pk[::max(1, pk.size // 64)] for pk, _ in parts]
+                                                + [np.zeros(1, np.uint64)]).astype(np.float64),
+                                 np.linspace(0, 1, threads + 1)[1:-1]).astype(np.uint64))
+    ranges = [[np.searchsorted(pk, cuts) for pk, _ in parts]]
+
+    def merge(r):
+        ks, vs = [], []
+        for (pk, pv), idx in zip(parts, ranges[0]):
+            lo = idx[r - 1] if r > 0 else 0
+            hi = idx[r] if r < idx.size else pk.size
+            ks.append(pk[lo:hi])
+            vs.append(pv[lo:hi])
+        kk = np.concatenate(ks)
+        vv = np.concatenate(vs)
+        order = np.argsort(kk, kind="stable")
+        return kk[order], vv[order]
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        out = list(ex.map(merge, range(cuts.size + 1)))
+    return np.concatenate([o[0] for o in out]), np.concatenate([o[1] for o in out])
+
+
 def lookup(keys, queries):
     """(lb, occ) of every query in the sorted key array."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)

@@ -116,9 +116,12 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->sp = sort_plan(expected, capacity, val_bytes);
     o->so.hist = b.take<uint32_t>(o->sp.digits ? o->sp.nchunks * o->sp.nfine : o->sp.nfine);
     o->so.tot = o->sp.digits ? b.take<uint32_t>(o->sp.nfine) : nullptr;
+    o->so.top = o->sp.digits ? b.take<uint32_t>(sort_top_bins()) : nullptr;
+    o->so.cdf = o->sp.digits ? b.take<uint64_t>(sort_top_bins() + 1) : nullptr;
     o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
     o->so.rank = o->sp.digits ? nullptr : b.take<uint32_t>(capacity);
-    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
+    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine > sort_top_bins() ? o->sp.nfine
+                                                                                 : sort_top_bins()));
     o->so.trec = b.take<ulonglong2>(capacity);
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
@@ -142,9 +145,12 @@ void plan_vote_ws(Bump &b, uint32_t n_reads, uint64_t capacity, VoteWs *o)
     o->sp = sort_plan(capacity, capacity > 0 ? capacity : 1, 4);
     o->so.hist = b.take<uint32_t>(o->sp.digits ? o->sp.nchunks * o->sp.nfine : o->sp.nfine);
     o->so.tot = o->sp.digits ? b.take<uint32_t>(o->sp.nfine) : nullptr;
+    o->so.top = o->sp.digits ? b.take<uint32_t>(sort_top_bins()) : nullptr;
+    o->so.cdf = o->sp.digits ? b.take<uint64_t>(sort_top_bins() + 1) : nullptr;
     o->so.fofs = b.take<uint64_t>(o->sp.nfine + 1);
     o->so.rank = o->sp.digits ? nullptr : b.take<uint32_t>(capacity);
-    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine));
+    o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine > sort_top_bins() ? o->sp.nfine
+                                                                                 : sort_top_bins()));
     o->so.trec = b.take<ulonglong2>(capacity);
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);

@@ -72,12 +72,25 @@ __device__ __forceinline__ uint64_t wang64(uint64_t key, uint64_t mask)
     return key;
 }
 
-// k-mer hash of a canonical code: kHash 0 = splitmix64 finalizer, 1 = Thomas Wang's hash.
+// mix64 of a code below 2^62 (k <= 31): z >> 30 then fits 32 bits, so the first
+// xor-shift leaves the high word alone and is one funnel shift and one xor.
+__device__ __forceinline__ uint64_t mix64_short(uint64_t z)
+{
+    const uint32_t lo = (uint32_t)z, hi = (uint32_t)(z >> 32);
+    z = ((uint64_t)hi << 32) | (lo ^ __builtin_amdgcn_alignbit(hi, lo, 30));
+    z *= 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// k-mer hash of a canonical code: kHash 0 = splitmix64 finalizer of a code of k <= 31
+// bases, 1 = Thomas Wang's hash, 2 = splitmix64 finalizer of any code (k = 32).
 template <int kHash>
 __device__ __forceinline__ uint64_t kmer_hash(uint64_t code, uint64_t mask)
 {
     if constexpr (kHash == 1) return wang64(code, mask);
-    else return mix64(code);
+    else if constexpr (kHash == 2) return mix64(code);
+    else return mix64_short(code);
 }
 
 // Pattern rotated right by a: bit t set iff P[(t - a) mod p] == '1' (p <= 64 only).

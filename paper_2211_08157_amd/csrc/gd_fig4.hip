@@ -416,6 +416,7 @@ hipError_t launch_seed_match(const godiet_seqs *a, const godiet_seqs *b, const P
     A.status = status;
     const unsigned grid = a->n_seq < 65536u ? a->n_seq : 65536u;
     if (hash == 1) GD_LAUNCH(k_seed_match<1>, dim3(grid), dim3(kBlock), 0, s, A);
+    else if (k == 32) GD_LAUNCH(k_seed_match<2>, dim3(grid), dim3(kBlock), 0, s, A);
     else GD_LAUNCH(k_seed_match<0>, dim3(grid), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }

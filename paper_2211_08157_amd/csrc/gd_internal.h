@@ -128,17 +128,21 @@ struct SortPlan {
     size_t nfine;          // 2^Bf fine bins
     size_t target;         // records per coarse bucket
     size_t ncoarse;        // coarse buckets launched
-    bool digits;           // counting pass by top Bf bits with workgroup-local counters
+    bool digits;           // counting pass of balanced digits with workgroup-local counters
     size_t nchunks;        // digits mode: record chunks (one workgroup each)
+    size_t chunk;          // digits mode: records per chunk
 };
 SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes);
+size_t sort_top_bins();    // slices of the digits mode's key histogram
 // Scratch pieces the sort needs.
 struct SortWs {
     uint32_t *hist;        // nfine (digits mode: nchunks * nfine per-chunk digit counts)
     uint32_t *tot;         // digits mode: nfine digit totals
+    uint32_t *top;         // digits mode: sort_top_bins() key-slice counts
+    uint64_t *cdf;         // digits mode: sort_top_bins() + 1 cumulative slice counts
     uint64_t *fofs;        // nfine + 1
     uint32_t *rank;        // capacity: rank of each record inside its fine bin
-    uint64_t *scan_tmp;    // scan_scratch(nfine)
+    uint64_t *scan_tmp;    // scan_scratch(max(nfine, sort_top_bins()))
     ulonglong2 *trec;      // capacity: (key, value) records grouped by fine bin
     uint32_t *cstart;      // ncoarse + 1: first fine bin of each coarse bucket
     uint32_t *overflow;    // ncoarse

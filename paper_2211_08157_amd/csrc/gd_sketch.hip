@@ -68,7 +68,19 @@ struct SeqCache {
     __device__ __forceinline__ uint32_t find(uint64_t j) const
     {
         if (n > 0 && j >= sh[0] && j < sh[n]) {
-            uint32_t a = 0, b = n;          // sh[a] <= j < sh[b]
+            // the guess that is exact for sequences of equal length (a batch of reads),
+            // then bisection on the side it leaves
+            const float f = (float)(j - sh[0]) * ((float)n / (float)(sh[n] - sh[0]));
+            uint32_t g = f < (float)n ? (uint32_t)f : n - 1;
+            uint32_t a, b;                  // sh[a] <= j < sh[b]
+            if (sh[g] <= j) {
+                if (j < sh[g + 1]) return lo + g;
+                a = g + 1;
+                b = n;
+            } else {
+                a = 0;
+                b = g;
+            }
             while (b - a > 1) {
                 const uint32_t m = (a + b) >> 1;
                 if (sh[m] <= j) a = m; else b = m;
@@ -627,27 +639,31 @@ __device__ __forceinline__ uint32_t mask_le(int64_t x)
 }
 
 
-// Minimizer selection for the 16 positions of this thread, w = W known at compile time.
-// Window minima of the windows starting in the chunk come from the chunk's suffix minima
-// and the next chunk's prefix minima (windows reaching into it) or from a split at a
-// position common to all windows inside the chunk; the opening (max over the windows
-// containing a position) is built the same way from the previous chunk's suffix maxima.
-// ex is an LDS array of kE words used for the two neighbour exchanges.
-template <int W>
-__device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t selm, uint32_t winm,
-                                               uint64_t *ex, bool owner)
+// Minimizer selection for the 16 positions of this thread, w = W known at compile time,
+// on values of type T: the full 64-bit hashes, or their high 32-bit words (see
+// sketch_tile for how the result is kept exact).  Window minima of the windows starting
+// in the chunk come from the chunk's suffix minima and the next chunk's prefix minima
+// (windows reaching into it) or from a split at a position common to all windows inside
+// the chunk; the opening (max over the windows containing a position) is built the same
+// way from the previous chunk's suffix maxima.  ex is an LDS array of kE values of type T
+// used for the two neighbour exchanges.  Returns the owned positions equal to their
+// opening (and allowed by selm); *eq_all receives the same bits for any thread.
+template <int W, typename T>
+__device__ __forceinline__ uint32_t select_reg(const T (&v)[16], uint32_t selm, uint32_t winm,
+                                               T *ex, bool owner, uint32_t *eq_all = nullptr)
 {
+    constexpr T kTop = ~T(0);
     const int t = threadIdx.x;
-    uint64_t P[16], S[16], mw[16];
+    T P[16], S[16], mw[16];
     P[0] = v[0];
 #pragma unroll
     for (int u = 1; u < 16; u++) P[u] = min(P[u - 1], v[u]);
 #pragma unroll
     for (int u = 0; u < W - 1; u++) ex[u * kBlock + t] = P[u];
     __syncthreads();
-    uint64_t Pn[W > 1 ? W - 1 : 1];
+    T Pn[W > 1 ? W - 1 : 1];
 #pragma unroll
-    for (int u = 0; u < W - 1; u++) Pn[u] = t + 1 < kBlock ? ex[u * kBlock + t + 1] : kMax64;
+    for (int u = 0; u < W - 1; u++) Pn[u] = t + 1 < kBlock ? ex[u * kBlock + t + 1] : kTop;
     __syncthreads();
     S[15] = v[15];
 #pragma unroll
@@ -658,7 +674,7 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     // windows inside the chunk (none when W == 17)
     if constexpr (W >= 9 && W <= 16) {
         constexpr int m = 16 - W;               // contained in every inner window
-        uint64_t SA[m + 1], PB[16];
+        T SA[m + 1], PB[16];
         SA[m] = v[m];
 #pragma unroll
         for (int s = m - 1; s >= 0; s--) SA[s] = min(SA[s + 1], v[s]);
@@ -670,7 +686,7 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     } else if constexpr (W <= 8) {
 #pragma unroll
         for (int s = 0; s <= 16 - W; s++) {
-            uint64_t x = v[s];
+            T x = v[s];
 #pragma unroll
             for (int d = 1; d < W; d++) x = min(x, v[s + d]);
             mw[s] = x;
@@ -678,20 +694,20 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     }
     if (__ballot(winm != 0xFFFFu) != 0) {       // skipped by waves whose windows are all valid
 #pragma unroll
-        for (int s = 0; s < 16; s++) mw[s] = ((winm >> s) & 1u) ? mw[s] : 0;
+        for (int s = 0; s < 16; s++) mw[s] = ((winm >> s) & 1u) ? mw[s] : T(0);
     }
 
     // opening
-    uint64_t SM[16], PM[16], op[16];
+    T SM[16], PM[16], op[16];
     SM[15] = mw[15];
 #pragma unroll
     for (int u = 14; u >= 0; u--) SM[u] = max(SM[u + 1], mw[u]);
 #pragma unroll
     for (int u = 17 - W; u < 16; u++) ex[u * kBlock + t] = SM[u];
     __syncthreads();
-    uint64_t Sp[W > 1 ? W - 1 : 1];
+    T Sp[W > 1 ? W - 1 : 1];
 #pragma unroll
-    for (int j = 0; j < W - 1; j++) Sp[j] = t > 0 ? ex[(17 - W + j) * kBlock + t - 1] : 0;
+    for (int j = 0; j < W - 1; j++) Sp[j] = t > 0 ? ex[(17 - W + j) * kBlock + t - 1] : T(0);
     PM[0] = mw[0];
 #pragma unroll
     for (int u = 1; u < 16; u++) PM[u] = max(PM[u - 1], mw[u]);
@@ -699,7 +715,7 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     for (int u = 0; u < (W - 1 < 16 ? W - 1 : 16); u++) op[u] = max(PM[u], Sp[u]);
     if constexpr (W >= 9 && W <= 16) {
         constexpr int m = W - 1;                // contained in every inner range
-        uint64_t SA[m + 1], PB[16];
+        T SA[m + 1], PB[16];
         SA[m] = mw[m];
 #pragma unroll
         for (int s = m - 1; s >= 0; s--) SA[s] = max(SA[s + 1], mw[s]);
@@ -714,7 +730,7 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     } else if constexpr (W <= 8) {
 #pragma unroll
         for (int u = (W - 1 > 0 ? W - 1 : 0); u < 16; u++) {
-            uint64_t x = mw[u];
+            T x = mw[u];
 #pragma unroll
             for (int d = 1; d < W; d++) x = max(x, mw[u - d]);
             op[u] = x;
@@ -723,7 +739,9 @@ __device__ __forceinline__ uint32_t select_reg(const uint64_t (&v)[16], uint32_t
     uint32_t eq = 0;
 #pragma unroll
     for (int u = 0; u < 16; u++) eq |= (v[u] == op[u] ? 1u : 0u) << u;
-    return owner ? eq & selm : 0u;
+    eq &= selm;
+    if (eq_all) *eq_all = eq;
+    return owner ? eq : 0u;
 }
 
 // Any w: window minima and the opening by doubling in LDS (ex holds kE words).
@@ -865,7 +883,7 @@ __device__ __forceinline__ void run_masks(const NB &nb, const SeqCache &C, int64
 template <int W, int HK>
 __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
                                             uint64_t n_tiles, uint64_t *ex, uint64_t *sh_scan,
-                                            uint64_t *sh_base_p, const SeqCache &C,
+                                            uint64_t *sh_misc, const SeqCache &C,
                                             const uint8_t *ones)
 {
     const int t = threadIdx.x;
@@ -998,15 +1016,76 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         }
     }
 
-    // ---- stage 2: minimizer selection (window minima, then the opening)
+    // ---- stage 2: minimizer selection (window minima, then the opening).
+    // For w = 3..17 the reductions first run on the hashes' high 32-bit words (one 32-bit
+    // min or max per step instead of a 64-bit compare and two selects).  A k-mer equal to
+    // the minimum of a window also has the smallest high word of that window, so every
+    // minimizer is selected, and a k-mer is selected wrongly only if, in some window, two
+    // positions share the smallest high word with different hashes.  Then two positions
+    // that are consecutive among the selected ones lie in that window with equal high
+    // words and different hashes (no selected position can lie between two positions of
+    // a window that attain its smallest high word).  Such a pair is either two consecutive
+    // owned records of this tile or the tile's first owned record and the last position of
+    // the chunk before the owned range that the same rule selects there (with fewer
+    // windows in view it selects a subset, which still holds the pair).  The tile checks
+    // every such pair on its compacted records; if one matches, or the records do not fit
+    // the exchange array, it selects again on the full hashes.
     const bool owner = 16 * t >= H && 16 * t < H + T;
-    uint32_t sel;
-    if constexpr (W > 0) sel = select_reg<W>(hv, selm, winm, ex, owner);
-    else sel = select_lds(hv, selm, winm, ex, w, owner);
+    const int vbytes = A.val_mode == VAL_SEQ64 ? 8 : 4;
+    uint32_t sel = 0;
+    uint64_t total = 0, excl = 0;
+    bool staged = false;
+    // exclusive record offset of this thread, the tile's count, whether it is staged
+    auto count = [&]() {
+        uint32_t tot32;
+        excl = block_excl_scan<uint32_t>((uint32_t)__popc(sel), (uint32_t *)sh_scan, &tot32);
+        total = tot32;
+        staged = total * (uint64_t)(8 + vbytes) <= (uint64_t)kE * 8;     // workgroup-uniform
+    };
+    // the selected hashes, compacted in position order into the exchange array
+    auto compact = [&]() {
+        uint32_t loc = (uint32_t)excl;
+#pragma unroll
+        for (int u = 0; u < 16; u++)
+            if ((sel >> u) & 1u) ex[loc++] = hv[u];
+    };
+    bool full = true;
+    if constexpr (W >= 3) {
+        uint32_t hi[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) hi[u] = (uint32_t)(hv[u] >> 32);
+        uint32_t eq_all;
+        sel = select_reg<W, uint32_t>(hi, selm, winm, (uint32_t *)ex, owner, &eq_all);
+        if (t == H / 16 - 1) {                     // the chunk before the owned range
+            uint64_t last = 0;
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if ((eq_all >> u) & 1u) last = hv[u];
+            sh_misc[1] = last;
+            sh_misc[2] = eq_all != 0;
+        }
+        count();                                   // its barriers publish sh_misc
+        bool bad = !staged;
+        if (staged) {
+            compact();
+            __syncthreads();
+            for (uint32_t i = t; i < (uint32_t)total; i += kBlock) {
+                const uint64_t cur = ex[i];
+                const uint64_t prev = i > 0 ? ex[i - 1] : sh_misc[1];
+                const bool has = i > 0 || sh_misc[2] != 0;
+                if (has && (cur >> 32) == (prev >> 32) && cur != prev) bad = true;
+            }
+        }
+        full = __syncthreads_or(bad) != 0;
+    }
+    if (full) {
+        if constexpr (W > 0) sel = select_reg<W, uint64_t>(hv, selm, winm, ex, owner);
+        else sel = select_lds(hv, selm, winm, ex, w, owner);
+        count();
+        if (staged) compact();
+    }
 
     // ---- stage 3: position-ordered compaction across tiles (decoupled look-back)
-    uint64_t total;
-    const uint64_t excl = block_excl_scan<uint64_t>((uint64_t)__popc(sel), sh_scan, &total);
     // Wave 0 publishes this tile's aggregate, then looks back over 64 predecessors per
     // step: it adds every aggregate up to the nearest tile that already carries its
     // inclusive prefix, and waits only while one of the tiles in between has not
@@ -1042,7 +1121,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             if (tile != 0)
                 __hip_atomic_store(&A.tile_state[tile], kFlagP | (before + total),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            *sh_base_p = before;
+            sh_misc[0] = before;
             if (tile == n_tiles - 1) {
                 if (A.n_out) *A.n_out = before + total;
                 if (before + total > A.capacity) set_status(A.status, 1u);
@@ -1050,24 +1129,18 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         }
     }
     // Records leave the tile in position order.  When they fit in the exchange array
-    // (12 or 16 bytes each, which every tile does unless w is tiny), the keys are compacted
-    // there straight from registers and the values after them, and the workgroup then
-    // writes the tile's contiguous record range with coalesced stores; otherwise the
-    // hashes go to LDS by position and each thread writes its own records.  Every read of
-    // the exchange array finished before the scan's barriers.
-    const int vbytes = A.val_mode == VAL_SEQ64 ? 8 : 4;
-    const bool staged = total * (uint64_t)(8 + vbytes) <= (uint64_t)kE * 8;   // workgroup-uniform
-    if (staged) {
-        uint32_t loc = (uint32_t)excl;
-#pragma unroll
-        for (int u = 0; u < 16; u++)
-            if ((sel >> u) & 1u) ex[loc++] = hv[u];
-    } else {
+    // (12 or 16 bytes each, which every tile does unless w is tiny or the sequence is of
+    // low complexity), the keys were compacted there straight from registers, the values
+    // go after them, and the workgroup then writes the tile's contiguous record range
+    // with coalesced stores; otherwise the hashes go to LDS by position and each thread
+    // writes its own records.  Every read of the exchange array by the selection
+    // finished before the scan's barriers.
+    if (!staged) {
 #pragma unroll
         for (int u = 0; u < 16; u++) ex[u * kBlock + t] = hv[u];
     }
     __syncthreads();
-    const uint64_t tile_base = *sh_base_p;
+    const uint64_t tile_base = sh_misc[0];
     const uint64_t base = tile_base + excl;
     uint32_t *sv32 = (uint32_t *)(ex + total);          // staged values, after the keys
     uint64_t *sv64 = ex + total;
@@ -1173,7 +1246,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
 {
     __shared__ uint64_t ex[kE];       // neighbour exchange / sliding-reduction work array
     __shared__ uint64_t sh_scan[kBlock / kWave];
-    __shared__ uint64_t sh_base;
+    __shared__ uint64_t sh_misc[3];   // tile base; key and flag of the record before the tile
     __shared__ uint32_t sh_tile;
     __shared__ uint64_t sh_pofs[kSeqCache];
     __shared__ uint8_t sh_ones[kMaxPattern];   // the pattern's kept offsets, read per record
@@ -1188,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
     const SeqCache C = seq_cache(A.pofs, A.n_seq, A.lohi, tile, sh_pofs);
-    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, &sh_base, C, sh_ones);
+    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, sh_misc, C, sh_ones);
 }
 
 }  // namespace
@@ -1296,6 +1369,11 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     A.status = status;
     A.inv_x = 1.0 / (double)P.x;
     const size_t grid = tiles;
+    if (hash == 0 && k == 32) {
+        // splitmix64 of full 64-bit codes: the general selection path (k = 32 is rare)
+        GD_LAUNCH((k_sketch<0, 2>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
+        return hipGetLastError();
+    }
     switch (w) {
 #define GD_W(n)                                                                             \
     case n:                                                                                 \

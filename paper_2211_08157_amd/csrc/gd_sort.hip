@@ -22,14 +22,19 @@
 // (hash, val) pairs are unique, so the result does not depend on the order in which the
 // scatter's atomics land.
 //
-// Indexes of up to ~10M records take a cheaper partition ("digits" mode): 2^14 digits of
-// the top key bits, counted per chunk of 32K records in LDS, turned into per-chunk digit
-// offsets by one thread per digit, and scattered with LDS atomics, so no record touches
-// a global atomic or a random global read.  The densest digit then holds about six times
-// the mean (~3.2K records at 8M), so coarse buckets target 512 records (at most 512 plus
-// one digit, within the LDS capacity); each is binned again in LDS by the next key bits
-// and its records placed by rank (k_digit_bucket_sort, in two launches sized for the
-// common and the dense buckets).
+// Indexes of up to ~190M records with 32-bit values (~48M with 64-bit values) take a
+// cheaper partition ("digits" mode) whose digits are balanced by the data: a histogram of
+// the keys' top 12 bits, scanned, maps a key to its approximate rank (the cumulative count
+// of its 12-bit slice plus its share of the slice, by the next 32 key bits, which is
+// monotone in the key), and the digit is that rank scaled to D <= 2^15 digits, so every
+// digit holds about N / D records whatever the skew of the hashes.  Digits are counted per
+// chunk of records in LDS, turned into per-chunk digit offsets by one thread per digit,
+// and scattered with LDS atomics, so no record touches a global atomic or a random global
+// read.  Coarse buckets of whole digits (about 2,048 records, at most that plus one
+// digit) are sorted in LDS: binned by their key's offset from the bucket's smallest key,
+// scaled to about two bins per record, and placed by rank inside their bin
+// (k_digit_bucket_sort, in two launches: half-capacity workgroups for the common buckets,
+// full-capacity ones of up to 160 KB of LDS for the largest).
 #include "gd_internal.h"
 
 namespace gd {
@@ -38,6 +43,9 @@ namespace {
 
 // records a workgroup sorts in LDS (a power of two, so bitonic padding fits)
 template <typename V> struct Cap { static constexpr int value = sizeof(V) == 4 ? 4096 : 2048; };
+// the digits mode's full-capacity buckets: 96 KB (32-bit values) or 64 KB (64-bit) of
+// records plus the sub-bins
+template <typename V> struct DCap { static constexpr int value = sizeof(V) == 4 ? 8192 : 4096; };
 constexpr int kSmall = 48;          // longest fine-bin run placed by ranking
 
 template <typename V>
@@ -73,24 +81,68 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *keys, const 
 }
 
 // ---- digits mode
-constexpr int kDigitBits = 14;
-constexpr int kChunk = 32768;       // records per counting / scatter workgroup
+constexpr int kDigitBits = 15;      // at most 2^15 digits (128 KB of LDS counters)
 constexpr int kBigBlock = 1024;
+constexpr int kTopBits = 12;        // slices of the key range whose counts balance the digits
+constexpr int kTop = 1 << kTopBits;
 
-__global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
-                                                           const uint64_t *n_ptr,
-                                                           uint64_t capacity, int Bd,
-                                                           uint32_t *mat)
+// Histogram of the keys' top kTopBits bits (per workgroup in LDS, then added globally).
+__global__ __launch_bounds__(kBigBlock) void k_top_hist(const uint64_t *keys, const uint64_t *n_ptr,
+                                                        uint64_t capacity, uint32_t *hist)
 {
-    __shared__ uint32_t cnt[1 << kDigitBits];
-    const uint32_t D = 1u << Bd;
-    for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) cnt[d] = 0;
+    __shared__ uint32_t h[kTop];
+    for (uint32_t d = threadIdx.x; d < (uint32_t)kTop; d += kBigBlock) h[d] = 0;
     __syncthreads();
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
-    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
-    const uint64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) atomicAdd(&cnt[keys[i] >> (64 - Bd)], 1u);
+    for (uint64_t i = blockIdx.x * (uint64_t)kBigBlock + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kBigBlock)
+        atomicAdd(&h[keys[i] >> (64 - kTopBits)], 1u);
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < (uint32_t)kTop; d += kBigBlock)
+        if (h[d]) atomicAdd(&hist[d], h[d]);
+}
+
+// Key -> digit, monotone in the key.  C (in LDS) holds the kTop + 1 cumulative slice
+// counts; a key's approximate rank is its slice's start plus the slice's count times the
+// key's position inside the slice (its next 32 bits), and the digit is rank * D / N.
+struct DigitMap {
+    const uint32_t *C;
+    uint64_t mul;                        // D * 2^32 / N
+    __device__ __forceinline__ void init(const uint64_t *cdf, uint32_t *lds, uint32_t D)
+    {
+        for (uint32_t j = threadIdx.x; j <= (uint32_t)kTop; j += blockDim.x) lds[j] = (uint32_t)cdf[j];
+        __syncthreads();
+        C = lds;
+        const uint64_t n = C[kTop];
+        mul = n ? ((uint64_t)D << 32) / n : 0;
+    }
+    __device__ __forceinline__ uint32_t operator()(uint64_t x) const
+    {
+        const uint32_t j = (uint32_t)(x >> (64 - kTopBits));
+        const uint32_t lo = C[j], cnt = C[j + 1] - lo;
+        const uint32_t f = (uint32_t)(x >> (64 - kTopBits - 32));
+        const uint32_t rank = lo + (uint32_t)(((uint64_t)cnt * f) >> 32);   // < N
+        return (uint32_t)(((uint64_t)rank * mul) >> 32);                    // < D
+    }
+};
+
+__global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
+                                                           const uint64_t *n_ptr,
+                                                           uint64_t capacity, uint32_t D,
+                                                           uint32_t chunk, const uint64_t *cdf,
+                                                           uint32_t *mat)
+{
+    __shared__ uint32_t cnt[1 << kDigitBits];
+    __shared__ uint32_t cl[kTop + 1];
+    for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) cnt[d] = 0;
+    DigitMap dm;
+    dm.init(cdf, cl, D);
+    uint64_t n = *n_ptr;
+    if (n > capacity) n = capacity;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) atomicAdd(&cnt[dm(keys[i])], 1u);
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) mat[(size_t)blockIdx.x * D + d] = cnt[d];
 }
@@ -125,20 +177,22 @@ __global__ __launch_bounds__(kBlock) void k_digit_offsets(uint32_t *mat, uint32_
 template <typename V>
 __global__ __launch_bounds__(kBigBlock) void k_digit_scatter(const uint64_t *keys, const V *vals,
                                                              const uint64_t *n_ptr,
-                                                             uint64_t capacity, int Bd,
+                                                             uint64_t capacity, uint32_t D,
+                                                             uint32_t chunk, const uint64_t *cdf,
                                                              const uint32_t *mat, ulonglong2 *trec)
 {
     __shared__ uint32_t off[1 << kDigitBits];
-    const uint32_t D = 1u << Bd;
+    __shared__ uint32_t cl[kTop + 1];
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) off[d] = mat[(size_t)blockIdx.x * D + d];
-    __syncthreads();
+    DigitMap dm;
+    dm.init(cdf, cl, D);
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
-    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
-    const uint64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) {
         const uint64_t key = keys[i];
-        const uint32_t pos = atomicAdd(&off[key >> (64 - Bd)], 1u);
+        const uint32_t pos = atomicAdd(&off[dm(key)], 1u);
         trec[pos] = make_ulonglong2(key, (uint64_t)vals[i]);
     }
 }
@@ -257,126 +311,176 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2 *trec,
     }
 }
 
-// Digits mode: a coarse bucket is a run of nd whole digits.  Its records are binned in
-// LDS by the key bits just below the digit (S of them, nd << S <= kSub sub-bins, about
-// two records each on average), the sub-bins are scanned and filled from registers, and
-// every record is then placed by its rank inside its sub-bin, as in k_bucket_sort.
-// Buckets spanning too many digits, or holding a long sub-bin, are bitonic-sorted.
-// Two launches share the buckets: most hold about the 512-record target and are sorted
-// by workgroups sized for half the LDS capacity (twice as many fit on a CU); the larger
-// ones (dense digits at the low end of the hash range) by full-capacity workgroups, which
-// also list the buckets beyond the capacity for the fallback.
-template <typename V, bool kFull>
-__global__ __launch_bounds__(kBlock) void k_digit_bucket_sort(const ulonglong2 *trec,
-                                                              const uint64_t *fofs,
-                                                              const uint32_t *cstart, int Bd,
-                                                              uint64_t *okeys, V *ovals,
-                                                              uint32_t *overflow,
-                                                              uint32_t *overflow_n)
+// In-LDS bitonic sort as lds_bitonic, for a workgroup of NT threads.
+template <typename V, int NT>
+__device__ void lds_bitonic_nt(uint64_t *K, V *Vv, int n)
 {
-    constexpr int kCap = kFull ? Cap<V>::value : Cap<V>::value / 2;
-    constexpr int kSub = kCap;                  // sub-bins
-    constexpr int kPer = kCap / kBlock;
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int i = n + threadIdx.x; i < P2; i += NT) { K[i] = kMax64; Vv[i] = (V)~(V)0; }
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P2 / 2; i += NT) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t ka = K[lo], kb = K[hi];
+                const V va = Vv[lo], vb = Vv[hi];
+                const bool gt = rec_less(kb, vb, ka, va);
+                if (gt == up) { K[lo] = kb; K[hi] = ka; Vv[lo] = vb; Vv[hi] = va; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Exclusive sum over the NT threads of a workgroup (sh: NT / kWave entries).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *sh)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; i++)
+        if (i < wv) before += sh[i];
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Digits mode: a coarse bucket is a run of whole digits holding more than kLo and at most
+// kCap records (three launches cover the sizes, with workgroups whose LDS and thread
+// count fit them).  Its records are binned in LDS by their key's offset from the
+// bucket's smallest key, scaled to NS bins (about two per record; monotone in the key),
+// the bins are scanned and filled from registers, and every record is then placed by its
+// rank inside its bin, as in k_bucket_sort.  A bucket holding a long bin (many equal
+// hashes) is bitonic-sorted; one beyond the largest capacity is listed for the fallback.
+template <typename V, int kCap, int kLo, int NT>
+__global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec,
+                                                          const uint64_t *fofs,
+                                                          const uint32_t *cstart,
+                                                          uint64_t *okeys, V *ovals,
+                                                          uint32_t *overflow,
+                                                          uint32_t *overflow_n, int last)
+{
+    constexpr int kSub = kCap;                  // bins
+    constexpr int kPer = kCap / NT;
     __shared__ uint64_t K[kCap];
     __shared__ V Vv[kCap];
     __shared__ uint32_t sub[kSub + 1];
-    __shared__ uint32_t sh_scan[kBlock / kWave];
+    __shared__ uint32_t sh_scan[NT / kWave];
+    __shared__ uint64_t sh_mm[2 * (NT / kWave)];
 
     const uint32_t d0 = cstart[blockIdx.x], d1 = cstart[blockIdx.x + 1];
     const uint64_t base = fofs[d0];
     const uint64_t n64 = fofs[d1] - base;
-    if (n64 == 0) return;
-    if (!kFull && n64 > (uint64_t)kCap) return;             // left to the full-size launch
-    if (kFull && n64 <= (uint64_t)(kCap / 2)) return;        // done by the half-size launch
+    if (n64 <= (uint64_t)kLo) return;                       // a smaller launch's bucket
     if (n64 > (uint64_t)kCap) {
-        if (threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
+        if (last && threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
         return;
     }
     const int n = (int)n64;
     const int t = threadIdx.x;
-    const uint32_t nd = d1 - d0;
-    int S = 0;
-    while (S < 16 && ((uint64_t)nd << (S + 1)) <= (uint64_t)kSub) S++;
-    const bool binned = ((uint64_t)nd << S) <= (uint64_t)kSub;
-    const uint32_t NS = binned ? nd << S : 0;
-    const int shs = 64 - Bd - S;
 
     ulonglong2 r[kPer];
+    uint64_t mn = kMax64, mx = 0;
 #pragma unroll
     for (int m = 0; m < kPer; m++) {
-        const int i = t + m * kBlock;
-        if (i < n) r[m] = trec[base + i];
+        const int i = t + m * NT;
+        if (i < n) {
+            r[m] = trec[base + i];
+            const uint64_t kx = r[m].x;       // (plain compares: no mixed-type min / max)
+            mn = kx < mn ? kx : mn;
+            mx = kx > mx ? kx : mx;
+        }
     }
-    int big = binned ? 0 : 1;
-    if (binned) {
-        for (uint32_t b = t; b <= NS; b += kBlock) sub[b] = 0;
-        __syncthreads();
-        uint32_t slot[kPer];
+    // the bucket's smallest and largest key
 #pragma unroll
-        for (int m = 0; m < kPer; m++) {
-            const int i = t + m * kBlock;
-            if (i < n) slot[m] = atomicAdd(&sub[(uint32_t)(r[m].x >> shs) - (d0 << S)], 1u);
-        }
-        __syncthreads();
-        // exclusive scan of sub[0, NS): each thread takes a run of consecutive entries
-        const uint32_t per = (NS + kBlock - 1) / kBlock;
-        const uint32_t b0 = t * per, b1 = b0 + per < NS ? b0 + per : NS;
-        uint32_t run = 0;
-        for (uint32_t b = b0; b < b1; b++) run += sub[b];
-        uint32_t total;
-        uint32_t acc = block_excl_scan<uint32_t>(run, sh_scan, &total);
-        for (uint32_t b = b0; b < b1; b++) {
-            const uint32_t c = sub[b];
-            sub[b] = acc;
-            acc += c;
-        }
-        if (t == 0) sub[NS] = (uint32_t)n;
-        __syncthreads();
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const uint64_t a = __shfl_xor(mn, d, kWave), b = __shfl_xor(mx, d, kWave);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if ((t & (kWave - 1)) == 0) {
+        sh_mm[t / kWave] = mn;
+        sh_mm[NT / kWave + t / kWave] = mx;
+    }
+    uint32_t NS = 2;
+    while (NS < 2 * (uint32_t)n && NS < (uint32_t)kSub) NS <<= 1;
+    for (uint32_t b = t; b <= NS; b += NT) sub[b] = 0;
+    __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kPer; m++) {
-            const int i = t + m * kBlock;
-            if (i < n) {
-                const uint32_t at = sub[(uint32_t)(r[m].x >> shs) - (d0 << S)] + slot[m];
-                K[at] = r[m].x;
-                Vv[at] = (V)r[m].y;
-            }
-        }
-    } else {
+    for (int i = 0; i < NT / kWave; i++) {
+        const uint64_t a = sh_mm[i], b = sh_mm[i + NT / kWave];
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    const float scale = (float)NS / ((float)(mx - mn) + 1.0f);
+    auto bin_of = [&](uint64_t x) -> uint32_t {
+        const uint32_t b = (uint32_t)((float)(x - mn) * scale);
+        return b < NS ? b : NS - 1;
+    };
+    uint32_t slot[kPer];
 #pragma unroll
-        for (int m = 0; m < kPer; m++) {
-            const int i = t + m * kBlock;
-            if (i < n) { K[i] = r[m].x; Vv[i] = (V)r[m].y; }
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * NT;
+        if (i < n) slot[m] = atomicAdd(&sub[bin_of(r[m].x)], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of sub[0, NS): each thread takes a run of consecutive entries
+    const uint32_t per = (NS + NT - 1) / NT;
+    const uint32_t b0 = t * per < NS ? t * per : NS, b1 = b0 + per < NS ? b0 + per : NS;
+    uint32_t run = 0;
+    for (uint32_t b = b0; b < b1; b++) run += sub[b];
+    uint32_t acc = block_excl_sum<NT>(run, sh_scan);
+    for (uint32_t b = b0; b < b1; b++) {
+        const uint32_t c = sub[b];
+        sub[b] = acc;
+        acc += c;
+    }
+    if (t == 0) sub[NS] = (uint32_t)n;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * NT;
+        if (i < n) {
+            const uint32_t at = sub[bin_of(r[m].x)] + slot[m];
+            K[at] = r[m].x;
+            Vv[at] = (V)r[m].y;
         }
     }
     __syncthreads();
     int pos[kPer];
-    if (binned) {
+    int big = 0;
 #pragma unroll
-        for (int m = 0; m < kPer; m++) {
-            const int i = t + m * kBlock;
-            pos[m] = i;
-            if (i >= n) continue;
-            const uint64_t k = K[i];
-            const V v = Vv[i];
-            const uint32_t b = (uint32_t)(k >> shs) - (d0 << S);
-            const int lo = (int)sub[b], hi = (int)sub[b + 1];
-            if (hi - lo > kSmall) {
-                big = 1;
-                continue;
-            }
-            int rank = 0;
-            for (int j = lo; j < hi; j++) rank += rec_less<V>(K[j], Vv[j], k, v) ? 1 : 0;
-            pos[m] = lo + rank;
+    for (int m = 0; m < kPer; m++) {
+        const int i = t + m * NT;
+        pos[m] = i;
+        if (i >= n) continue;
+        const uint64_t k = K[i];
+        const V v = Vv[i];
+        const uint32_t b = bin_of(k);
+        const int lo = (int)sub[b], hi = (int)sub[b + 1];
+        if (hi - lo > kSmall) {
+            big = 1;
+            continue;
         }
+        int rank = 0;
+        for (int j = lo; j < hi; j++) rank += rec_less<V>(K[j], Vv[j], k, v) ? 1 : 0;
+        pos[m] = lo + rank;
     }
     if (__syncthreads_or(big)) {
-        lds_bitonic<V>(K, Vv, n);
-        for (int i = t; i < n; i += kBlock) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
+        lds_bitonic_nt<V, NT>(K, Vv, n);
+        for (int i = t; i < n; i += NT) { okeys[base + i] = K[i]; ovals[base + i] = Vv[i]; }
         return;
     }
 #pragma unroll
     for (int m = 0; m < kPer; m++) {
-        const int i = t + m * kBlock;
+        const int i = t + m * NT;
         if (i < n) { okeys[base + pos[m]] = K[i]; ovals[base + pos[m]] = Vv[i]; }
     }
 }
@@ -465,16 +569,20 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
     if ((e = fill_u32(w.overflow_n, 0, 1, s)) != hipSuccess) return e;
     if (sp.digits) {
         const uint32_t D = (uint32_t)sp.nfine, nc = (uint32_t)sp.nchunks;
+        const uint32_t ch = (uint32_t)sp.chunk;
         const unsigned dg = (D + kBlock - 1) / kBlock;
-        GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, sp.Bf,
-                  w.hist);
+        if ((e = fill_u32(w.top, 0, kTop, s)) != hipSuccess) return e;
+        GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, w.top);
+        if ((e = exclusive_scan_u32(w.top, w.cdf, kTop, w.scan_tmp, s)) != hipSuccess) return e;
+        GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, D, ch,
+                  (const uint64_t *)w.cdf, w.hist);
         GD_LAUNCH(k_digit_totals, dim3(dg), dim3(kBlock), 0, s, (const uint32_t *)w.hist, nc, D,
                   w.tot);
         if ((e = exclusive_scan_u32(w.tot, w.fofs, D, w.scan_tmp, s)) != hipSuccess) return e;
         GD_LAUNCH(k_digit_offsets, dim3(dg), dim3(kBlock), 0, s, w.hist, nc, D,
                   (const uint64_t *)w.fofs);
         GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), 0, s, keys, vals, n_ptr, capacity,
-                  sp.Bf, (const uint32_t *)w.hist, w.trec);
+                  D, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.hist, w.trec);
     } else {
         if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
         const unsigned grid = 4096;
@@ -489,14 +597,19 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
     GD_LAUNCH(k_coarse_starts, dim3((unsigned)((sp.nfine + kBlock) / kBlock)), dim3(kBlock), 0, s,
               (const uint64_t *)w.fofs, (uint32_t)sp.nfine, (uint32_t)sp.target, w.cstart,
               (uint64_t)sp.ncoarse + 1);
-    if (sp.digits)
-    {
-        GD_LAUNCH((k_digit_bucket_sort<V, false>), dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
-                  (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
-                  (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
-        GD_LAUNCH((k_digit_bucket_sort<V, true>), dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
-                  (const ulonglong2 *)w.trec, (const uint64_t *)w.fofs,
-                  (const uint32_t *)w.cstart, sp.Bf, keys, vals, w.overflow, w.overflow_n);
+    if (sp.digits) {
+        // buckets by size: up to a quarter, a half and the whole of the largest capacity
+        constexpr int C = DCap<V>::value;
+        const dim3 g((unsigned)sp.ncoarse);
+        const ulonglong2 *tr = w.trec;
+        const uint64_t *fo = w.fofs;
+        const uint32_t *cs = w.cstart;
+        GD_LAUNCH((k_digit_bucket_sort<V, C / 4, 0, kBlock>), g, dim3(kBlock), 0, s, tr, fo, cs,
+                  keys, vals, w.overflow, w.overflow_n, 0);
+        GD_LAUNCH((k_digit_bucket_sort<V, C / 2, C / 4, 2 * kBlock>), g, dim3(2 * kBlock), 0, s,
+                  tr, fo, cs, keys, vals, w.overflow, w.overflow_n, 0);
+        GD_LAUNCH((k_digit_bucket_sort<V, C, C / 2, kBigBlock>), g, dim3(kBigBlock), 0, s, tr, fo,
+                  cs, keys, vals, w.overflow, w.overflow_n, 1);
     }
     else
         GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
@@ -513,16 +626,21 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
 SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
 {
     SortPlan sp;
-    // digits mode while the densest of 2^14 digits (about 6x the mean) plus a 512-record
-    // target stays within the LDS capacity of a bucket
-    if (val_bytes == 4 && capacity <= ((uint64_t)640 << kDigitBits) && capacity > 0) {
-        int Bd = 4;                          // about 512 records per digit, at most 2^14 digits
+    const uint64_t dcap = val_bytes == 4 ? DCap<uint32_t>::value : DCap<uint64_t>::value;
+    // digits mode while balanced digits (at most 2^15 of them, about 512 records each when
+    // there are fewer) stay within three quarters of the largest bucket capacity
+    if (capacity > 0 && capacity <= ((dcap * 3 / 4) << kDigitBits)) {
+        int Bd = 4;
         while (Bd < kDigitBits && (capacity >> Bd) > 512) Bd++;
         sp.digits = true;
         sp.Bf = Bd;
         sp.nfine = (size_t)1 << Bd;
-        sp.nchunks = (size_t)((capacity + kChunk - 1) / kChunk);
-        sp.target = 512;
+        // chunks of at least 32K records, at most about 1,024 of them
+        uint64_t chunk = 32768;
+        while ((capacity + chunk - 1) / chunk > 1024) chunk *= 2;
+        sp.chunk = (size_t)chunk;
+        sp.nchunks = (size_t)((capacity + chunk - 1) / chunk);
+        sp.target = (capacity >> Bd) > 512 ? 2048 : 512;
         sp.ncoarse = (size_t)(capacity / sp.target) + 2;
         return sp;
     }
@@ -530,12 +648,15 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
     while (Bf < 26 && (expected_records >> Bf) > 2) Bf++;
     sp.digits = false;
     sp.nchunks = 0;
+    sp.chunk = 0;
     sp.Bf = Bf;
     sp.nfine = (size_t)1 << Bf;
     sp.target = val_bytes == 4 ? 2048 : 1024;
     sp.ncoarse = (size_t)(capacity / sp.target) + 2;
     return sp;
 }
+
+size_t sort_top_bins() { return kTop; }
 
 hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void *vals,
                        int val_bytes, const uint64_t *n_ptr, uint64_t capacity, hipStream_t s)

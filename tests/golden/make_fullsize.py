@@ -5,9 +5,9 @@ Every value in it comes from the oracle (oracle/) on inputs from datagen; nothin
 calls the GPU library.  Run from the repository root:
 
     python tests/golden/make_fullsize.py [--out FILE] [illumina] [gapped] [fig4] [uneven]
-        [lookups] [containment]
+        [lookups | lookups10 | lookups11] [containment]
 
-(no argument: all).  It needs about 20 GB of memory and takes tens of minutes on 8 cores.
+(no argument: all; "lookups" records both key arrays).  It needs about 20 GB of memory and takes tens of minutes on 8 cores.
 Seeding and lookups are split over threads by read and query ranges (each read's anchors
 and each query's result are independent of the others); index builds and containment
 counts run as one oracle call each.
@@ -31,6 +31,9 @@ import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "fullsize_oracle.json")
 K, W = 21, 11
+# patterns of the 1 Gbp key arrays queried 500M times: '10' (about 83M keys) and '11'
+# (about 167M keys, the unsparsified array)
+LOOKUP_PATTERNS = ("10", "11")
 
 
 def log(msg, t0=[time.perf_counter()]):
@@ -165,23 +168,28 @@ def main(which):
         del d
     if "fig4" in which:
         table["fig4-100k"] = fig4_entry()
-    if "uneven" in which or "lookups" in which:
+    if "uneven" in which or any(x.startswith("lookups") for x in which):
         d = datagen.workload_uneven()
         log("uneven workload generated")
         for pattern in (["10", "110"] if "uneven" in which else []):
             ent, ik = seed_entry(d, pattern)
             table["uneven-1Gbp/" + pattern] = ent
             del ik
-        if "lookups" in which:
-            ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], "10", K, W)
+        for pattern in LOOKUP_PATTERNS:
+            if "lookups" not in which and "lookups" + pattern not in which:
+                continue
+            # the key array of the 1 Gbp reference under the pattern ('11': no base
+            # dropped), queried with the mixed batch's minimizers under the same pattern
+            ik, iv = oracle.index_build(d["ref"], d["ref_offsets"], pattern, K, W)
             del iv
-            rk, _, _ = oracle.sketch(d["reads"], d["read_offsets"], "10", K, W)
-            log("lookups: %d index keys, %d read minimizers" % (ik.size, rk.size))
+            rk, _, _ = oracle.sketch(d["reads"], d["read_offsets"], pattern, K, W)
+            log("lookups %s: %d index keys, %d read minimizers" % (pattern, ik.size, rk.size))
             q = fullsize.lookup_queries(rk)
             del rk
             lb, occ = parallel_lookup(ik, q)
-            log("lookups: %d queries done" % q.size)
-            table["lookups-1Gbp/10"] = dict(lookups=fullsize.lookup_digest(lb, occ))
+            log("lookups %s: %d queries done" % (pattern, q.size))
+            table["lookups-1Gbp/" + pattern] = dict(index_keys=int(ik.size),
+                                                    lookups=fullsize.lookup_digest(lb, occ))
             del q, lb, occ, ik
         del d
     if "containment" in which:

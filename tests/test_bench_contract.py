@@ -19,9 +19,9 @@ def test_more_than_one_gpu_is_refused():
 def test_stored_traffic_matches_its_profile_summary():
     sys.path.insert(0, ROOT)
     import bench
-    for kernel, m in bench.MEASURED_TRAFFIC.items():
+    for (kernel, workload), m in bench.MEASURED_TRAFFIC.items():
         text = open(os.path.join(ROOT, m["summary"])).read()
-        assert kernel in text
+        assert kernel in text and workload in text
         sha = re.search(r"sha256 ([0-9a-f]{16})", text).group(1)
         assert sha == m["sha256_16"]
         mb = float(re.search(r"Per step \(.*?\): ([0-9.]+) MB measured", text).group(1))

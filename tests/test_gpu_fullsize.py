@@ -12,7 +12,8 @@ part that differs when a check fails.
     '10' and '110': index build, then one HIP-graph-captured seeding pass with launch
     parameters from the autotuner, then location voting (D 100, V 3, 4 winners);
   * 500M lookups (80 % drawn from that batch's read minimizers, 20 % random keys) in the
-    1 Gbp '10' index: learned index (MLP and linear roots, 2^18 leaves) equals binary
+    1 Gbp '10' index (about 83M keys) and the unsparsified '11' index (about 167M keys):
+    learned index (MLP and linear roots, 2^18 leaves; 2^22 leaves on '11') equals binary
     search equals the oracle; every result also satisfies the lower-bound property;
   * 1,000-genome containment database with 10M reads: 64-bit-value index and per-genome
     shared-minimizer counts, with binary search and with the learned index;
@@ -68,13 +69,15 @@ def test_illumina_100mbp_benchmark_step(gpu, golden):
     import bench
     exp = want(golden, "illumina-100Mbp/10")
     d = datagen.workload_illumina()
-    s = bench.Session(gpu, d, "10", K, W)
+    s = bench.Session(gpu, gpu.to_device(d["ref"], d["ref_offsets"]),
+                      gpu.to_device(d["reads"], d["read_offsets"]), d["ref_offsets"],
+                      d["read_offsets"], "10", K, W)
     del d
     # binary search, learned index, and the learned-index step with index construction on
     # a second stream overlapping the read sketches
     for learned, overlap in ((False, False), (True, False), (True, True)):
         s.overlap = overlap
-        s.step(learned)
+        s.step("learned_index" if learned else "binary_search")
         s.check()
         n = s.n_index
         got = fullsize.index_digest(host_u64(s.ikeys[:n]), host_vals(s.ivals[:n]))
@@ -94,7 +97,9 @@ def test_illumina_gapped_100mbp_benchmark_step(gpu, golden):
     import bench
     exp = want(golden, "illumina-gapped-100Mbp/10")
     d = datagen.workload_gapped()
-    s = bench.Session(gpu, d, "10", K, W)
+    s = bench.Session(gpu, gpu.to_device(d["ref"], d["ref_offsets"]),
+                      gpu.to_device(d["reads"], d["read_offsets"]), d["ref_offsets"],
+                      d["read_offsets"], "10", K, W)
     del d
     assert s.ref.nmask is not None and s.reads.nmask is not None
     for mode in ("binary_search", "learned_index"):
@@ -172,18 +177,56 @@ def test_uneven_1gbp_graph_captured_autotuned(gpu, golden, uneven, pattern, tmp_
 
 
 @pytest.mark.timeout(900)
-def test_learned_index_500m_lookups_1gbp(gpu, golden, uneven):
-    exp = want(golden, "lookups-1Gbp/10")["lookups"]
+def test_uneven_1gbp_benchmark_step(gpu, golden, uneven):
+    # the benchmark's headline step on the mixed batch, as it times it: index build, then
+    # learned-index training (or nothing, or the hash table), then seeding with launch
+    # parameters from the autotuner; every mode, and the step replayed as one HIP graph
+    import bench
+    from paper_2211_08157_amd import autotune
+    exp = want(golden, "uneven-1Gbp/10")
+    d = datagen.workload_uneven()
     ix = gpu.index_build(uneven["ref"], "10", K, W)
-    rk, _, _ = gpu.sketch(uneven["reads"], "10", K, W)
+    leaves = bench.leaves_for(ix.n)
+    tuning, _ = autotune.tune(gpu.rmi_train(ix, root="mlp", log2_leaves=leaves), uneven["reads"],
+                              "10", K, W, grid=bench.TUNE_GRID, reps=1, use_cache=False)
+    del ix
+    s = bench.Session(gpu, uneven["ref"], uneven["reads"], d["ref_offsets"], d["read_offsets"],
+                      "10", K, W, log2_leaves=leaves, tuning=tuning)
+    del d
+    for mode in bench.STEP_MODES:
+        s.step(mode)
+        s.check()
+        n = s.n_index
+        got = fullsize.index_digest(host_u64(s.ikeys[:n]), host_vals(s.ivals[:n]))
+        assert_digest(got, exp["index"], "index")
+        a = s.anchors[:4 * s.n_anchors].cpu().numpy().view(np.uint32)
+        got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
+        assert_digest(got, exp["anchors"], "anchors (%s)" % mode)
+    bench.graph_step(torch, s, "learned_index", 2)
+    a = s.anchors[:4 * s.n_anchors].cpu().numpy().view(np.uint32)
+    got = fullsize.anchors_digest(a, host_u64(s.roff), s.shift.cpu().numpy())
+    assert_digest(got, exp["anchors"], "anchors (graph-replayed step)")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("pattern", ["10", "11"])
+def test_learned_index_500m_lookups_1gbp(gpu, golden, uneven, pattern):
+    ent = want(golden, "lookups-1Gbp/" + pattern)
+    exp = ent["lookups"]
+    ix = gpu.index_build(uneven["ref"], pattern, K, W)
+    if "index_keys" in ent:
+        assert ix.n == ent["index_keys"]
+    rk, _, _ = gpu.sketch(uneven["reads"], pattern, K, W)
     q = fullsize.lookup_queries(host_u64(rk))
     del rk
     qd = torch.from_numpy(q.view(np.int64)).cuda()
     del q
     lb0, occ0 = gpu.lookup(ix, qd)
-    for root in ("mlp", "linear"):
-        lb1, occ1 = gpu.lookup(gpu.rmi_train(ix, root=root, log2_leaves=18), qd)
-        assert torch.equal(lb0, lb1) and torch.equal(occ0, occ1), root
+    # both roots at 2^18 leaves; the unsparsified array also at about 40 keys per leaf
+    models = [("mlp", 18), ("linear", 18)] + ([("mlp", 22)] if pattern == "11" else [])
+    for root, leaves in models:
+        lb1, occ1 = gpu.lookup(gpu.rmi_train(ix, root=root, log2_leaves=leaves), qd)
+        assert torch.equal(lb0, lb1) and torch.equal(occ0, occ1), (root, leaves)
         del lb1, occ1
     # lower-bound property of every result: keys[lb-1] < q <= keys[lb], and the run
     # [lb, lb+occ) holds exactly the keys equal to q (keys compared as unsigned)

@@ -257,6 +257,22 @@ def test_index_is_sorted_sketch(val_bits):
     assert len(np.unique(ik)) < len(ik)
 
 
+@pytest.mark.parametrize("pattern,k,w", [("10", 15, 10), ("110", 21, 11), ("1", 9, 5),
+                                           ("1001010011", 11, 7)])
+def test_chunked_index_equals_whole(pattern, k, w):
+    # the CPU baseline's many-thread index: chunks with a margin of context, merged by
+    # key ranges, equal the index of the whole sequence (chunk edges land everywhere:
+    # 37 chunks, a repeat copied across a chunk edge, low-complexity runs)
+    rng = np.random.default_rng(16)
+    s = rng.integers(0, 4, 60_000, dtype=np.uint8)
+    s[10_000:12_000] = s[30_000:32_000]
+    s[40_000:40_300] = 0
+    ik, iv = oracle.index_build(s, np.array([0, s.size], np.int64), pattern, k, w)
+    for threads, chunks in ((3, 37), (4, None), (1, 1)):
+        ck, cv = oracle.index_build_chunked(s, pattern, k, w, threads, chunks)
+        assert np.array_equal(ck, ik) and np.array_equal(cv, iv), (threads, chunks)
+
+
 def test_lookup_matches_searchsorted():
     rng = np.random.default_rng(15)
     keys = np.sort(rng.integers(0, 1000, 5000).astype(np.uint64))
