@@ -234,6 +234,24 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
                             uint64_t *mz_offsets, uint64_t capacity,
                             void *ws, size_t ws_bytes, uint32_t *status, hipStream_t stream);
 
+/* [host] Scratch bytes godiet_sketch_static can use (64 MiB): the largest
+ * godiet_workspace_size(GODIET_OP_SKETCH, ...) it accepts. */
+size_t godiet_sketch_static_max_bytes(void);
+
+/* godiet_sketch without a workspace, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments and results as godiet_sketch minus ws / ws_bytes.  Its scratch is a
+ * library-owned device array of godiet_sketch_static_max_bytes() bytes, one per GPU,
+ * located on the first call on each device and kept until the process ends; the call
+ * allocates and frees nothing.  A batch whose sketch workspace would exceed that size
+ * returns GODIET_E_WORKSPACE before anything is enqueued (use godiet_sketch then).  Every
+ * call on one GPU shares that GPU's array, so calls that overlap on one GPU (concurrent
+ * streams, or host threads) race and give undefined results; serialise them. */
+godiet_status godiet_sketch_static(const godiet_seqs *in, const godiet_sketch_params *prm,
+                                   const uint32_t *shift, uint64_t *keys, uint32_t *vals,
+                                   uint64_t *mz_offsets, uint64_t capacity, uint32_t *status,
+                                   hipStream_t stream);
+
 /* Compressed indexing (Section 3.1): minimizers of the sparsified reference (shift 0),
  * appended and sorted ascending by (hash, val) into keys[] / vals[].  val_bits 32: vals is
  * uint32 (global position in the batch) << 1 | strand, needs n_bases < 2^31; val_bits

@@ -95,6 +95,10 @@ def lib():
         L.godiet_pack_ascii.restype = i32
         L.godiet_sketch.argtypes = [S(Seqs), S(Params), P, P, P, P, u64, P, sz, P, P]
         L.godiet_sketch.restype = i32
+        L.godiet_sketch_static_max_bytes.argtypes = []
+        L.godiet_sketch_static_max_bytes.restype = sz
+        L.godiet_sketch_static.argtypes = [S(Seqs), S(Params), P, P, P, P, u64, P, P]
+        L.godiet_sketch_static.restype = i32
         L.godiet_index_build.argtypes = [S(Seqs), S(Params), P, P, i32, u64, P, P, sz, P, P]
         L.godiet_index_build.restype = i32
         L.godiet_seed.argtypes = [S(Index), S(Seqs), S(Params), S(SeedOpts), P, u64, P, P, P, sz,

@@ -1,6 +1,9 @@
 // C ABI entry points: host-side validation, workspace layout and kernel sequencing.
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "../../include/godiet.h"
 #include "gd_internal.h"
 
@@ -435,6 +438,70 @@ godiet_status godiet_sketch(const godiet_seqs *in, const godiet_sketch_params *p
     SketchWs W;
     plan_sketch_ws(b, in, npb, prm->w, &W);
     if (!ws || ws_bytes < b.off) return GODIET_E_WORKSPACE;
+    GD_TRY(fill_u32(status, 0, 1, stream));
+    GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, prm->w, status, stream));
+    SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
+    GD_TRY(launch_sketch(batch_of(in), P, shift, 0, W.pofs, W.psw, W.pnw, npb, prm->k, prm->w,
+                         prm->hash, o, W.tiles, W.lohi_sk, in->n_seq > 0, status, stream));
+    return GODIET_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of godiet_sketch_static: one copy per GPU, held until the process ends.  Host
+// code never uses the array's name as an address: each device's copy is found once with
+// hipGetSymbolAddress (with that device current) and that pointer is passed on.
+constexpr size_t kStaticScratch = (size_t)64 << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratch];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// This device's copy of `scratch` (null if the runtime cannot provide it).
+void *device_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    void *p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return nullptr;
+        g_scratch[dev].store(q, std::memory_order_release);
+        p = q;
+    }
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t godiet_sketch_static_max_bytes(void) { return kStaticScratch; }
+
+godiet_status godiet_sketch_static(const godiet_seqs *in, const godiet_sketch_params *prm,
+                                   const uint32_t *shift, uint64_t *keys, uint32_t *vals,
+                                   uint64_t *mz_offsets, uint64_t capacity, uint32_t *status,
+                                   hipStream_t stream)
+{
+    Pattern P;
+    if (!valid_seqs(in) || !valid_params(prm, &P) || !mz_offsets || !status) return GODIET_E_INVAL;
+    if (capacity > 0 && (!keys || !vals)) return GODIET_E_INVAL;
+    // the same workspace plan as godiet_sketch, measured before any HIP call
+    const uint64_t npb = kept_bound(in, P);
+    Bump m(nullptr);
+    SketchWs W;
+    plan_sketch_ws(m, in, npb, prm->w, &W);
+    if (m.off > kStaticScratch) return GODIET_E_WORKSPACE;
+    void *ws = device_scratch();
+    if (!ws) return GODIET_E_HIP;
+    Bump b(ws);
+    plan_sketch_ws(b, in, npb, prm->w, &W);
     GD_TRY(fill_u32(status, 0, 1, stream));
     GD_TRY(sparsify_to_stream(in, P, shift, 0, W, npb, prm->w, status, stream));
     SketchOut o{keys, vals, VAL_LOCAL32, mz_offsets, capacity, nullptr};
