@@ -731,7 +731,9 @@ def lookups_1gbp(gd, torch, ref, reads, reps):
     drawn from the mixed batch's read minimizers under the same pattern and 20 % random
     64-bit keys (seeded device generator), two-stage FP32 models with an MLP root at 2^18
     and at about 32 keys per leaf.  Every model must return the binary-search (lower
-    bound, run length) of every query."""
+    bound, run length) of every query; each model's fallback fraction (queries its window
+    does not bracket) and histogram of window widths (keys read, powers of two) are
+    reported."""
     out = {}
     for pat in ("10", "11"):
         ix = gd.index_build(ref, pat, 21, 11)
@@ -769,7 +771,9 @@ def lookups_1gbp(gd, torch, ref, reads, reps):
                 raise RuntimeError("learned-index lookups differ from binary search")
             res[name] = dict(ms=ms, lookups_per_s=n_total / (ms * 1e-3))
             if lv is not None:
-                res[name]["log2_leaves"] = lv
+                st = gd.rmi_stats(index, q)
+                res[name].update(log2_leaves=lv, fallback_fraction=st["fallbacks"] / n_total,
+                                 window_keys_hist=st["window_keys"])
             del lb, occ
         res["found"] = int((ref_occ != 0).sum().item())
         res["random_keys_found"] = int((ref_occ[n_pres:] != 0).sum().item())

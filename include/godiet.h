@@ -108,8 +108,12 @@ typedef struct {
 /* A sorted seed index as produced by godiet_index_build.  val_bits 32: vals is uint32
  * global position << 1 | strand; val_bits 64: vals is uint64 sequence id << 32 |
  * position << 1 | strand.  rmi: NULL for binary-search lookups, else a learned index
- * trained on exactly these keys by godiet_rmi_train (rmi_bytes its size); a model trained
- * on other keys is detected by its key count and ignored (binary search is used). */
+ * trained on exactly these keys by godiet_rmi_train (rmi_bytes its size, at least
+ * godiet_rmi_size(1), else calls return GODIET_E_INVAL).  The lookup kernels read the
+ * model only after checking that its header names this key count and that its leaves lie
+ * inside rmi_bytes; any other model is ignored (binary search), and a model's content
+ * never changes a result (every window is checked against the keys).  table/table_bytes:
+ * see godiet_table_build. */
 typedef struct {
     const uint64_t *keys;
     const void *vals;
@@ -329,8 +333,11 @@ godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64
  * whole buffer (16-byte aligned, table_bytes >= that size) from index->keys.  godiet_seed
  * and godiet_contain then look read minimizers up in it when index->table is set, with
  * results identical to binary search; godiet_lookup ignores it (a table has no lower
- * bound for an absent key).  A table built for other keys is detected by its key count
- * and ignored. */
+ * bound for an absent key).  table_bytes below godiet_table_size(index->n) returns
+ * GODIET_E_INVAL.  The header records the key count and a fingerprint of the keys (their
+ * count and eight keys spread over them); the lookup kernels use the table only when
+ * both match index->keys and its slots lie inside table_bytes, and take a slot's run only
+ * when it lies inside the keys; otherwise they search the sorted keys. */
 size_t godiet_table_size(uint64_t n_index);
 godiet_status godiet_table_build(const godiet_index *index, void *table, size_t table_bytes,
                                  hipStream_t stream);
@@ -347,6 +354,17 @@ godiet_status godiet_table_build(const godiet_index *index, void *table, size_t 
 size_t godiet_rmi_size(uint32_t log2_leaves);
 godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uint32_t log2_leaves,
                                void *rmi, size_t rmi_bytes, hipStream_t stream);
+
+/* Learned-index diagnostics (a measurement aid; lookups never need it): for each of the
+ * n_q queries q (device uint64), whether the model's key window brackets it or the lookup
+ * falls back to binary search, and how many keys the window spans with its two brackets.
+ * stats (device, GODIET_RMI_STAT_WORDS uint64 words, overwritten): [0] queries, [1]
+ * fallbacks (the model unusable for this index, or a window that does not bracket the
+ * query), [2 + b] windows of w keys with 2^(b-1) < w <= 2^b for b = 0..16, and [19]
+ * windows of more than 2^16 keys.  index->rmi must be set. */
+#define GODIET_RMI_STAT_WORDS 20
+godiet_status godiet_rmi_stats(const godiet_index *index, const uint64_t *q, uint64_t n_q,
+                               uint64_t *stats, hipStream_t stream);
 
 /* Kernel tracing, a profiling aid outside the method.  While enabled, every kernel launch
  * of the library is bracketed by HIP events recorded on the launch's stream.  After the

@@ -113,6 +113,8 @@ def lib():
         L.godiet_table_size.restype = sz
         L.godiet_table_build.argtypes = [S(Index), P, sz, P]
         L.godiet_table_build.restype = i32
+        L.godiet_rmi_stats.argtypes = [S(Index), P, u64, P, P]
+        L.godiet_rmi_stats.restype = i32
         L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
         L.godiet_lookup.restype = i32
         L.godiet_rmi_size.argtypes = [u32]
@@ -400,6 +402,21 @@ def lookup(index, queries):
     _check(lib().godiet_lookup(ctypes.byref(ix), _ptr(queries), n, _ptr(lb), _ptr(occ),
                                _stream()), "godiet_lookup")
     return lb[:n], occ[:n]
+
+
+RMI_STAT_WORDS = 20
+
+
+def rmi_stats(index, queries):
+    """Learned-index diagnostics over an int64 query tensor: dict(queries, fallbacks,
+    window_keys) with window_keys[b] = windows of w keys, 2^(b-1) < w <= 2^b (the last
+    entry open-ended)."""
+    torch = _torch()
+    st = _empty(RMI_STAT_WORDS, torch.int64)
+    _check(lib().godiet_rmi_stats(ctypes.byref(index.c()), _ptr(queries), queries.numel(),
+                                  _ptr(st), _stream()), "godiet_rmi_stats")
+    v = st.cpu().numpy().view(np.uint64)
+    return dict(queries=int(v[0]), fallbacks=int(v[1]), window_keys=[int(x) for x in v[2:]])
 
 
 def index_build(ref, pattern, k, w, val_bits=32, capacity=None, hash="splitmix64"):

@@ -50,6 +50,15 @@ uint64_t kept_bound(const godiet_seqs *q, const Pattern &P)
     return b < q->n_bases ? b : q->n_bases;
 }
 
+// An index's learned-index model must hold at least its header and smallest leaf table,
+// its hash table the size built for its key count (the kernels check the rest).
+bool models_fit(const godiet_index *ix)
+{
+    if (ix->rmi && ix->rmi_bytes < rmi_bytes(1)) return false;
+    if (ix->table && ix->table_bytes < table_bytes(ix->n)) return false;
+    return true;
+}
+
 Batch batch_of(const godiet_seqs *q)
 {
     return Batch{q->bases, q->offsets, q->n_seq, q->n_bases, q->nmask};
@@ -200,6 +209,7 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
 {
     if (index->n > 0 && (!index->keys || !index->vals)) return GODIET_E_INVAL;
     if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (!models_fit(index)) return GODIET_E_INVAL;
     if (opts->shift_mode < -1 || opts->shift_mode >= (int32_t)P.p) return GODIET_E_INVAL;
     const uint64_t npb = kept_bound(reads, P);
     const uint32_t n_shift = opts->shift_mode >= 0 ? 1u : P.p;
@@ -228,7 +238,8 @@ godiet_status seed_front(const godiet_index *index, const godiet_seqs *reads, co
         const uint64_t *mz = W.mzofs + si * (nr + 1);
         GD_TRY(launch_lookup(index->keys, index->n, W.qkeys + si * W.stride, mz + nr, W.stride,
                              W.lb + si * W.stride, W.occ + si * W.stride, index->rmi,
-                             index->table, opts->lookup_blocks, stream));
+                             index->rmi_bytes, index->table, index->table_bytes,
+                             opts->lookup_blocks, stream));
     }
     AlignArgs &A = *Ap;
     A.mzofs = W.mzofs;
@@ -648,14 +659,28 @@ godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uin
     return GODIET_OK;
 }
 
+godiet_status godiet_rmi_stats(const godiet_index *index, const uint64_t *q, uint64_t n_q,
+                               uint64_t *stats, hipStream_t stream)
+{
+    if (!index || !index->rmi || !stats || (n_q > 0 && !q)) return GODIET_E_INVAL;
+    if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
+    if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (!models_fit(index)) return GODIET_E_INVAL;
+    GD_TRY(launch_rmi_stats(index->keys, index->n, index->rmi, index->rmi_bytes, q, n_q, stats,
+                            stream));
+    return GODIET_OK;
+}
+
 godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64_t n_q,
                             uint32_t *lb, uint32_t *occ, hipStream_t stream)
 {
     if (!index || (n_q > 0 && (!q || !lb || !occ))) return GODIET_E_INVAL;
     if (index->n > 0 && !index->keys) return GODIET_E_INVAL;
     if (index->n >= (1ull << 32)) return GODIET_E_RANGE;
+    if (!models_fit(index)) return GODIET_E_INVAL;
     if (n_q == 0) return GODIET_OK;
-    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi, nullptr, 0,
+    GD_TRY(launch_lookup(index->keys, index->n, q, nullptr, n_q, lb, occ, index->rmi,
+                         index->rmi_bytes, nullptr, 0, 0,
                          stream));
     return GODIET_OK;
 }

@@ -168,7 +168,8 @@ hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *
 // table (nullable, seeding only): hash-table lookups, whose lb is 0 for absent keys
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, const void *table, uint32_t blocks, hipStream_t s);
+                         const void *rmi, size_t rmi_bytes, const void *table,
+                         size_t table_bytes, uint32_t max_blocks, hipStream_t s);
 
 // ---- hash-table index form (gd_table.hip) ----
 uint32_t table_log2_slots(uint64_t n);
@@ -177,6 +178,9 @@ hipError_t launch_table_build(const uint64_t *keys, uint64_t n, void *table, hip
 
 // ---- learned index (gd_rmi.hip)
 size_t rmi_bytes(uint32_t log2_leaves);
+int rmi_stat_words();
+hipError_t launch_rmi_stats(const uint64_t *keys, uint64_t n, const void *rmi, size_t rmi_bytes,
+                            const uint64_t *q, uint64_t n_q, uint64_t *stats, hipStream_t s);
 hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t log2_leaves,
                             void *rmi, hipStream_t s);
 

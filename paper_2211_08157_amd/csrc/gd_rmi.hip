@@ -7,11 +7,12 @@
 //                                  hidden unit i = relu(x - t_i), out = c0 + sum c_i h_i,
 //                                  x = key * 2^-64 (FP32), out = predicted rank / n
 //   RmiLeaf[L]                     16 bytes: high half of the first key, base
-//                                  position, slope, FP16 intercept, 8-bit errors
+//                                  position (intercept folded in), FP32 slope, 16-bit
+//                                  error bounds
 //
 // Routing is monotone in the key (FP32 conversion, non-negative slopes, floor), so each
 // leaf owns a contiguous run of the sorted keys.  A leaf predicts
-//     p = base + floor(icpt + slope * float((q >> 32) - khi))
+//     p = base + floor(slope * float((q >> 32) - khi))
 // and the answer is searched in [p - err_lo, p + err_hi + 1].  The window is accepted
 // only if keys[lo-1] < q <= keys[hi] (with the array ends as sentinels); otherwise the
 // lookup falls back to a full binary search, so results never depend on the model or on
@@ -60,18 +61,27 @@ __global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint6
             h.c[i + 1] = (float)(s - prev);
             prev = s;
         }
+        // the network per segment (FP32 prefix sums of the output weights)
+        h.sa[0] = h.c[0];
+        h.sb[0] = 0.f;
+        for (int j = 1; j <= kKnots; j++) {
+            h.sb[j] = __fadd_rn(h.sb[j - 1], h.c[j]);
+            h.sa[j] = __fsub_rn(h.sa[j - 1], __fmul_rn(h.c[j], h.t[j - 1]));
+        }
     }
     *H = h;
 }
 
-// Leaf boundaries: leaf l starts at the first key routed to a leaf >= l.  Stored in the
-// leaves' base field for the fitting pass.  The FP32 root can step back by one leaf
-// between neighbouring keys, so a leaf may be claimed by several keys: the smallest index
-// wins (the bases start at all ones), which keeps the model independent of store order.
+// Leaf boundaries: leaf l starts at the first key routed to a leaf >= l (index n routes
+// past the last leaf), stored in its base field.  The FP32 root can step back by one leaf
+// between neighbouring keys, so a boundary may be claimed by several keys: the smallest
+// index wins (the fields start at all ones), which keeps the model independent of store
+// order.  k_rmi_ends then copies each leaf's end (the next leaf's start) into its own slope
+// field, so the fitting pass reads and rewrites only its own leaf.
 __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
                                                        const RmiHeader *Hp, RmiLeaf *leaves)
 {
-    const RmiHeader H = *Hp;
+    const RmiHeader &H = *Hp;      // read in place: per-lane segment indices would force a copy to scratch
     const uint32_t L = 1u << H.log2_leaves;
     // A wave takes 63 new indices per step: lane t routes index s - 1 + t, so every lane
     // but the first finds its predecessor's leaf in the lane below (each key is routed
@@ -82,10 +92,26 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
     const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
     for (uint64_t s = wave * (kWave - 1); s <= n; s += waves * (kWave - 1)) {   // wave-uniform
         const uint64_t i = s + lane - 1;                 // s - 1 for lane 0 (wraps at s = 0)
+        const bool key = !(lane == 0 && s == 0) && i < n;
         uint32_t cur = 0;
-        if (lane == 0 && s == 0) cur = 0;                // no predecessor of index 0
-        else if (i < n) cur = route(H, keys[i]);
-        else cur = L;                                    // index n (and past it)
+        if (key) {
+            const float x = key_x(keys[i]);
+            if (H.kind == 0) {
+                cur = route(H, keys[i]);
+            } else {
+                // the keys are sorted, so a wave's keys usually share the root's segment:
+                // then it is counted once for the wave (route() gives the same leaves)
+                const uint64_t m = __ballot(key);
+                const int first = __ffsll((unsigned long long)m) - 1;
+                const int last = 63 - __clzll((long long)m);
+                const float x0 = __shfl(x, first), x1 = __shfl(x, last);
+                uint32_t j = root_segment(H, x0);
+                if (j != root_segment(H, x1)) j = root_segment(H, x);   // wave-uniform test
+                cur = leaf_of(root_on_segment(H, j, x), L);
+            }
+        } else if (!(lane == 0 && s == 0)) {
+            cur = L;                                     // index n (and past it)
+        }
         const uint32_t prv = __shfl_up(cur, 1);
         if (lane == 0 || i > n) continue;
         const uint32_t from = i > 0 ? prv + 1 : 0;
@@ -93,12 +119,20 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
     }
 }
 
+// One thread per leaf: its end is the next leaf's start (n for the last leaf).
+__global__ __launch_bounds__(kBlock) void k_rmi_ends(uint64_t n, uint32_t L, RmiLeaf *leaves)
+{
+    const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < L) leaves[l].end = l + 1 < L ? leaves[l + 1].base : (uint32_t)n;
+}
+
 // Eight lanes per leaf (a group never straddles a wave): least-squares line through
 // ((key >> 32) - khi, position) in FP64, the lanes taking every eighth key so that a
-// group reads consecutive keys, then the largest under- and over-prediction over the
-// leaf's keys with the lookup's own prediction function (saturated at 255: a larger miss
-// only sends those lookups to the binary-search fallback).  The butterfly sums add the
-// same pairs in every lane, so all eight lanes hold identical totals.
+// group reads consecutive keys; the intercept's integer part moves into the leaf's base
+// position; then the largest under- and over-prediction over the leaf's keys with the
+// lookup's own prediction function (saturated at 65535: a larger miss only sends those
+// lookups to the binary-search fallback).  The butterfly sums add the same pairs in every
+// lane, so all eight lanes hold identical totals.
 constexpr int kFitLanes = 8;
 
 __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64_t n,
@@ -110,21 +144,36 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     const int j = (int)(g % kFitLanes);
     if (l >= L) return;                       // whole groups only
     const uint64_t lo = leaves[l].base;
-    const uint64_t hi = l + 1 < L ? leaves[l + 1].base : n;
+    const uint64_t hi = leaves[l].end;
     RmiLeaf lf;
     lf.base = (uint32_t)lo;
     lf.khi = lo < n ? (uint32_t)(keys[lo] >> 32) : 0xffffffffu;
     lf.slope = 0.f;
-    lf.icpt = (_Float16)0.f;
     lf.err_lo = 0;
     lf.err_hi = 0;
     const uint64_t m = hi > lo ? hi - lo : 0;
+    // the group's first kHold * 8 keys stay in registers for the error pass; longer leaves
+    // read the rest twice
+    constexpr int kHold = 8;
+    unsigned long long held[kHold];
+#pragma unroll
+    for (int c = 0; c < kHold; c++) {
+        const uint64_t i = lo + j + (uint64_t)c * kFitLanes;
+        held[c] = i < hi ? keys[i] : 0;
+    }
+    const uint64_t rest = lo + (uint64_t)kHold * kFitLanes;      // first key not held
     if (m >= 2) {
         double sx = 0, sy = 0, sxx = 0, sxy = 0;
-        for (uint64_t i = lo + j; i < hi; i += kFitLanes) {
-            const double x = (double)((uint32_t)(keys[i] >> 32) - lf.khi), y = (double)(i - lo);
+        auto add = [&](uint64_t i, unsigned long long k) {
+            const double x = (double)((uint32_t)(k >> 32) - lf.khi), y = (double)(i - lo);
             sx += x; sy += y; sxx += x * x; sxy += x * y;
+        };
+#pragma unroll
+        for (int c = 0; c < kHold; c++) {
+            const uint64_t i = lo + j + (uint64_t)c * kFitLanes;
+            if (i < hi) add(i, held[c]);
         }
+        for (uint64_t i = rest + j; i < hi; i += kFitLanes) add(i, keys[i]);
 #pragma unroll
         for (int o = 1; o < kFitLanes; o <<= 1) {
             sx += __shfl_xor(sx, o, kFitLanes);
@@ -134,18 +183,17 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
         }
         const double var = sxx - sx * sx / (double)m;
         const double sl = var > 0 ? (sxy - sx * sy / (double)m) / var : 0.0;
-        double ic = (sy - sl * sx) / (double)m;
-        ic = ic > 60000.0 ? 60000.0 : (ic < -60000.0 ? -60000.0 : ic);
+        const double ic = (sy - sl * sx) / (double)m;
         lf.slope = (float)(sl > 0 ? sl : 0.0);
-        lf.icpt = (_Float16)(float)ic;
+        // base = lo + floor(intercept), kept inside [0, n]
+        const double b = (double)lo + floor(ic);
+        lf.base = b <= 0.0 ? 0u : (b >= (double)n ? (uint32_t)n : (uint32_t)b);
     }
     // errors: keep every key's first occurrence inside [p - err_lo, p + err_hi]; a lane's
     // previous key is the lane below's (lane 0: the last key of the group's previous step)
     long long elo = 0, ehi = 0;
     unsigned long long carry = 0;
-    for (uint64_t i0 = lo; i0 < hi; i0 += kFitLanes) {           // uniform in the group
-        const uint64_t i = i0 + j;
-        const unsigned long long k = i < hi ? keys[i] : 0;
+    auto step = [&](uint64_t i, unsigned long long k) {
         unsigned long long prev = __shfl_up(k, 1, kFitLanes);
         if (j == 0) prev = carry;
         if (i < hi && (i == lo || k != prev)) {
@@ -154,6 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
             if (-d > elo) elo = -d;
         }
         carry = __shfl(k, kFitLanes - 1, kFitLanes);
+    };
+#pragma unroll
+    for (int c = 0; c < kHold; c++)
+        if (lo + (uint64_t)c * kFitLanes < hi) step(lo + j + (uint64_t)c * kFitLanes, held[c]);
+    for (uint64_t i0 = rest; i0 < hi; i0 += kFitLanes) {         // uniform in the group
+        const uint64_t i = i0 + j;
+        step(i, i < hi ? keys[i] : 0);
     }
 #pragma unroll
     for (int o = 1; o < kFitLanes; o <<= 1) {
@@ -161,12 +216,62 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
         elo = a > elo ? a : elo;
         ehi = b > ehi ? b : ehi;
     }
-    lf.err_lo = (uint8_t)(elo < 255 ? elo : 255);
-    lf.err_hi = (uint8_t)(ehi < 255 ? ehi : 255);
+    lf.err_lo = (uint16_t)(elo < 65535 ? elo : 65535);
+    lf.err_hi = (uint16_t)(ehi < 65535 ? ehi : 65535);
     if (j == 0) leaves[l] = lf;
 }
 
+// Diagnostics: per query, whether the model's window brackets it (else the lookups fall
+// back to binary search) and how many keys the window spans with its brackets, counted in
+// LDS per workgroup.  stats: [0] queries, [1] fallbacks, [2 + b] windows of w keys with
+// 2^(b-1) < w <= 2^b (b = 0..kRmiStatBins - 1, the last bin open-ended).
+constexpr int kRmiStatBins = 18;
+
+__global__ __launch_bounds__(kBlock) void k_rmi_stats(const uint64_t *keys, uint64_t n,
+                                                      const void *rmi, size_t rmi_bytes_,
+                                                      const uint64_t *q, uint64_t n_q,
+                                                      unsigned long long *stats)
+{
+    __shared__ unsigned long long h[2 + kRmiStatBins];
+    __shared__ int sh_valid;
+    for (int i = threadIdx.x; i < 2 + kRmiStatBins; i += kBlock) h[i] = 0;
+    if (threadIdx.x == 0) sh_valid = rmi_valid(rmi, rmi_bytes_, n);
+    __syncthreads();
+    const bool valid = sh_valid != 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n_q;
+         i += (uint64_t)gridDim.x * kBlock) {
+        int64_t lo = 0, hi = 0;
+        if (!valid || !rmi_window(rmi, keys, n, q[i], lo, hi)) {
+            atomicAdd(&h[1], 1ull);
+            continue;
+        }
+        const uint64_t w = (uint64_t)(hi - lo) + 2;
+        int b = 0;
+        while (b < kRmiStatBins - 1 && (1ull << b) < w) b++;
+        atomicAdd(&h[2 + b], 1ull);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 + kRmiStatBins; i += kBlock)
+        if (h[i]) atomicAdd(&stats[i], h[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[0], (unsigned long long)n_q);
+}
+
 }  // namespace
+
+int rmi_stat_words() { return 2 + kRmiStatBins; }
+
+hipError_t launch_rmi_stats(const uint64_t *keys, uint64_t n, const void *rmi, size_t rmi_bytes_,
+                            const uint64_t *q, uint64_t n_q, uint64_t *stats, hipStream_t s)
+{
+    hipError_t e = fill_u64(stats, 0, (size_t)rmi_stat_words(), s);
+    if (e != hipSuccess) return e;
+    uint64_t blocks = (n_q + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    GD_LAUNCH(k_rmi_stats, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n, rmi, rmi_bytes_, q,
+              n_q, (unsigned long long *)stats);
+    return hipGetLastError();
+}
 
 size_t rmi_bytes(uint32_t log2_leaves)
 {
@@ -186,6 +291,7 @@ hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t
     if (blocks > 8192) blocks = 8192;
     GD_LAUNCH(k_rmi_bounds, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n,
               (const RmiHeader *)H, leaves);
+    GD_LAUNCH(k_rmi_ends, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, L, leaves);
     GD_LAUNCH(k_rmi_fit, dim3((unsigned)(((uint64_t)L * kFitLanes + kBlock - 1) / kBlock)),
               dim3(kBlock), 0, s, keys, n,
               (const RmiHeader *)H, leaves);

@@ -50,12 +50,12 @@ __device__ __forceinline__ uint64_t run_end(const uint64_t *keys, uint64_t n, ui
 // bisection after the same check, and a failed check takes the plain searches.
 constexpr int kPairs = 8;
 
-__device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, uint64_t n,
-                                         uint64_t q, uint64_t &l, uint64_t &u)
+__device__ __forceinline__ void rmi_find(const void *rmi, bool valid, const uint64_t *keys,
+                                         uint64_t n, uint64_t q, uint64_t &l, uint64_t &u)
 {
     const RmiHeader &H = *(const RmiHeader *)rmi;
     const RmiLeaf *leaves = (const RmiLeaf *)((const char *)rmi + sizeof(RmiHeader));
-    if (H.magic == kRmiMagic && H.n_keys == n && n > 0) {
+    if (valid) {
         const RmiLeaf lf = leaves[route(H, q)];
         const int64_t p = predict(lf, q);
         int64_t lo = p - lf.err_lo, hi = p + lf.err_hi + 1;
@@ -119,12 +119,23 @@ __device__ __forceinline__ void rmi_find(const void *rmi, const uint64_t *keys, 
 
 // One lane per query.  kMode: 0 binary search, 1 learned index (scalar loads), 2 learned
 // index (keys 16-byte aligned, windowed loads), 3 hash table (lb 0 for absent keys).
+// The model (model_bytes bytes) is checked once per workgroup: a learned index whose
+// leaves would lie outside its buffer, or a hash table that does not fit its buffer or
+// was built over other keys, is not used (binary search instead).
 template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64_t in,
                                                    const uint64_t *q, const uint64_t *n_q,
                                                    uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                                                   const void *model)
+                                                   const void *model, size_t model_bytes)
 {
+    __shared__ int sh_valid;
+    if (kMode != 0) {
+        if (threadIdx.x == 0)
+            sh_valid = kMode == 3 ? table_valid(model, model_bytes, in, table_keys_fp(ikeys, in))
+                                  : rmi_valid(model, model_bytes, in);
+        __syncthreads();
+    }
+    const bool valid = kMode != 0 && sh_valid != 0;
     uint64_t n = n_q ? *n_q : q_cap;
     if (n > q_cap) n = q_cap;
     for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
@@ -133,16 +144,17 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
         uint64_t l, u;
         if (kMode == 3) {
             uint64_t c;
-            if (table_find(model, in, x, l, c)) {
+            if (valid && table_find(model, in, x, l, c)) {
                 u = l + c;
             } else {
                 l = lower_bound_u64(ikeys, in, x);
                 u = run_end(ikeys, in, l, x);
             }
         } else if (kMode == 2) {
-            rmi_find(model, ikeys, in, x, l, u);
+            rmi_find(model, valid, ikeys, in, x, l, u);
         } else {
-            l = kMode == 1 ? rmi_lower_bound(model, ikeys, in, x) : lower_bound_u64(ikeys, in, x);
+            l = kMode == 1 ? rmi_lower_bound(model, valid, ikeys, in, x)
+                           : lower_bound_u64(ikeys, in, x);
             u = run_end(ikeys, in, l, x);
         }
         lb[i] = (uint32_t)l;
@@ -519,7 +531,8 @@ __global__ __launch_bounds__(kHugeBlock) void k_expand_huge(AlignArgs A, const u
 
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
-                         const void *rmi, const void *table, uint32_t max_blocks, hipStream_t s)
+                         const void *rmi, size_t rmi_bytes, const void *table,
+                         size_t table_bytes, uint32_t max_blocks, hipStream_t s)
 {
     uint64_t blocks = (q_cap + kBlock - 1) / kBlock;
     const uint64_t cap = max_blocks ? max_blocks : 8192;
@@ -527,16 +540,16 @@ hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
     if (blocks == 0) blocks = 1;
     if (table)
         GD_LAUNCH(k_lookup<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, table);
+                  q_cap, lb, occ, table, table_bytes);
     else if (rmi && ((uintptr_t)ikeys & 15) == 0)
         GD_LAUNCH(k_lookup<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, rmi);
+                  q_cap, lb, occ, rmi, rmi_bytes);
     else if (rmi)
         GD_LAUNCH(k_lookup<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, rmi);
+                  q_cap, lb, occ, rmi, rmi_bytes);
     else
         GD_LAUNCH(k_lookup<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ikeys, in, q, n_q,
-                  q_cap, lb, occ, rmi);
+                  q_cap, lb, occ, rmi, (size_t)0);
     return hipGetLastError();
 }
 

@@ -24,17 +24,17 @@
 //
 // Indexes of up to ~190M records with 32-bit values (~48M with 64-bit values) take a
 // cheaper partition ("digits" mode) whose digits are balanced by the data: a histogram of
-// the keys' top 12 bits, scanned, maps a key to its approximate rank (the cumulative count
-// of its 12-bit slice plus its share of the slice, by the next 32 key bits, which is
-// monotone in the key), and the digit is that rank scaled to D <= 2^15 digits, so every
-// digit holds about N / D records whatever the skew of the hashes.  Digits are counted per
-// chunk of records in LDS, turned into per-chunk digit offsets by one thread per digit,
-// and scattered with LDS atomics, so no record touches a global atomic or a random global
-// read.  Coarse buckets of whole digits (about 2,048 records, at most that plus one
-// digit) are sorted in LDS: binned by their key's offset from the bucket's smallest key,
-// scaled to about two bins per record, and placed by rank inside their bin
-// (k_digit_bucket_sort, in two launches: half-capacity workgroups for the common buckets,
-// full-capacity ones of up to 160 KB of LDS for the largest).
+// the top 12 bits of a sample of the keys, scanned, maps a key to its approximate rank
+// (the cumulative count of its 12-bit slice plus its share of the slice, by the next 32
+// key bits, which is monotone in the key), and the digit is that rank scaled to
+// D <= 2^15 digits, so every digit holds about N / D records whatever the skew of the
+// hashes.  Digits are counted per chunk of records in LDS, turned into per-chunk digit
+// offsets by one thread per digit, and scattered with LDS atomics, so no record touches a
+// global atomic or a random global read.  Coarse buckets of whole digits (about 2,048
+// records, at most that plus one digit) are sorted in LDS: binned by their key's offset
+// from the bucket's smallest key, scaled to about two bins per record, and placed by rank
+// inside their bin (k_digit_bucket_sort, in three launches by bucket size, the largest
+// with up to 128 KB of LDS).
 #include "gd_internal.h"
 
 namespace gd {
@@ -86,17 +86,20 @@ constexpr int kBigBlock = 1024;
 constexpr int kTopBits = 12;        // slices of the key range whose counts balance the digits
 constexpr int kTop = 1 << kTopBits;
 
-// Histogram of the keys' top kTopBits bits (per workgroup in LDS, then added globally).
+// Histogram of the top kTopBits bits of every stride-th key (per workgroup in LDS, then
+// added globally).  The digit map only needs the key distribution's shape: any counts give
+// a monotone map (so a correct sort), a sample of the keys a balanced one.
 __global__ __launch_bounds__(kBigBlock) void k_top_hist(const uint64_t *keys, const uint64_t *n_ptr,
-                                                        uint64_t capacity, uint32_t *hist)
+                                                        uint64_t capacity, uint32_t stride,
+                                                        uint32_t *hist)
 {
     __shared__ uint32_t h[kTop];
     for (uint32_t d = threadIdx.x; d < (uint32_t)kTop; d += kBigBlock) h[d] = 0;
     __syncthreads();
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
-    for (uint64_t i = blockIdx.x * (uint64_t)kBigBlock + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * kBigBlock)
+    for (uint64_t i = (blockIdx.x * (uint64_t)kBigBlock + threadIdx.x) * stride; i < n;
+         i += (uint64_t)gridDim.x * kBigBlock * stride)
         atomicAdd(&h[keys[i] >> (64 - kTopBits)], 1u);
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < (uint32_t)kTop; d += kBigBlock)
@@ -142,7 +145,16 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
     if (n > capacity) n = capacity;
     const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
-    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) atomicAdd(&cnt[dm(keys[i])], 1u);
+    constexpr int U = 4;
+    for (uint64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += (uint64_t)kBigBlock * U) {
+        uint64_t key[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (i0 + (uint64_t)u * kBigBlock < c1) key[u] = keys[i0 + (uint64_t)u * kBigBlock];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (i0 + (uint64_t)u * kBigBlock < c1) atomicAdd(&cnt[dm(key[u])], 1u);
+    }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) mat[(size_t)blockIdx.x * D + d] = cnt[d];
 }
@@ -190,10 +202,27 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_scatter(const uint64_t *key
     if (n > capacity) n = capacity;
     const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
-    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBigBlock) {
-        const uint64_t key = keys[i];
-        const uint32_t pos = atomicAdd(&off[dm(key)], 1u);
-        trec[pos] = make_ulonglong2(key, (uint64_t)vals[i]);
+    // four records per thread and step: their loads, LDS atomics and stores overlap
+    constexpr int U = 4;
+    for (uint64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += (uint64_t)kBigBlock * U) {
+        uint64_t key[U];
+        V val[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t i = i0 + (uint64_t)u * kBigBlock;
+            if (i < c1) {
+                key[u] = keys[i];
+                val[u] = vals[i];
+            }
+        }
+        uint32_t pos[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (i0 + (uint64_t)u * kBigBlock < c1) pos[u] = atomicAdd(&off[dm(key[u])], 1u);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (i0 + (uint64_t)u * kBigBlock < c1)
+                trec[pos[u]] = make_ulonglong2(key[u], (uint64_t)val[u]);
     }
 }
 
@@ -572,7 +601,10 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         const uint32_t ch = (uint32_t)sp.chunk;
         const unsigned dg = (D + kBlock - 1) / kBlock;
         if ((e = fill_u32(w.top, 0, kTop, s)) != hipSuccess) return e;
-        GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, w.top);
+        // one key in 8 once there are about 64 per slice (the sample still holds ~8 each)
+        const uint32_t stride = capacity >= ((uint64_t)kTop << 6) ? 8u : 1u;
+        GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, stride,
+                  w.top);
         if ((e = exclusive_scan_u32(w.top, w.cdf, kTop, w.scan_tmp, s)) != hipSuccess) return e;
         GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, D, ch,
                   (const uint64_t *)w.cdf, w.hist);

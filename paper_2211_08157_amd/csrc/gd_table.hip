@@ -12,14 +12,15 @@ namespace gd {
 
 namespace {
 
-__global__ void k_table_header(void *table, uint32_t log2_slots, uint64_t n)
+__global__ void k_table_header(const uint64_t *keys, void *table, uint32_t log2_slots, uint64_t n)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     TableHeader h;
     h.magic = kTableMagic;
     h.log2_slots = log2_slots;
     h.n_keys = n;
-    for (int i = 0; i < 6; i++) h.pad[i] = 0;
+    h.keys_fp = table_keys_fp(keys, n);
+    for (int i = 0; i < 5; i++) h.pad[i] = 0;
     *(TableHeader *)table = h;
 }
 
@@ -73,7 +74,7 @@ hipError_t launch_table_build(const uint64_t *keys, uint64_t n, void *table, hip
     const uint32_t b = table_log2_slots(n);
     hipError_t e = fill_u32((uint32_t *)table, 0, table_bytes(n) / 4, s);
     if (e != hipSuccess) return e;
-    GD_LAUNCH(k_table_header, dim3(1), dim3(64), 0, s, table, b, n);
+    GD_LAUNCH(k_table_header, dim3(1), dim3(64), 0, s, keys, table, b, n);
     if (n > 0) {
         uint64_t blocks = (n + kBlock - 1) / kBlock;
         if (blocks > 16384) blocks = 16384;

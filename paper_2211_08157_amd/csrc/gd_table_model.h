@@ -17,7 +17,8 @@ constexpr uint32_t kTableMagic = 0x48544231u;   // "HTB1"
 struct TableHeader {
     uint32_t magic, log2_slots;
     uint64_t n_keys;
-    uint64_t pad[6];
+    uint64_t keys_fp;       // table_keys_fp of the keys the table was built over
+    uint64_t pad[5];
 };
 static_assert(sizeof(TableHeader) == 64, "slots start 64 bytes in");
 
@@ -27,13 +28,36 @@ struct TableSlot {
 };
 static_assert(sizeof(TableSlot) == 16, "a slot is one 16-byte load");
 
-// (start, count) of q; count 0 when q is absent.  Returns false when the table does not
-// belong to an index of n keys (the caller then searches the sorted keys).
+// Fingerprint of a sorted key array: its size and eight keys spread over it, mixed.  A
+// table whose fingerprint differs was built over other keys.
+__device__ __forceinline__ uint64_t table_keys_fp(const uint64_t *keys, uint64_t n)
+{
+    uint64_t h = n * 0x9e3779b97f4a7c15ull;
+    for (int i = 0; i < 8 && n > 0; i++) {
+        h ^= keys[(n - 1) * (uint64_t)i / 7];
+        h = (h ^ (h >> 29)) * 0xbf58476d1ce4e5b9ull;
+    }
+    return h ^ (h >> 32);
+}
+
+// Whether `table` (table_bytes bytes) is a hash table of the n keys with fingerprint fp
+// whose slots all lie inside the buffer.
+__device__ __forceinline__ bool table_valid(const void *table, size_t table_bytes, uint64_t n,
+                                            uint64_t fp)
+{
+    if (table_bytes < sizeof(TableHeader)) return false;
+    const TableHeader &H = *(const TableHeader *)table;
+    return H.magic == kTableMagic && H.n_keys == n && H.keys_fp == fp && H.log2_slots <= 40 &&
+           sizeof(TableHeader) + (((size_t)1 << H.log2_slots) * sizeof(TableSlot)) <= table_bytes;
+}
+
+// (start, count) of q; count 0 when q is absent.  The caller has checked table_valid.
+// Returns false when a slot's run does not lie inside the n keys (the caller then
+// searches the sorted keys).
 __device__ __forceinline__ bool table_find(const void *table, uint64_t n, uint64_t q,
                                            uint64_t &start, uint64_t &count)
 {
     const TableHeader &H = *(const TableHeader *)table;
-    if (H.magic != kTableMagic || H.n_keys != n || H.log2_slots > 40) return false;
     const uint64_t mask = (1ull << H.log2_slots) - 1;
     const ulonglong2 *slots = (const ulonglong2 *)((const char *)table + sizeof(TableHeader));
     uint64_t s = q & mask;
@@ -41,7 +65,11 @@ __device__ __forceinline__ bool table_find(const void *table, uint64_t n, uint64
         const ulonglong2 v = slots[s];
         const uint32_t cnt = (uint32_t)(v.y >> 32);
         if (cnt == 0) { start = 0; count = 0; return true; }
-        if (v.x == q) { start = (uint32_t)v.y; count = cnt; return true; }
+        if (v.x == q) {
+            start = (uint32_t)v.y;
+            count = cnt;
+            return start + count <= n;
+        }
         s = (s + 1) & mask;
     }
     start = 0;

@@ -6,8 +6,9 @@ header (format version, record count, value width, pattern, k, w, and the byte s
 the optional learned-index model and hash table), zero padding to a multiple of 64, then
 the arrays, each starting on a 64-byte boundary: keys (uint64 x n), vals (uint32 or
 uint64 x n), the learned-index model bytes, the hash-table bytes.  Loading reads the JSON
-and raw arrays only (nothing is executed from the file) and checks every size against
-the file length.
+and raw arrays only (nothing is executed from the file), checks every size against the
+file length, and checks that the model's and the table's headers belong to the keys and
+fit their sizes.
 """
 import json
 import os
@@ -18,6 +19,42 @@ from .api import DeviceIndex
 
 MAGIC = b"GODIETIX"
 VERSION = 1
+RMI_MAGIC, RMI_HEADER, RMI_LEAF = 0x524D4932, 576, 16      # learned-index model layout
+TABLE_MAGIC, TABLE_HEADER, TABLE_SLOT = 0x48544231, 64, 16   # hash-table layout
+M64 = (1 << 64) - 1
+
+
+def keys_fingerprint(keys):
+    """The hash table's fingerprint of a sorted key array (its count and eight keys spread
+    over it, mixed), as the library writes it into the table header."""
+    n = int(keys.size)
+    h = (n * 0x9E3779B97F4A7C15) & M64
+    for i in range(8 if n > 0 else 0):
+        h ^= int(keys[(n - 1) * i // 7])
+        h = ((h ^ (h >> 29)) * 0xBF58476D1CE4E5B9) & M64
+    return h ^ (h >> 32)
+
+
+def check_models(keys, rmi, table):
+    """Raise ValueError unless the model and table blobs are headers of this index's kind
+    whose leaves / slots fit their byte sizes (a damaged or foreign file is refused)."""
+    n = int(keys.size)
+    if rmi.size:
+        if rmi.size < RMI_HEADER:
+            raise ValueError("learned-index model shorter than its header")
+        magic, kind, log2 = (int(x) for x in rmi[:12].view(np.uint32))
+        nk = int(rmi[16:24].view(np.uint64)[0])
+        if (magic != RMI_MAGIC or kind > 1 or not 1 <= log2 <= 24 or nk != n or
+                RMI_HEADER + (RMI_LEAF << log2) > rmi.size):
+            raise ValueError("learned-index model does not belong to this index")
+    if table.size:
+        if table.size < TABLE_HEADER:
+            raise ValueError("hash table shorter than its header")
+        magic, log2 = (int(x) for x in table[:8].view(np.uint32))
+        nk, fp = (int(x) for x in table[8:24].view(np.uint64))
+        if (magic != TABLE_MAGIC or log2 > 40 or nk != n or fp != keys_fingerprint(keys) or
+                TABLE_HEADER + (TABLE_SLOT << log2) > table.size):
+            raise ValueError("hash table does not belong to this index")
 
 
 def _pad(n):
@@ -72,6 +109,7 @@ def load_index(path, device="cuda"):
             out.append(np.fromfile(f, dtype=dt, count=nbytes // np.dtype(dt).itemsize))
             pos += nbytes + _pad(nbytes)
     keys, vals, rmi, table = out
+    check_models(keys, rmi, table)
 
     def dev(a, signed):
         return torch.from_numpy(a.view(signed)).to(device)

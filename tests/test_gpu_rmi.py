@@ -54,15 +54,17 @@ def test_rmi_lookup_equals_binary_search(gpu, ref_index, root, leaves):
 
 @pytest.mark.parametrize("root", ["mlp", "linear"])
 def test_rmi_training_is_deterministic(gpu, ref_index, root):
-    # every leaf's base is the first key routed to it or past it, whatever order the
-    # claims land in: two trainings give the same bytes and the bases never decrease
+    # every leaf's boundaries are the first keys routed to it or past it, whatever order
+    # the claims land in: two trainings give the same bytes; every leaf's base position
+    # (its first key plus the fitted intercept) lies inside the keys
     ref, offs, ek, ev, ix = ref_index
     a = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
     b = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
     assert np.array_equal(a, b)
-    base = a[320:].view(np.uint32).reshape(-1, 4)[:, 1]     # header 320 B, 16-B leaves
-    assert base.size == 1 << 18 and base[0] == 0
-    assert np.all(np.diff(base.astype(np.int64)) >= 0) and base[-1] <= ek.size
+    leaves = a[576:].view(np.uint32).reshape(-1, 4)         # header 576 B, 16-B leaves
+    assert leaves.shape[0] == 1 << 18 and np.all(leaves[:, 1] <= ek.size)
+    slope = leaves[:, 2].view(np.float32)
+    assert np.all(np.isfinite(slope)) and np.all(slope >= 0)
 
 
 def test_rmi_corrupted_model_falls_back(gpu, ref_index):
@@ -70,9 +72,9 @@ def test_rmi_corrupted_model_falls_back(gpu, ref_index):
     q = queries_from(ek)
     qt = torch.from_numpy(q.view(np.int64)).cuda()
     m = gpu.rmi_train(ix, root="mlp", log2_leaves=12)
-    words = m.rmi.view(torch.int32)                 # header 320 B, then 16-B leaves
-    leaves = words[80:].view(-1, 4)                 # khi, base, slope, icpt|err_lo|err_hi
-    leaves[:, 3] = leaves[:, 3] & 0xFFFF            # both errors 0
+    words = m.rmi.view(torch.int32)                 # header 576 B, then 16-B leaves
+    leaves = words[144:].view(-1, 4)                # khi, base, slope, err_lo|err_hi
+    leaves[:, 3] = 0                                # both errors 0
     leaves[::3, 2] = 0x3f800000                     # slope = 1.0: wild predictions
     leaves[1::5, 1] = 0x7FFFFFFF                    # base far past the end
     lb_r, occ_r = gpu.lookup(m, qt)
@@ -117,3 +119,60 @@ def test_rmi_empty_and_tiny_index(gpu):
         elb, eocc = oracle.lookup(ek, q)
         assert np.array_equal(u32(lb).astype(np.uint64), elb)
         assert np.array_equal(u32(occ).astype(np.uint64), eocc)
+
+
+def test_rmi_model_beyond_its_bytes_is_ignored(gpu, ref_index):
+    # a model whose leaves would lie past the bytes the index declares is not read (the
+    # buffers below are allocated large enough that even a read would stay inside them)
+    import ctypes
+    from paper_2211_08157_amd import api
+    ref, offs, ek, ev, ix = ref_index
+    q = queries_from(ek)
+    qt = torch.from_numpy(q.view(np.int64)).cuda()
+    elb, eocc = oracle.lookup(ek, q)
+    L = api.lib()
+    size12, size13 = L.godiet_rmi_size(12), L.godiet_rmi_size(13)
+    blob = torch.zeros(size13 + 64, dtype=torch.uint8, device="cuda")
+    off = (-blob.data_ptr()) % 64
+    blob = blob[off:off + size13]
+    r = L.godiet_rmi_train(ctypes.byref(ix.c()), 1, 12, ctypes.c_void_p(blob.data_ptr()), size13,
+                           api._stream())
+    assert r == api.OK
+    reads = gpu.to_device(*datagen.fixed_reads(ref, 500, 150, 45, sub=0.01)[:2])
+    for case in ("truncated", "leaf count"):
+        if case == "truncated":
+            b = blob[:size12 // 2]                    # half the leaves' bytes declared
+        else:
+            blob.view(torch.int32)[2] = 13            # header claims 2^13 leaves ...
+            b = blob[:size12]                         # ... but declares 2^12 leaves' bytes
+        lb, occ = gpu.lookup(ix.with_rmi(b), qt)
+        assert np.array_equal(u32(lb).astype(np.uint64), elb)
+        assert np.array_equal(u32(occ).astype(np.uint64), eocc)
+        a, _, _ = gpu.seed(ix.with_rmi(b), reads, "10", 15, 10)
+        a0, _, _ = gpu.seed(ix, reads, "10", 15, 10)
+        assert a.shape[0] > 0 and torch.equal(a, a0), case
+    # fewer bytes than a header and two leaves: refused on the host
+    with pytest.raises(api.GodietError):
+        gpu.lookup(ix.with_rmi(blob[:300]), qt)
+
+
+def test_rmi_stats_account_for_every_query(gpu, ref_index):
+    # the diagnostics see every query once; a fitted model brackets every present key, a
+    # model with its error bounds zeroed misses some, and each query's window is the one
+    # the lookups read (their results stay those of binary search either way)
+    ref, offs, ek, ev, ix = ref_index
+    q = queries_from(ek)
+    qt = torch.from_numpy(q.view(np.int64)).cuda()
+    m = gpu.rmi_train(ix, root="mlp", log2_leaves=12)
+    st = gpu.rmi_stats(m, qt)
+    assert st["queries"] == q.size and st["fallbacks"] + sum(st["window_keys"]) == q.size
+    present = torch.from_numpy(ek[::7].view(np.int64)).cuda()
+    assert gpu.rmi_stats(m, present)["fallbacks"] == 0
+    m.rmi.view(torch.int32)[144:].view(-1, 4)[:, 3] = 0     # err_lo = err_hi = 0
+    st0 = gpu.rmi_stats(m, present)
+    assert 0 < st0["fallbacks"] < present.numel()
+    # every bracketing window is [p, p + 1) with its two brackets: 3 keys (fewer at the ends)
+    assert sum(st0["window_keys"][:3]) == present.numel() - st0["fallbacks"]
+    lb, occ = gpu.lookup(m, present)
+    elb, eocc = oracle.lookup(ek, ek[::7])
+    assert np.array_equal(u32(lb).astype(np.uint64), elb)

@@ -1,7 +1,8 @@
 """Hash-table form of the seed index (the paper's hash -> location-list table): seeding
 and containment through the table equal binary search and the oracle, on a repeat-rich
 reference (long runs of equal keys), for keys absent from the index, with every read
-option, for the empty index, and with a table built for other keys (ignored)."""
+option, for the empty index, and with a table built for other keys (refused when too small
+for the index, ignored when of the same size)."""
 import numpy as np
 import pytest
 
@@ -44,12 +45,19 @@ def test_seed_through_table_equals_oracle(gpu, setup, shift_mode, t, max_occ):
 
 
 def test_table_from_other_keys_is_ignored_and_empty_index(gpu, setup):
+    from paper_2211_08157_amd import api
     ref, offs, ix, ek, ev, codes, ro = setup
-    other = gpu.index_build(gpu.to_device(ref[:300_000], [0, 300_000]), "10", 15, 10)
-    mixed = ix.with_table(gpu.table_build(other).table)
     reads = gpu.to_device(codes, ro)
-    a, _, _ = gpu.seed(mixed, reads, "10", 15, 10)
     ea, _, _ = oracle.seed(ek, ev, codes, ro, "10", 15, 10)
+    # a table of another index: smaller than this index needs, refused on the host
+    other = gpu.index_build(gpu.to_device(ref[:300_000], [0, 300_000]), "10", 15, 10)
+    with pytest.raises(api.GodietError):
+        gpu.seed(ix.with_table(gpu.table_build(other).table), reads, "10", 15, 10)
+    # a table of other keys with the same count: its key fingerprint differs, so seeding
+    # searches the sorted keys instead
+    shifted = api.DeviceIndex(ix.keys + 1, ix.vals, ix.n, 32)
+    mixed = ix.with_table(gpu.table_build(shifted).table)
+    a, _, _ = gpu.seed(mixed, reads, "10", 15, 10)
     assert np.array_equal(u32(a).reshape(-1, 4), ea)
     empty = gpu.index_build(gpu.to_device(ref[:5], [0, 5]), "10", 15, 10)
     assert empty.n == 0
