@@ -25,10 +25,14 @@ class Scope {
 }  // namespace trace
 
 // Launch a kernel on stream s, bracketed by trace events when tracing is on.
+// Launches a kernel (traced when tracing is on) and returns from the calling function
+// with the error if the launch failed (every caller returns hipError_t).
 #define GD_LAUNCH(kernel, grid, block, shmem, s, ...)                        \
     do {                                                                      \
         ::gd::trace::Scope gd_scope_(#kernel, s);                             \
         hipLaunchKernelGGL(kernel, grid, block, shmem, s, __VA_ARGS__);       \
+        const hipError_t gd_err_ = hipGetLastError();                         \
+        if (gd_err_ != hipSuccess) return gd_err_;                            \
     } while (0)
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -136,8 +136,8 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
                                                            uint32_t chunk, const uint64_t *cdf,
                                                            uint32_t *mat)
 {
-    __shared__ uint32_t cnt[1 << kDigitBits];
-    __shared__ uint32_t cl[kTop + 1];
+    extern __shared__ uint32_t dyn[];           // D counters, then the kTop + 1 slice counts
+    uint32_t *cnt = dyn, *cl = dyn + D;
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) cnt[d] = 0;
     DigitMap dm;
     dm.init(cdf, cl, D);
@@ -193,8 +193,8 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_scatter(const uint64_t *key
                                                              uint32_t chunk, const uint64_t *cdf,
                                                              const uint32_t *mat, ulonglong2 *trec)
 {
-    __shared__ uint32_t off[1 << kDigitBits];
-    __shared__ uint32_t cl[kTop + 1];
+    extern __shared__ uint32_t dyn[];           // D offsets, then the kTop + 1 slice counts
+    uint32_t *off = dyn, *cl = dyn + D;
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) off[d] = mat[(size_t)blockIdx.x * D + d];
     DigitMap dm;
     dm.init(cdf, cl, D);
@@ -590,6 +590,22 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort_big(ulonglong2 *trec, co
     }
 }
 
+// Raise the dynamic-LDS limit of the digit kernels to the CU's 160 KB (once per process).
+template <typename V>
+hipError_t allow_digit_lds()
+{
+    static hipError_t once = [] {
+        const int bytes = 160 * 1024;
+        hipError_t e = hipFuncSetAttribute((const void *)k_digit_count,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_digit_scatter<V>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        return e;
+    }();
+    return once;
+}
+
 template <typename V>
 hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *vals,
                      const uint64_t *n_ptr, uint64_t capacity, hipStream_t s)
@@ -606,15 +622,18 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, stride,
                   w.top);
         if ((e = exclusive_scan_u32(w.top, w.cdf, kTop, w.scan_tmp, s)) != hipSuccess) return e;
-        GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, D, ch,
+        // LDS sized to the digits (two workgroups per CU up to 2^14 digits)
+        const size_t lds = ((size_t)D + kTop + 1) * sizeof(uint32_t);
+        if ((e = allow_digit_lds<V>()) != hipSuccess) return e;
+        GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), lds, s, keys, n_ptr, capacity, D, ch,
                   (const uint64_t *)w.cdf, w.hist);
         GD_LAUNCH(k_digit_totals, dim3(dg), dim3(kBlock), 0, s, (const uint32_t *)w.hist, nc, D,
                   w.tot);
         if ((e = exclusive_scan_u32(w.tot, w.fofs, D, w.scan_tmp, s)) != hipSuccess) return e;
         GD_LAUNCH(k_digit_offsets, dim3(dg), dim3(kBlock), 0, s, w.hist, nc, D,
                   (const uint64_t *)w.fofs);
-        GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), 0, s, keys, vals, n_ptr, capacity,
-                  D, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.hist, w.trec);
+        GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), lds, s, keys, vals, n_ptr,
+                  capacity, D, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.hist, w.trec);
     } else {
         if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
         const unsigned grid = 4096;
@@ -662,8 +681,13 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
     // digits mode while balanced digits (at most 2^15 of them, about 512 records each when
     // there are fewer) stay within three quarters of the largest bucket capacity
     if (capacity > 0 && capacity <= ((dcap * 3 / 4) << kDigitBits)) {
+        // about 512 records per digit for small indexes; large ones keep 2^14 digits while
+        // a digit holds at most ~6K records: twice the records of one digit per chunk
+        // (longer runs of scattered records, half the LDS of 2^15 counters), buckets still
+        // within the largest bucket launch
         int Bd = 4;
         while (Bd < kDigitBits && (capacity >> Bd) > 512) Bd++;
+        if (Bd == kDigitBits && (capacity >> (kDigitBits - 1)) <= 6144) Bd = kDigitBits - 1;
         sp.digits = true;
         sp.Bf = Bd;
         sp.nfine = (size_t)1 << Bd;
