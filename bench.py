@@ -130,9 +130,7 @@ class Session:
         self.cix_table = api.Index(self.ikeys.data_ptr(), self.ivals.data_ptr(), self.n_index, 32,
                                    None, 0, self.table.data_ptr(), self.table.numel())
         t = self.tuning
-        self.opts = api.SeedOpts(-1, 0, 0, int(t.get("long_records", 0)),
-                                 int(t.get("lookup_blocks", 0)), int(t.get("long_blocks", 0)),
-                                 None)
+        self.opts = api.seed_opts(tuning=t)
         # with overlap, index construction runs on a side stream (default priority) and
         # overlaps the read sketches of seeding; events order the two streams both ways
         self.overlap = False
@@ -647,8 +645,10 @@ def kept_counts(lengths, pattern, shift):
 
 
 
-# launch-parameter grid searched on the mixed batch (every candidate's anchors must match)
-TUNE_GRID = {"long_records": [64, 192], "lookup_blocks": [8192], "long_blocks": [1024]}
+# launch-parameter grid searched on the mixed batch (every candidate's anchors must match):
+# 12 candidates
+TUNE_GRID = {"long_records": [64, 192], "lookup_blocks": [8192, 32768],
+             "long_blocks": [256, 1024, 4096]}
 STEP_MODES = ("learned_index", "binary_search", "hash_table")
 
 
@@ -665,7 +665,7 @@ def uneven_section(gd, torch, d, args):
     ref = gd.to_device(d["ref"], d["ref_offsets"])
     reads = gd.to_device(d["reads"], d["read_offsets"])
     res = {}
-    for pat in ("10", "110"):
+    for pat in args.patterns:
         head = pat == "10"
         ix = gd.index_build(ref, pat, d["k"], d["w"])
         leaves = leaves_for(ix.n)
@@ -686,7 +686,11 @@ def uneven_section(gd, torch, d, args):
         li = modes["learned_index"]
         r = dict(index_records=s.n_index, anchors=s.n_anchors, lookups_per_step=s.queries,
                  log2_leaves=leaves, tuning=tuning,
-                 tuning_report=[dict(tuning=t, ms=ms) for t, ms in report],
+                 tuning_report=dict(candidates=len(report), winner=tuning,
+                                    winner_ms=min(ms for _, ms in report),
+                                    slowest_ms=max(ms for _, ms in report),
+                                    note="seeding pass per candidate (index and model built)",
+                                    rows=[dict(tuning=t, ms=ms) for t, ms in report]),
                  work_per_step=units, output_sha256_16=li["digest"])
         for m in STEP_MODES:
             r[m] = dict(ms_per_step=modes[m]["ms_per_step"], reads_per_s=modes[m]["reads_per_s"],
@@ -941,6 +945,8 @@ def main():
     ap.add_argument("--sections", default=",".join(SECTIONS),
                     help="comma-separated parts to run: " + ", ".join(SECTIONS) +
                          " (the headline needs 'uneven')")
+    ap.add_argument("--patterns", default="10,110",
+                    help="patterns of the uneven section ('10' is the headline and required)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -948,6 +954,10 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (the index is "
               "replicated and reads split by range when it is sharded); run with --gpus 1",
               file=sys.stderr)
+        sys.exit(2)
+    args.patterns = [x for x in args.patterns.split(",") if x]
+    if "10" not in args.patterns or set(args.patterns) - {"10", "110"}:
+        print("--patterns: a comma-separated subset of 10,110 that holds 10", file=sys.stderr)
         sys.exit(2)
     sections = set(x for x in args.sections.split(",") if x)
     bad = sections - set(SECTIONS)
@@ -997,7 +1007,8 @@ def main():
             out["kernels"] = h["learned_index"]["kernels"]
             out["output_sha256_16"] = h["output_sha256_16"]
             out["tuning_report"] = h["tuning_report"]
-            out["pattern_110"] = un["110"]
+            if "110" in un:
+                out["pattern_110"] = un["110"]
         if ref is None:
             ref = gd.to_device(d["ref"], d["ref_offsets"])
             reads = gd.to_device(d["reads"], d["read_offsets"])

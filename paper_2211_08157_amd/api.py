@@ -48,6 +48,19 @@ class SeedOpts(ctypes.Structure):
                 ("index_ready", ctypes.c_void_p)]
 
 
+TUNING_KEYS = ("long_records", "lookup_blocks", "long_blocks")
+
+
+def seed_opts(shift_mode=-1, align_t=0, max_occ=0, tuning=None, index_ready=None):
+    """godiet_seed_opts from a tuning dict (missing launch parameters: library default)."""
+    t = tuning or {}
+    bad = set(t) - set(TUNING_KEYS)
+    if bad:
+        raise ValueError("unknown launch parameters: %s" % ", ".join(sorted(bad)))
+    return SeedOpts(shift_mode=int(shift_mode), align_t=int(align_t), max_occ=int(max_occ),
+                    index_ready=index_ready, **{k: int(t.get(k, 0)) for k in TUNING_KEYS})
+
+
 class VoteOpts(ctypes.Structure):
     _fields_ = [("max_dist", ctypes.c_uint32), ("min_votes", ctypes.c_uint32),
                 ("max_winners", ctypes.c_uint32), ("sort", ctypes.c_uint32)]
@@ -456,10 +469,8 @@ def seed(index, reads, pattern, k, w, shift_mode=-1, align_t=0, max_occ=0, capac
     L = lib()
     prm = _params(pattern, k, w, hash)
     ix = index.c()
-    t = tuning or {}
-    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), int(t.get("long_records", 0)),
-                    int(t.get("lookup_blocks", 0)), int(t.get("long_blocks", 0)),
-                    index_ready.cuda_event if index_ready is not None else None)
+    opts = seed_opts(shift_mode, align_t, max_occ, tuning,
+                     index_ready.cuda_event if index_ready is not None else None)
     ws = _empty(workspace_size(OP_SEED, reads, pattern, k, w, index.n), torch.uint8)
     off = _empty(reads.n_seq + 1, torch.int64)
     shift = _empty(reads.n_seq, torch.uint8)
@@ -488,7 +499,7 @@ def contain(index, reads, pattern, k, w, n_genomes, shift_mode=-1, align_t=0, ma
     L = lib()
     prm = _params(pattern, k, w, hash)
     ix = index.c()
-    opts = SeedOpts(int(shift_mode), int(align_t), int(max_occ), 0, 0, 0)
+    opts = seed_opts(shift_mode, align_t, max_occ)
     ws = _empty(workspace_size(OP_CONTAIN, reads, pattern, k, w, index.n), torch.uint8)
     counts = _empty(n_genomes, torch.int32)
     sizes = _empty(n_genomes, torch.int32)

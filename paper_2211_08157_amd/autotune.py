@@ -9,11 +9,13 @@ class and the batch's read-length profile, so a later batch of the same shape re
 them without timing.
 """
 import hashlib
+import itertools
 import json
 import os
 
 import numpy as np
 
+from .api import TUNING_KEYS
 from .plan import SeedPlan
 
 DEFAULT_GRID = {
@@ -21,6 +23,15 @@ DEFAULT_GRID = {
     "lookup_blocks": [2048, 8192, 32768],
     "long_blocks": [256, 1024, 4096],
 }
+
+
+def candidates(grid):
+    """Every combination of the grid's values, in the grid's key order."""
+    bad = set(grid) - set(TUNING_KEYS)
+    if bad:
+        raise ValueError("unknown launch parameters: %s" % ", ".join(sorted(bad)))
+    keys = list(grid)
+    return [dict(zip(keys, vals)) for vals in itertools.product(*(grid[k] for k in keys))]
 
 
 def _cache_path(path):
@@ -68,9 +79,7 @@ def tune(index, reads, pattern, k, w, grid=None, reps=3, cache=None, use_cache=T
             table = {}
         if key in table:
             return dict(table[key]["tuning"]), []
-    cands = [dict(long_records=a, lookup_blocks=b, long_blocks=c)
-             for a in grid["long_records"] for b in grid["lookup_blocks"]
-             for c in grid["long_blocks"]]
+    cands = candidates(grid)
     report, ref_digest, capacity = [], None, None
     for cand in cands:
         plan = SeedPlan(index, reads, pattern, k, w, tuning=cand, capacity=capacity, **seed_kw)

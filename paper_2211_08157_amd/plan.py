@@ -20,9 +20,7 @@ class SeedPlan:
         self.pattern, self.k, self.w = pattern, int(k), int(w)
         t = tuning or {}
         self.tuning = dict(t)
-        self.opts = api.SeedOpts(int(shift_mode), int(align_t), int(max_occ),
-                                 int(t.get("long_records", 0)), int(t.get("lookup_blocks", 0)),
-                                 int(t.get("long_blocks", 0)))
+        self.opts = api.seed_opts(shift_mode, align_t, max_occ, t)
         self.prm = api.Params(pattern.encode(), self.k, self.w)
         self.cix = index.c()
         self.creads = reads.c()

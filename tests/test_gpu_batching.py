@@ -81,10 +81,10 @@ def test_autotune_candidates_agree(gpu, mixed, tmp_path):
     from paper_2211_08157_amd import autotune
     ref, ix, ek, ev, classes, codes, offs = mixed
     reads = gpu.to_device(codes, offs)
-    grid = {"long_records": [32, 4096], "lookup_blocks": [64, 8192], "long_blocks": [1, 512]}
+    grid = {"long_records": [32, 4096], "lookup_blocks": [64, 8192], "long_blocks": [1, 7, 512]}
     cache = str(tmp_path / "tune.json")
     best, report = autotune.tune(ix, reads, PAT, K, W, grid=grid, reps=1, cache=cache)
-    assert len(report) == 8 and best in [r[0] for r in report]
+    assert len(report) == 12 and best in [r[0] for r in report]
     again, rep2 = autotune.tune(ix, reads, PAT, K, W, grid=grid, reps=1, cache=cache)
     assert again == best and rep2 == []
     a, _, _ = gpu.seed(ix, reads, PAT, K, W, tuning=best)
