@@ -276,6 +276,31 @@ def time_modes(gd, torch, s, modes, steps, warmup, index=True):
     return out
 
 
+OVERLAP_NOTE = ("index build + learned-index training on a side stream, seeding waits on "
+                "their event after its read sketches")
+
+
+def overlapped_step(torch, s, steps, warmup, digest):
+    """ms per learned-index step with index construction on a second stream overlapping
+    the read sketches (outputs must equal the one-stream step's)."""
+    s.overlap = True
+    try:
+        for _ in range(warmup):
+            s.step("learned_index")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step("learned_index")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        s.check()
+        if s.digest() != digest:
+            raise RuntimeError("overlapped steps changed the outputs")
+    finally:
+        s.overlap = False
+    return ms
+
+
 def graph_step(torch, s, mode, steps):
     """The whole step (index build, training, seeding) captured as one HIP graph and
     replayed; returns ms per replay.  Outputs must equal the eager step's."""
@@ -719,6 +744,10 @@ def uneven_section(gd, torch, d, args):
                                    note="the whole learned-index step captured as one HIP "
                                         "graph and replayed")
             log("[bench] graph-replayed step: %.3f ms" % gms)
+            oms = overlapped_step(torch, s, steps, warm, li["digest"])
+            r["overlapped_step"] = dict(ms_per_step=oms, reads_per_s=s.reads.n_seq / (oms * 1e-3),
+                                        note=OVERLAP_NOTE)
+            log("[bench] overlapped step: %.3f ms" % oms)
         r["index_build"] = index_build_rate(gd, torch, s)
         log("[bench] index build, pattern %s: %.3f ms per call, sort %.3f ms = %.0f GB/s"
             % (pat, r["index_build"]["call_ms"], r["index_build"]["sort_ms"],
@@ -855,20 +884,7 @@ def illumina_section(gd, torch, data, args):
     log("[bench] illumina: index %d records, %d anchors, %d lookups per step"
         % (s.n_index, s.n_anchors, s.queries))
     modes = time_modes(gd, torch, s, STEP_MODES, args.steps, args.warmup)
-    # index construction on a second stream, overlapping the read sketches
-    s.overlap = True
-    for _ in range(args.warmup):
-        s.step("learned_index")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step("learned_index")
-    torch.cuda.synchronize()
-    ms_ov = (time.perf_counter() - t0) * 1e3 / args.steps
-    s.check()
-    if s.digest() != modes["learned_index"]["digest"]:
-        raise RuntimeError("overlapped steps changed the outputs")
-    s.overlap = False
+    ms_ov = overlapped_step(torch, s, args.steps, args.warmup, modes["learned_index"]["digest"])
     units = work_units(s)
     li = modes["learned_index"]
     dom = li["dominant"]
@@ -885,9 +901,7 @@ def illumina_section(gd, torch, data, args):
              work_per_step=units, output_sha256_16=li["digest"],
              learned_vs_binary_speedup=modes["binary_search"]["ms_per_step"] / li["ms_per_step"],
              overlapped_step=dict(ms_per_step=ms_ov, reads_per_s=s.reads.n_seq / (ms_ov * 1e-3),
-                                  note="index build + learned-index training on a side "
-                                       "stream, seeding waits on their event after its read "
-                                       "sketches"),
+                                  note=OVERLAP_NOTE),
              roofline=roof, roofline_second_kernel=roof_next)
     for m in STEP_MODES:
         r[m] = dict(ms_per_step=modes[m]["ms_per_step"], reads_per_s=modes[m]["reads_per_s"],
@@ -998,6 +1012,7 @@ def main():
             out["learned_vs_binary_speedup"] = h["learned_vs_binary_speedup"]
             out["hash_table"] = h["hash_table"]
             out["graph_step"] = h["graph_step"]
+            out["overlapped_step"] = h["overlapped_step"]
             out["seeding_pass"] = h["seeding_pass"]
             out["roofline"] = h["roofline"]
             out["roofline_sketch"] = h.get("roofline_sketch")

@@ -106,24 +106,25 @@ __global__ __launch_bounds__(kBigBlock) void k_top_hist(const uint64_t *keys, co
         if (h[d]) atomicAdd(&hist[d], h[d]);
 }
 
-// Key -> digit, monotone in the key.  C (in LDS) holds the kTop + 1 cumulative slice
-// counts; a key's approximate rank is its slice's start plus the slice's count times the
+// Key -> digit, monotone in the key.  The kTop + 1 cumulative slice counts are the first
+// kTop in LDS and the total N in a register; a key's approximate rank is its slice's start plus the slice's count times the
 // key's position inside the slice (its next 32 bits), and the digit is rank * D / N.
 struct DigitMap {
-    const uint32_t *C;
+    const uint32_t *C;                   // the first kTop CDF entries (in LDS)
+    uint32_t total;                      // the last one, N
     uint64_t mul;                        // D * 2^32 / N
     __device__ __forceinline__ void init(const uint64_t *cdf, uint32_t *lds, uint32_t D)
     {
-        for (uint32_t j = threadIdx.x; j <= (uint32_t)kTop; j += blockDim.x) lds[j] = (uint32_t)cdf[j];
+        for (uint32_t j = threadIdx.x; j < (uint32_t)kTop; j += blockDim.x) lds[j] = (uint32_t)cdf[j];
+        total = (uint32_t)cdf[kTop];
         __syncthreads();
         C = lds;
-        const uint64_t n = C[kTop];
-        mul = n ? ((uint64_t)D << 32) / n : 0;
+        mul = total ? ((uint64_t)D << 32) / total : 0;
     }
     __device__ __forceinline__ uint32_t operator()(uint64_t x) const
     {
         const uint32_t j = (uint32_t)(x >> (64 - kTopBits));
-        const uint32_t lo = C[j], cnt = C[j + 1] - lo;
+        const uint32_t lo = C[j], cnt = (j + 1 < (uint32_t)kTop ? C[j + 1] : total) - lo;
         const uint32_t f = (uint32_t)(x >> (64 - kTopBits - 32));
         const uint32_t rank = lo + (uint32_t)(((uint64_t)cnt * f) >> 32);   // < N
         return (uint32_t)(((uint64_t)rank * mul) >> 32);                    // < D
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
                                                            uint32_t chunk, const uint64_t *cdf,
                                                            uint32_t *mat)
 {
-    extern __shared__ uint32_t dyn[];           // D counters, then the kTop + 1 slice counts
+    extern __shared__ uint32_t dyn[];           // D counters, then kTop slice CDF entries
     uint32_t *cnt = dyn, *cl = dyn + D;
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) cnt[d] = 0;
     DigitMap dm;
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_scatter(const uint64_t *key
                                                              uint32_t chunk, const uint64_t *cdf,
                                                              const uint32_t *mat, ulonglong2 *trec)
 {
-    extern __shared__ uint32_t dyn[];           // D offsets, then the kTop + 1 slice counts
+    extern __shared__ uint32_t dyn[];           // D offsets, then kTop slice CDF entries
     uint32_t *off = dyn, *cl = dyn + D;
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) off[d] = mat[(size_t)blockIdx.x * D + d];
     DigitMap dm;
@@ -622,8 +623,8 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, stride,
                   w.top);
         if ((e = exclusive_scan_u32(w.top, w.cdf, kTop, w.scan_tmp, s)) != hipSuccess) return e;
-        // LDS sized to the digits (two workgroups per CU up to 2^14 digits)
-        const size_t lds = ((size_t)D + kTop + 1) * sizeof(uint32_t);
+        // LDS sized to the digits: 80 KB at 2^14 digits, two workgroups per CU
+        const size_t lds = ((size_t)D + kTop) * sizeof(uint32_t);
         if ((e = allow_digit_lds<V>()) != hipSuccess) return e;
         GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), lds, s, keys, n_ptr, capacity, D, ch,
                   (const uint64_t *)w.cdf, w.hist);
@@ -691,9 +692,14 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
         sp.digits = true;
         sp.Bf = Bd;
         sp.nfine = (size_t)1 << Bd;
-        // chunks of at least 32K records, at most about 1,024 of them
-        uint64_t chunk = 32768;
-        while ((capacity + chunk - 1) / chunk > 1024) chunk *= 2;
+        // chunks of at least 32K records (a multiple of the 4,096 a workgroup step takes),
+        // as few as fill 256 CUs at once (two workgroups per CU up to 2^14 digits, one
+        // above): the longer a chunk, the longer its run of records in each digit's range
+        // (short scattered runs cost partial-line writes)
+        const uint64_t slots = Bd <= 14 ? 512 : 256;
+        uint64_t chunk = (capacity + slots - 1) / slots;
+        chunk = (chunk + 4095) / 4096 * 4096;
+        if (chunk < 32768) chunk = 32768;
         sp.chunk = (size_t)chunk;
         sp.nchunks = (size_t)((capacity + chunk - 1) / chunk);
         sp.target = (capacity >> Bd) > 512 ? 2048 : 512;
