@@ -53,7 +53,16 @@ SORT_BYTES = 24
 SORT_KERNELS = ("k_digit", "k_hist", "k_scatter", "k_bucket_sort", "k_coarse_starts")
 # HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
 # kernel source on a workload; reported only while that source is unchanged.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("k_lookup<2>", "uneven-1Gbp/10"): dict(
+        summary="profiles/k_lookup_uneven-1Gbp_hbm_bytes.md",
+        src="paper_2211_08157_amd/csrc/gd_seed.hip", sha256_16="9a1f90b2215604c5",
+        bytes_per_step=37770.8e6),
+    ("k_sketch<11,0>", "uneven-1Gbp/10"): dict(
+        summary="profiles/k_sketch_uneven-1Gbp_hbm_bytes.md",
+        src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="4938a77b0d40d4f5",
+        bytes_per_step=3060.6e6),
+}
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
 SECTIONS = ("uneven", "lookups", "sketch1g", "illumina", "extras", "containment")
 
@@ -732,6 +741,13 @@ def uneven_section(gd, torch, d, args):
         n_l, ms_l = li["live"][dom]
         roof = roofline(dom, s, units, ms_l, steps, n_l, "uneven-1Gbp/" + pat)
         roof["timing"] = "HIP events around this kernel's launches inside the timed region"
+        if roof and roof["kernel"].startswith("k_lookup"):
+            # the lookups as random requests: one launch's time at the rate of random 8-byte
+            # gathers into an array of the index's size, per query of the launch
+            g = gather_rate(torch, s.n_index, s.queries_per_shift[0])
+            roof["random_gather_per_s"] = g
+            roof["requests_per_query"] = (roof["avg_launch_ms"] * 1e-3 * g /
+                                          (s.queries / roof["launches_per_step"]))
         r["roofline"] = roof
         sk = [kv for kv in li["trace"].items() if kv[0].startswith("k_sketch")]
         if sk:
