@@ -50,7 +50,8 @@ LOOKUP_BYTES = 8 + 8 + 64
 # Algorithmic bytes of the index sort per record: one read and one write of the 12-byte
 # (key, value) record.
 SORT_BYTES = 24
-SORT_KERNELS = ("k_digit", "k_hist", "k_scatter", "k_bucket_sort", "k_coarse_starts")
+SORT_KERNELS = ("k_top_hist", "k_digit", "k_hist", "k_scatter", "k_bucket_sort", "k_coarse",
+                "k_fine_scatter")
 # HBM bytes measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy) for a
 # kernel source on a workload; reported only while that source is unchanged.
 MEASURED_TRAFFIC = {

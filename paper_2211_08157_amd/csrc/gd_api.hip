@@ -135,6 +135,8 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine > sort_top_bins() ? o->sp.nfine
                                                                                  : sort_top_bins()));
     o->so.trec = b.take<ulonglong2>(capacity);
+    o->so.tmp = o->sp.two_level ? b.take<ulonglong2>(capacity) : nullptr;
+    o->so.cmat = o->sp.two_level ? b.take<uint32_t>(o->sp.nchunks * 256) : nullptr;
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
     o->so.overflow_n = b.take<uint32_t>(1);
@@ -164,6 +166,8 @@ void plan_vote_ws(Bump &b, uint32_t n_reads, uint64_t capacity, VoteWs *o)
     o->so.scan_tmp = b.take<uint64_t>(scan_scratch(o->sp.nfine > sort_top_bins() ? o->sp.nfine
                                                                                  : sort_top_bins()));
     o->so.trec = b.take<ulonglong2>(capacity);
+    o->so.tmp = o->sp.two_level ? b.take<ulonglong2>(capacity) : nullptr;
+    o->so.cmat = o->sp.two_level ? b.take<uint32_t>(o->sp.nchunks * 256) : nullptr;
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
     o->so.overflow_n = b.take<uint32_t>(1);
@@ -338,10 +342,13 @@ size_t godiet_workspace_size(int32_t op, const godiet_seqs *seqs, const godiet_s
         return b.off;
     }
     case GODIET_OP_INDEX_BUILD: {
+        // enough for either value width (the sort's partition depends on it)
         if (!valid_params(prm, &P)) return 0;
         IndexWs o;
+        Bump b4(nullptr);
         plan_index_ws(b, seqs, P, prm->w, n_index, 8, &o);
-        return b.off;
+        plan_index_ws(b4, seqs, P, prm->w, n_index, 4, &o);
+        return b.off > b4.off ? b.off : b4.off;
     }
     case GODIET_OP_SEED:
     case GODIET_OP_CONTAIN: {

@@ -133,6 +133,7 @@ struct SortPlan {
     size_t target;         // records per coarse bucket
     size_t ncoarse;        // coarse buckets launched
     bool digits;           // counting pass of balanced digits with workgroup-local counters
+    bool two_level;        // digits mode through a coarse then a fine scatter (large indexes)
     size_t nchunks;        // digits mode: record chunks (one workgroup each)
     size_t chunk;          // digits mode: records per chunk
 };
@@ -148,6 +149,8 @@ struct SortWs {
     uint32_t *rank;        // capacity: rank of each record inside its fine bin
     uint64_t *scan_tmp;    // scan_scratch(max(nfine, sort_top_bins()))
     ulonglong2 *trec;      // capacity: (key, value) records grouped by fine bin
+    ulonglong2 *tmp;       // two-level: capacity records grouped by coarse digit
+    uint32_t *cmat;        // two-level: nchunks * 256 per-chunk coarse-digit counts
     uint32_t *cstart;      // ncoarse + 1: first fine bin of each coarse bucket
     uint32_t *overflow;    // ncoarse
     uint32_t *overflow_n;  // 1

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
                                                            const uint64_t *n_ptr,
                                                            uint64_t capacity, uint32_t D,
                                                            uint32_t chunk, const uint64_t *cdf,
-                                                           uint32_t *mat)
+                                                           uint32_t *mat, uint32_t *cmat,
+                                                           int sub_bits)
 {
     extern __shared__ uint32_t dyn[];           // D counters, then kTop slice CDF entries
     uint32_t *cnt = dyn, *cl = dyn + D;
@@ -158,6 +159,14 @@ __global__ __launch_bounds__(kBigBlock) void k_digit_count(const uint64_t *keys,
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < D; d += kBigBlock) mat[(size_t)blockIdx.x * D + d] = cnt[d];
+    if (cmat) {                                  // two-level: the chunk's coarse-digit counts
+        const uint32_t G = D >> sub_bits;
+        for (uint32_t g = threadIdx.x; g < G; g += kBigBlock) {
+            uint32_t sum = 0;
+            for (uint32_t j = 0; j < (1u << sub_bits); j++) sum += cnt[(g << sub_bits) + j];
+            cmat[(size_t)blockIdx.x * G + g] = sum;
+        }
+    }
 }
 
 // One thread per digit: its total over all chunks.
@@ -380,6 +389,157 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *sh)
         if (i < wv) before += sh[i];
     __syncthreads();
     return before + inc - v;
+}
+
+// ---- two-level scatter (large indexes): records go first to one of kCoarse coarse
+// digits (a digit's top kCoarseBits bits), then within each coarse digit to its fine
+// digits.  Both passes stage a tile of kTile records in LDS, grouped by (coarse or fine)
+// digit, and write every group as one run of consecutive 16-byte records, so each
+// workgroup store instruction covers whole lines; a chunk's next tile continues the same
+// runs.  (A one-pass scatter to 2^15 digits lands runs of a few records each, whose
+// partial lines double the bytes written.)
+constexpr int kCoarseBits = 8;
+constexpr int kCoarse = 1 << kCoarseBits;
+constexpr int kTile = 4 * kBigBlock;
+
+// One thread per coarse digit: per-chunk coarse counts -> each chunk's first slot of it.
+__global__ __launch_bounds__(kCoarse) void k_coarse_offsets(uint32_t *cmat, uint32_t nchunks,
+                                                            int sub_bits, const uint64_t *start)
+{
+    const uint32_t g = threadIdx.x;
+    uint32_t run = (uint32_t)start[(size_t)g << sub_bits];
+    for (uint32_t b = 0; b < nchunks; b++) {
+        const uint32_t v = cmat[(size_t)b * kCoarse + g];
+        cmat[(size_t)b * kCoarse + g] = run;
+        run += v;
+    }
+}
+
+// Stage up to kTile records (held four per thread in r, with group id gid[] and rank in
+// its group rk[]) grouped by group id in LDS, then write each group's run at run[group].
+// G groups (<= 256); cnt holds the tile's group counts on entry.
+template <int G>
+__device__ __forceinline__ void stage_and_write(const ulonglong2 (&r)[4], const uint32_t (&gid)[4],
+                                                const uint32_t (&rk)[4], int m, uint32_t *cnt,
+                                                uint32_t *lofs, uint32_t *run,
+                                                ulonglong2 *stage, uint8_t *sg, uint32_t *sh_scan,
+                                                ulonglong2 *out)
+{
+    const int t = threadIdx.x;
+    const uint32_t ex = block_excl_sum<kBigBlock>(t < G ? cnt[t] : 0u, sh_scan);
+    if (t < G) lofs[t] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int i = t + u * kBigBlock;
+        if (i < m) {
+            const uint32_t p = lofs[gid[u]] + rk[u];
+            stage[p] = r[u];
+            sg[p] = (uint8_t)gid[u];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int j = t + u * kBigBlock;
+        if (j < m) {
+            const uint32_t g = sg[j];
+            out[run[g] + ((uint32_t)j - lofs[g])] = stage[j];
+        }
+    }
+    __syncthreads();
+    if (t < G) {
+        run[t] += cnt[t];
+        cnt[t] = 0;
+    }
+    __syncthreads();
+}
+
+// Pass 1: one workgroup per chunk; coarse digit = digit >> sub_bits.
+template <typename V>
+__global__ __launch_bounds__(kBigBlock) void k_coarse_scatter(const uint64_t *keys, const V *vals,
+                                                              const uint64_t *n_ptr,
+                                                              uint64_t capacity, uint32_t D,
+                                                              int sub_bits, uint32_t chunk,
+                                                              const uint64_t *cdf,
+                                                              const uint32_t *coff,
+                                                              ulonglong2 *tmp)
+{
+    __shared__ uint32_t cl[kTop];
+    __shared__ ulonglong2 stage[kTile];
+    __shared__ uint8_t sg[kTile];
+    __shared__ uint32_t cnt[kCoarse], lofs[kCoarse], run[kCoarse];
+    __shared__ uint32_t sh_scan[kBigBlock / kWave];
+    const int t = threadIdx.x;
+    if (t < kCoarse) {
+        cnt[t] = 0;
+        run[t] = coff[(size_t)blockIdx.x * kCoarse + t];
+    }
+    DigitMap dm;
+    dm.init(cdf, cl, D);                        // (its barrier also orders the lines above)
+    uint64_t n = *n_ptr;
+    if (n > capacity) n = capacity;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    for (uint64_t t0 = c0; t0 < c1; t0 += kTile) {
+        const int m = (int)(c1 - t0 < (uint64_t)kTile ? c1 - t0 : (uint64_t)kTile);
+        ulonglong2 r[4];
+        uint32_t gid[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int i = t + u * kBigBlock;
+            if (i < m) {
+                const uint64_t key = keys[t0 + i];
+                r[u] = make_ulonglong2(key, (uint64_t)vals[t0 + i]);
+                gid[u] = dm(key) >> sub_bits;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (t + u * kBigBlock < m) rk[u] = atomicAdd(&cnt[gid[u]], 1u);
+        __syncthreads();
+        stage_and_write<kCoarse>(r, gid, rk, m, cnt, lofs, run, stage, sg, sh_scan, tmp);
+    }
+}
+
+// Pass 2: one workgroup per coarse digit g, over its range of the pass-1 output; fine
+// digit (g << sub_bits) + j goes to its final range at fofs.
+__global__ __launch_bounds__(kBigBlock) void k_fine_scatter(const ulonglong2 *tmp, uint32_t D,
+                                                            int sub_bits, const uint64_t *cdf,
+                                                            const uint64_t *fofs,
+                                                            ulonglong2 *trec)
+{
+    constexpr int kMaxSub = 1 << (kDigitBits - kCoarseBits);
+    __shared__ uint32_t cl[kTop];
+    __shared__ ulonglong2 stage[kTile];
+    __shared__ uint8_t sg[kTile];
+    __shared__ uint32_t cnt[kMaxSub], lofs[kMaxSub], run[kMaxSub];
+    __shared__ uint32_t sh_scan[kBigBlock / kWave];
+    const int t = threadIdx.x;
+    const uint32_t g = blockIdx.x, S = 1u << sub_bits;
+    if (t < kMaxSub) cnt[t] = 0;
+    if (t < (int)S) run[t] = (uint32_t)fofs[((size_t)g << sub_bits) + t];
+    DigitMap dm;
+    dm.init(cdf, cl, D);
+    const uint64_t b0 = fofs[(size_t)g << sub_bits], b1 = fofs[(size_t)(g + 1) << sub_bits];
+    for (uint64_t t0 = b0; t0 < b1; t0 += kTile) {
+        const int m = (int)(b1 - t0 < (uint64_t)kTile ? b1 - t0 : (uint64_t)kTile);
+        ulonglong2 r[4];
+        uint32_t gid[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int i = t + u * kBigBlock;
+            if (i < m) {
+                r[u] = tmp[t0 + i];
+                gid[u] = dm(r[u].x) & (S - 1);   // pass 1 put the record in digit group g
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (t + u * kBigBlock < m) rk[u] = atomicAdd(&cnt[gid[u]], 1u);
+        __syncthreads();
+        stage_and_write<kMaxSub>(r, gid, rk, m, cnt, lofs, run, stage, sg, sh_scan, trec);
+    }
 }
 
 // Digits mode: a coarse bucket is a run of whole digits holding more than kLo and at most
@@ -626,15 +786,28 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         // LDS sized to the digits: 80 KB at 2^14 digits, two workgroups per CU
         const size_t lds = ((size_t)D + kTop) * sizeof(uint32_t);
         if ((e = allow_digit_lds<V>()) != hipSuccess) return e;
+        const int sb = sp.two_level ? sp.Bf - kCoarseBits : 0;
         GD_LAUNCH(k_digit_count, dim3(nc), dim3(kBigBlock), lds, s, keys, n_ptr, capacity, D, ch,
-                  (const uint64_t *)w.cdf, w.hist);
+                  (const uint64_t *)w.cdf, w.hist, sp.two_level ? w.cmat : nullptr, sb);
         GD_LAUNCH(k_digit_totals, dim3(dg), dim3(kBlock), 0, s, (const uint32_t *)w.hist, nc, D,
                   w.tot);
         if ((e = exclusive_scan_u32(w.tot, w.fofs, D, w.scan_tmp, s)) != hipSuccess) return e;
-        GD_LAUNCH(k_digit_offsets, dim3(dg), dim3(kBlock), 0, s, w.hist, nc, D,
-                  (const uint64_t *)w.fofs);
-        GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), lds, s, keys, vals, n_ptr,
-                  capacity, D, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.hist, w.trec);
+        if (sp.two_level) {
+            GD_LAUNCH(k_coarse_offsets, dim3(1), dim3(kCoarse), 0, s, w.cmat, nc, sb,
+                      (const uint64_t *)w.fofs);
+            GD_LAUNCH(k_coarse_scatter<V>, dim3(nc), dim3(kBigBlock), 0, s, keys, vals, n_ptr,
+                      capacity, D, sb, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.cmat,
+                      w.tmp);
+            GD_LAUNCH(k_fine_scatter, dim3(kCoarse), dim3(kBigBlock), 0, s,
+                      (const ulonglong2 *)w.tmp, D, sb, (const uint64_t *)w.cdf,
+                      (const uint64_t *)w.fofs, w.trec);
+        } else {
+            GD_LAUNCH(k_digit_offsets, dim3(dg), dim3(kBlock), 0, s, w.hist, nc, D,
+                      (const uint64_t *)w.fofs);
+            GD_LAUNCH(k_digit_scatter<V>, dim3(nc), dim3(kBigBlock), lds, s, keys, vals, n_ptr,
+                      capacity, D, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.hist,
+                      w.trec);
+        }
     } else {
         if ((e = fill_u32(w.hist, 0, sp.nfine, s)) != hipSuccess) return e;
         const unsigned grid = 4096;
@@ -688,7 +861,11 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
         // within the largest bucket launch
         int Bd = 4;
         while (Bd < kDigitBits && (capacity >> Bd) > 512) Bd++;
-        if (Bd == kDigitBits && (capacity >> (kDigitBits - 1)) <= 6144) Bd = kDigitBits - 1;
+        // from 2^24 records: 2^15 digits through the two-level scatter (buckets of ~2.5K
+        // records at 100M, two bucket-sort workgroups per CU); below, one scatter pass
+        sp.two_level = capacity >= ((uint64_t)1 << 24);
+        if (!sp.two_level && Bd == kDigitBits && (capacity >> (kDigitBits - 1)) <= 6144)
+            Bd = kDigitBits - 1;
         sp.digits = true;
         sp.Bf = Bd;
         sp.nfine = (size_t)1 << Bd;
@@ -696,7 +873,7 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
         // as few as fill 256 CUs at once (two workgroups per CU up to 2^14 digits, one
         // above): the longer a chunk, the longer its run of records in each digit's range
         // (short scattered runs cost partial-line writes)
-        const uint64_t slots = Bd <= 14 ? 512 : 256;
+        const uint64_t slots = Bd <= 14 && !sp.two_level ? 512 : 256;
         uint64_t chunk = (capacity + slots - 1) / slots;
         chunk = (chunk + 4095) / 4096 * 4096;
         if (chunk < 32768) chunk = 32768;
@@ -709,6 +886,7 @@ SortPlan sort_plan(uint64_t expected_records, uint64_t capacity, int val_bytes)
     int Bf = 4;
     while (Bf < 26 && (expected_records >> Bf) > 2) Bf++;
     sp.digits = false;
+    sp.two_level = false;
     sp.nchunks = 0;
     sp.chunk = 0;
     sp.Bf = Bf;

@@ -203,6 +203,39 @@ def test_index_build_large_buckets(gpu):
     assert np.array_equal(u32(ix.vals).astype(np.uint64), ev)
 
 
+# index capacities from 2^24 records take the two-level scatter (a coarse pass by the top
+# 8 bits of the digit, then a fine pass inside each coarse digit); a large capacity over a
+# small reference reaches it with few records per digit, many empty chunks and digits
+TWO_LEVEL_CAPACITY = (1 << 24) + 12345
+
+
+@pytest.mark.parametrize("val_bits", [32, 64])
+def test_index_build_two_level_scatter(gpu, val_bits):
+    codes, offs = ragged_batch(11, [3_000_000, 1, 2_500_000, 0, 999_999])
+    codes[5000:405_000] = codes[1_000_000:1_400_000]   # a 400 kbp repeat: equal keys
+    for pattern, k, w in [("10", 21, 11), ("1", 15, 5)]:
+        ix = gpu.index_build(dev(gpu, codes, offs), pattern, k, w, val_bits=val_bits,
+                             capacity=TWO_LEVEL_CAPACITY)
+        ek, ev = oracle.index_build(codes, offs, pattern, k, w, val_bits=val_bits)
+        assert ix.n == ek.size
+        assert np.array_equal(u64(ix.keys), ek)
+        gv = u32(ix.vals).astype(np.uint64) if val_bits == 32 else u64(ix.vals)
+        assert np.array_equal(gv, ev)
+
+
+def test_index_build_two_level_long_runs(gpu):
+    # equal hashes by the thousand through the two-level scatter
+    rng = np.random.default_rng(19)
+    unit = rng.integers(0, 4, 7, dtype=np.uint8)
+    codes = np.tile(unit, 300_000)
+    codes[::997] = rng.integers(0, 4, codes[::997].size, dtype=np.uint8)
+    offs = np.array([0, codes.size], np.int64)
+    ix = gpu.index_build(dev(gpu, codes, offs), "1", 11, 5, capacity=TWO_LEVEL_CAPACITY)
+    ek, ev = oracle.index_build(codes, offs, "1", 11, 5)
+    assert np.array_equal(u64(ix.keys), ek)
+    assert np.array_equal(u32(ix.vals).astype(np.uint64), ev)
+
+
 def _seed_compare(gpu, ref, roffs, reads, offs, pattern, k, w, **kw):
     ix = gpu.index_build(dev(gpu, ref, roffs), pattern, k, w)
     ek, ev = oracle.index_build(ref, roffs, pattern, k, w)
