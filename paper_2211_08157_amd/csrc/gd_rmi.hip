@@ -83,39 +83,59 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
 {
     const RmiHeader &H = *Hp;      // read in place: per-lane segment indices would force a copy to scratch
     const uint32_t L = 1u << H.log2_leaves;
-    // A wave takes 63 new indices per step: lane t routes index s - 1 + t, so every lane
+    // A wave takes 63 new indices per group: lane t routes index s - 1 + t, so every lane
     // but the first finds its predecessor's leaf in the lane below (each key is routed
     // about once instead of twice).  Indices run to n inclusive (index n routes past the
-    // end, to L).
+    // end, to L).  A wave loads the keys of kGroups consecutive groups before routing
+    // them, so that several loads are in flight.
+    constexpr int kGroups = 4;
+    constexpr uint64_t kStep = (uint64_t)(kWave - 1) * kGroups;
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t wave = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) / kWave;
     const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
-    for (uint64_t s = wave * (kWave - 1); s <= n; s += waves * (kWave - 1)) {   // wave-uniform
-        const uint64_t i = s + lane - 1;                 // s - 1 for lane 0 (wraps at s = 0)
-        const bool key = !(lane == 0 && s == 0) && i < n;
-        uint32_t cur = 0;
-        if (key) {
-            const float x = key_x(keys[i]);
+    const float knot = H.t[lane & (kKnots - 1)];          // lane i < 32 holds knot i
+    for (uint64_t s0 = wave * kStep; s0 <= n; s0 += waves * kStep) {   // wave-uniform
+        uint64_t kvs[kGroups];
+#pragma unroll
+        for (int g = 0; g < kGroups; g++) {
+            const uint64_t s = s0 + (uint64_t)g * (kWave - 1), i = s + lane - 1;
+            kvs[g] = !(lane == 0 && s == 0) && i < n ? keys[i] : 0;
+        }
+#pragma unroll
+        for (int g = 0; g < kGroups; g++) {
+            const uint64_t s = s0 + (uint64_t)g * (kWave - 1);
+            if (s > n) break;                            // wave-uniform
+            const uint64_t i = s + lane - 1;             // s - 1 for lane 0 (wraps at s = 0)
+            const bool key = !(lane == 0 && s == 0) && i < n;
+            const uint64_t kv = kvs[g];
+            uint32_t cur = 0;
             if (H.kind == 0) {
-                cur = route(H, keys[i]);
+                cur = route(H, kv);
             } else {
                 // the keys are sorted, so a wave's keys usually share the root's segment:
-                // then it is counted once for the wave (route() gives the same leaves)
+                // it is then the number of knots below the first and the last key, which
+                // 32 lanes compare at once (route() gives the same leaves)
+                const float x = key_x(kv);
                 const uint64_t m = __ballot(key);
-                const int first = __ffsll((unsigned long long)m) - 1;
-                const int last = 63 - __clzll((long long)m);
-                const float x0 = __shfl(x, first), x1 = __shfl(x, last);
-                uint32_t j = root_segment(H, x0);
-                if (j != root_segment(H, x1)) j = root_segment(H, x);   // wave-uniform test
+                uint32_t j = 0;
+                if (m != 0) {
+                    const int first = __ffsll((unsigned long long)m) - 1;
+                    const int last = 63 - __clzll((long long)m);
+                    const float x0 = __shfl(x, first), x1 = __shfl(x, last);
+                    j = (uint32_t)__popcll(__ballot(lane < kKnots && knot < x0));
+                    const uint32_t j1 =
+                        (uint32_t)__popcll(__ballot(lane < kKnots && knot < x1));
+                    if (j != j1) j = root_segment(H, x);  // wave-uniform test
+                }
                 cur = leaf_of(root_on_segment(H, j, x), L);
             }
-        } else if (!(lane == 0 && s == 0)) {
-            cur = L;                                     // index n (and past it)
+            if (!key) cur = (lane == 0 && s == 0) ? 0u : L;   // index n and past it: L
+            const uint32_t prv = __shfl_up(cur, 1);
+            if (lane == 0 || i > n) continue;
+            const uint32_t from = i > 0 ? prv + 1 : 0;
+            for (uint32_t l = from; l <= cur && l < L; l++)
+                atomicMin(&leaves[l].base, (uint32_t)i);
         }
-        const uint32_t prv = __shfl_up(cur, 1);
-        if (lane == 0 || i > n) continue;
-        const uint32_t from = i > 0 ? prv + 1 : 0;
-        for (uint32_t l = from; l <= cur && l < L; l++) atomicMin(&leaves[l].base, (uint32_t)i);
     }
 }
 
