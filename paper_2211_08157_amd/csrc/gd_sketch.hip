@@ -884,7 +884,8 @@ template <int W, int HK>
 __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, uint64_t np,
                                             uint64_t n_tiles, uint64_t *ex, uint64_t *sh_scan,
                                             uint64_t *sh_misc, const SeqCache &C,
-                                            const uint8_t *ones)
+                                            const uint8_t *ones, uint32_t w0, uint32_t w1,
+                                            uint32_t w2)
 {
     const int t = threadIdx.x;
     const int H = A.H, T = A.T, w = W > 0 ? W : A.w, k = A.k;
@@ -906,8 +907,6 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         uint64_t seq_beg = C.at(seq), seq_end = C.at(seq + 1);
         while ((uint64_t)jc >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
         seq0 = seq; beg0 = seq_beg; end0 = seq_end;
-        const size_t wi = (size_t)jc / 16;
-        const uint32_t w0 = A.psw[wi], w1 = A.psw[wi + 1], w2 = A.psw[wi + 2];
         // an N within k + w - 1 positions of the chunk needs the run-aware masks below
         const uint64_t L = (uint64_t)(k + w - 1);
         bool n_near = false;
@@ -1085,6 +1084,77 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         if (staged) compact();
     }
 
+    // The records of this thread's selected positions: their values (and, when the tile
+    // is not staged, their keys) go out in position order.  A staged tile writes values to
+    // the exchange array only, so it needs no tile base and runs before the look-back
+    // finishes.
+    uint32_t *sv32 = (uint32_t *)(ex + total);          // staged values, after the keys
+    uint64_t *sv64 = ex + total;
+    auto records = [&](uint64_t tile_base) {
+        // The original coordinate of patterned position li of a sequence is
+        // (li / x) * p + phase(li % x); the division is done once per chunk (or per
+        // sequence start) and then advanced by small offsets with a reciprocal multiply.
+        uint32_t seq = seq0;
+        uint64_t seq_beg = beg0, seq_end = end0;
+        uint32_t a = seq_shift(A.shift, A.uniform, seq);
+        if (a >= A.P.p) a = 0;
+        uint32_t front = kept_front(A.P, a);
+        // original offset of the sequence (global positions only), reloaded per sequence
+        uint64_t obase = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] : 0;
+        uint64_t per0;
+        uint32_t r0;
+        div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
+        uint64_t jb = (uint64_t)jc;                // position whose rank is (per0, r0)
+        const uint32_t magic = (65536u + A.P.x - 1) / A.P.x;
+        uint64_t idx = excl;                       // record index within the tile
+        uint32_t bits = sel;
+        while (bits) {
+            const int u = __ffs(bits) - 1;
+            bits &= bits - 1;
+            const uint64_t j = (uint64_t)jc + u;
+            if (j >= seq_end) {
+                while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
+                a = seq_shift(A.shift, A.uniform, seq);
+                if (a >= A.P.p) a = 0;
+                front = kept_front(A.P, a);
+                if (A.val_mode == VAL_GLOBAL32) obase = A.offsets[seq];
+                per0 = 0;
+                r0 = 0;
+                jb = seq_beg;
+            }
+            const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
+            const uint32_t q = (rr * magic) >> 16;
+            // offset in the period of kept phase r under shift a (ones[] in LDS)
+            uint32_t oi = rr - q * A.P.x + front;
+            if (oi >= A.P.x) oi -= A.P.x;
+            uint32_t ph = ones[oi] + a;
+            if (ph >= A.P.p) ph -= A.P.p;
+            const uint64_t local = (per0 + q) * A.P.p + ph;
+            const uint32_t strand = (smask >> u) & 1u;
+            if (A.val_mode == VAL_SEQ64) {
+                if (local >= (1ull << 31)) set_status(A.status, 2u);
+                const uint64_t v = ((uint64_t)seq << 32) | (local << 1) | strand;
+                if (staged) {
+                    sv64[idx] = v;
+                } else if (tile_base + idx < A.capacity) {
+                    A.keys[tile_base + idx] = ex[u * kBlock + t];
+                    ((uint64_t *)A.vals)[tile_base + idx] = v;
+                }
+            } else {
+                const uint64_t pos = obase + local;
+                if (pos >= (1ull << 31)) set_status(A.status, 2u);
+                const uint32_t v = (uint32_t)((pos << 1) | strand);
+                if (staged) {
+                    sv32[idx] = v;
+                } else if (tile_base + idx < A.capacity) {
+                    A.keys[tile_base + idx] = ex[u * kBlock + t];
+                    ((uint32_t *)A.vals)[tile_base + idx] = v;
+                }
+            }
+            idx++;
+        }
+    };
+
     // ---- stage 3: position-ordered compaction across tiles (decoupled look-back)
     // Wave 0 publishes this tile's aggregate, then looks back over 64 predecessors per
     // step: it adds every aggregate up to the nearest tile that already carries its
@@ -1128,6 +1198,8 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
             }
         }
     }
+    // waves 1-3 fill in their staged values while wave 0 looks back
+    if (staged && owner && (uint64_t)jc <= np && sel != 0) records(0);
     // Records leave the tile in position order.  When they fit in the exchange array
     // (12 or 16 bytes each, which every tile does unless w is tiny or the sequence is of
     // low complexity), the keys were compacted there straight from registers, the values
@@ -1142,8 +1214,6 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
     __syncthreads();
     const uint64_t tile_base = sh_misc[0];
     const uint64_t base = tile_base + excl;
-    uint32_t *sv32 = (uint32_t *)(ex + total);          // staged values, after the keys
-    uint64_t *sv64 = ex + total;
 
     if (owner && (uint64_t)jc <= np) {
         // per-sequence record offsets of the sequences that start inside this chunk
@@ -1157,70 +1227,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 s++;
             }
         }
-        if (sel != 0) {
-            // The original coordinate of patterned position li of a sequence is
-            // (li / x) * p + phase(li % x); the division is done once per chunk (or per
-            // sequence start) and then advanced by small offsets with a reciprocal multiply.
-            uint32_t seq = seq0;
-            uint64_t seq_beg = beg0, seq_end = end0;
-            uint32_t a = seq_shift(A.shift, A.uniform, seq);
-            if (a >= A.P.p) a = 0;
-            uint32_t front = kept_front(A.P, a);
-            // original offset of the sequence (global positions only), reloaded per sequence
-            uint64_t obase = A.val_mode == VAL_GLOBAL32 ? A.offsets[seq] : 0;
-            uint64_t per0;
-            uint32_t r0;
-            div_x((uint64_t)jc - seq_beg, A.P.x, A.inv_x, &per0, &r0);
-            uint64_t jb = (uint64_t)jc;                // position whose rank is (per0, r0)
-            const uint32_t magic = (65536u + A.P.x - 1) / A.P.x;
-            uint64_t idx = excl;                       // record index within the tile
-            uint32_t bits = sel;
-            while (bits) {
-                const int u = __ffs(bits) - 1;
-                bits &= bits - 1;
-                const uint64_t j = (uint64_t)jc + u;
-                if (j >= seq_end) {
-                    while (j >= seq_end) { seq++; seq_beg = seq_end; seq_end = C.at(seq + 1); }
-                    a = seq_shift(A.shift, A.uniform, seq);
-                    if (a >= A.P.p) a = 0;
-                    front = kept_front(A.P, a);
-                    if (A.val_mode == VAL_GLOBAL32) obase = A.offsets[seq];
-                    per0 = 0;
-                    r0 = 0;
-                    jb = seq_beg;
-                }
-                const uint32_t rr = r0 + (uint32_t)(j - jb);          // < x + 16
-                const uint32_t q = (rr * magic) >> 16;
-                // offset in the period of kept phase r under shift a (ones[] in LDS)
-                uint32_t oi = rr - q * A.P.x + front;
-                if (oi >= A.P.x) oi -= A.P.x;
-                uint32_t ph = ones[oi] + a;
-                if (ph >= A.P.p) ph -= A.P.p;
-                const uint64_t local = (per0 + q) * A.P.p + ph;
-                const uint32_t strand = (smask >> u) & 1u;
-                if (A.val_mode == VAL_SEQ64) {
-                    if (local >= (1ull << 31)) set_status(A.status, 2u);
-                    const uint64_t v = ((uint64_t)seq << 32) | (local << 1) | strand;
-                    if (staged) {
-                        sv64[idx] = v;
-                    } else if (tile_base + idx < A.capacity) {
-                        A.keys[tile_base + idx] = ex[u * kBlock + t];
-                        ((uint64_t *)A.vals)[tile_base + idx] = v;
-                    }
-                } else {
-                    const uint64_t pos = obase + local;
-                    if (pos >= (1ull << 31)) set_status(A.status, 2u);
-                    const uint32_t v = (uint32_t)((pos << 1) | strand);
-                    if (staged) {
-                        sv32[idx] = v;
-                    } else if (tile_base + idx < A.capacity) {
-                        A.keys[tile_base + idx] = ex[u * kBlock + t];
-                        ((uint32_t *)A.vals)[tile_base + idx] = v;
-                    }
-                }
-                idx++;
-            }
-        }
+        if (!staged && sel != 0) records(tile_base);
     }
     if (staged) {
         __syncthreads();
@@ -1260,8 +1267,15 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     __syncthreads();
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
+    // the chunk's three stream words (the 16 positions and the 32 after them), loaded
+    // before the sequence cache so that the two loads' latencies overlap (unconditionally,
+    // from word 0 for chunks outside the stream, whose words are never used: a load under
+    // a branch is waited for at the branch's end)
+    const int64_t jc = (int64_t)(tile * (uint64_t)A.T) - A.H + 16 * (int64_t)threadIdx.x;
+    const size_t wi = jc >= 0 && (uint64_t)jc < np ? (size_t)jc / 16 : 0;
+    const uint32_t w0 = A.psw[wi], w1 = A.psw[wi + 1], w2 = A.psw[wi + 2];
     const SeqCache C = seq_cache(A.pofs, A.n_seq, A.lohi, tile, sh_pofs);
-    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, sh_misc, C, sh_ones);
+    sketch_tile<W, HK>(A, tile, np, n_tiles, ex, sh_scan, sh_misc, C, sh_ones, w0, w1, w2);
 }
 
 }  // namespace
