@@ -613,17 +613,21 @@ def copy_gbps(torch, nbytes=1 << 30, reps=5):
 
 
 def gather_rate(torch, n_keys, n_q, reps=5):
-    """Random 8-byte gathers per second into an array of n_keys (torch's index kernel):
-    the random-line reference for the lookups."""
+    """Random 8-byte gathers per second into an array of n_keys, by the library's gather
+    probe (independent loads, four in flight per lane): the random-request reference for
+    the lookups.  The probe's output is checked against torch's indexing."""
+    import paper_2211_08157_amd as gd
     keys = torch.arange(n_keys, dtype=torch.int64, device="cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(404)
     idx = torch.randint(0, n_keys, (n_q,), device="cuda", generator=g)
-    out = keys[idx]
+    out, st = gd.random_gather(keys, idx)
+    if not torch.equal(out, idx) or int(st.item()) != 0:
+        raise RuntimeError("random-gather probe returned wrong values")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        out = keys[idx]
+        gd.random_gather(keys, idx)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps

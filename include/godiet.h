@@ -366,6 +366,16 @@ godiet_status godiet_rmi_train(const godiet_index *index, int32_t root_kind, uin
 godiet_status godiet_rmi_stats(const godiet_index *index, const uint64_t *q, uint64_t n_q,
                                uint64_t *stats, hipStream_t stream);
 
+/* Random-gather probe, a measurement aid outside the method: the rate at which the GPU
+ * serves independent random 8-byte loads sets the roofline of the lookups (each lookup is
+ * a short chain of such loads).  out[i] = src[idx[i]] for i < n_idx (device arrays; every
+ * idx[i] < n_src is checked in the kernel and an out-of-range index writes 0 and sets
+ * GODIET_ST_RANGE in the device status word, which the call clears first).  Each lane
+ * keeps four independent loads in flight. */
+godiet_status godiet_random_gather(const uint64_t *src, uint64_t n_src, const uint64_t *idx,
+                                   uint64_t n_idx, uint64_t *out, uint32_t *status,
+                                   hipStream_t stream);
+
 /* Kernel tracing, a profiling aid outside the method.  While enabled, every kernel launch
  * of the library is bracketed by HIP events recorded on the launch's stream.  After the
  * caller has synchronised, godiet_trace_dump writes one line "kernel launches total_ms"

@@ -11,16 +11,16 @@ fallback.
 """
 from .store import save_index, load_index
 from .api import (GodietError, DeviceSeqs, DeviceIndex, pack, pack_n, to_device,
-                  to_device_ascii, sparsify, sketch, index_build, seed, rmi_train, rmi_stats, lookup,
-                  contain, lib, lib_path, workspace_size, kept_bound, trace_enable, trace_dump,
-                  trace_filter, vote, winners_rows, table_build, seed_match, edit_distance,
-                  accepted_pairs, FIG4_ALGORITHMS, STATUS_CAPACITY,
+                  to_device_ascii, sparsify, sketch, index_build, seed, rmi_train, rmi_stats,
+                  lookup, random_gather, contain, lib, lib_path, workspace_size, kept_bound,
+                  trace_enable, trace_dump, trace_filter, vote, winners_rows, table_build,
+                  seed_match, edit_distance, accepted_pairs, FIG4_ALGORITHMS, STATUS_CAPACITY,
                   STATUS_RANGE, STATUS_SHIFT)
 
 __all__ = ["GodietError", "DeviceSeqs", "DeviceIndex", "pack", "pack_n", "to_device",
-           "to_device_ascii", "sparsify", "sketch", "index_build", "seed", "rmi_train", "rmi_stats",
-           "lookup", "contain", "lib", "lib_path", "workspace_size", "kept_bound",
-           "trace_enable", "trace_dump", "trace_filter", "vote", "winners_rows",
-           "table_build", "save_index", "load_index", "seed_match", "edit_distance",
-           "accepted_pairs", "FIG4_ALGORITHMS", "STATUS_CAPACITY", "STATUS_RANGE",
-           "STATUS_SHIFT"]
+           "to_device_ascii", "sparsify", "sketch", "index_build", "seed", "rmi_train",
+           "rmi_stats", "lookup", "random_gather", "contain", "lib", "lib_path",
+           "workspace_size", "kept_bound", "trace_enable", "trace_dump", "trace_filter", "vote",
+           "winners_rows", "table_build", "save_index", "load_index", "seed_match",
+           "edit_distance", "accepted_pairs", "FIG4_ALGORITHMS", "STATUS_CAPACITY",
+           "STATUS_RANGE", "STATUS_SHIFT"]

@@ -130,6 +130,8 @@ def lib():
         L.godiet_rmi_stats.restype = i32
         L.godiet_lookup.argtypes = [S(Index), P, u64, P, P, P]
         L.godiet_lookup.restype = i32
+        L.godiet_random_gather.argtypes = [P, u64, P, u64, P, P, P]
+        L.godiet_random_gather.restype = i32
         L.godiet_rmi_size.argtypes = [u32]
         L.godiet_rmi_size.restype = sz
         L.godiet_rmi_train.argtypes = [S(Index), i32, u32, P, sz, P]
@@ -415,6 +417,17 @@ def lookup(index, queries):
     _check(lib().godiet_lookup(ctypes.byref(ix), _ptr(queries), n, _ptr(lb), _ptr(occ),
                                _stream()), "godiet_lookup")
     return lb[:n], occ[:n]
+
+
+def random_gather(src, idx):
+    """out[i] = src[idx[i]] through the library's random-gather probe (int64 tensors);
+    returns (out, status tensor)."""
+    torch = _torch()
+    out = _empty(idx.numel(), torch.int64)
+    st = _empty(1, torch.int32)
+    _check(lib().godiet_random_gather(_ptr(src), src.numel(), _ptr(idx), idx.numel(), _ptr(out),
+                                      _ptr(st), _stream()), "godiet_random_gather")
+    return out[:idx.numel()], st
 
 
 RMI_STAT_WORDS = 20

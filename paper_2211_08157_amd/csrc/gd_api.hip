@@ -678,6 +678,15 @@ godiet_status godiet_rmi_stats(const godiet_index *index, const uint64_t *q, uin
     return GODIET_OK;
 }
 
+godiet_status godiet_random_gather(const uint64_t *src, uint64_t n_src, const uint64_t *idx,
+                                   uint64_t n_idx, uint64_t *out, uint32_t *status,
+                                   hipStream_t stream)
+{
+    if (!status || (n_idx > 0 && (!src || !idx || !out))) return GODIET_E_INVAL;
+    GD_TRY(launch_random_gather(src, n_src, idx, n_idx, out, status, stream));
+    return GODIET_OK;
+}
+
 godiet_status godiet_lookup(const godiet_index *index, const uint64_t *q, uint64_t n_q,
                             uint32_t *lb, uint32_t *occ, hipStream_t stream)
 {

@@ -173,6 +173,8 @@ hipError_t launch_vote(const VoteArgs &A, const uint4 *anchors, const uint64_t *
 // ---- lookups, alignment, anchors (gd_seed.hip) ----
 // lb/occ of min(*n_q, q_cap) queries (n_q may be null: q_cap queries); rmi nullable.
 // table (nullable, seeding only): hash-table lookups, whose lb is 0 for absent keys
+hipError_t launch_random_gather(const uint64_t *src, uint64_t n_src, const uint64_t *idx,
+                                uint64_t n_idx, uint64_t *out, uint32_t *status, hipStream_t s);
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,
                          const void *rmi, size_t rmi_bytes, const void *table,

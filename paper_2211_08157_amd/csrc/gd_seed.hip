@@ -162,6 +162,34 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t *ikeys, uint64
     }
 }
 
+// Random-gather probe: four independent loads per lane per step.
+__global__ __launch_bounds__(kBlock) void k_random_gather(const uint64_t *src, uint64_t n_src,
+                                                          const uint64_t *idx, uint64_t n_idx,
+                                                          uint64_t *out, uint32_t *status)
+{
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i0 = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i0 < n_idx; i0 += stride * U) {
+        uint64_t v[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t i = i0 + (uint64_t)u * stride;
+            const uint64_t j = i < n_idx ? idx[i] : 0;
+            ok[u] = i < n_idx && j < n_src;
+            v[u] = ok[u] ? src[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t i = i0 + (uint64_t)u * stride;
+            if (i < n_idx) {
+                out[i] = v[u];
+                if (!ok[u]) set_status(status, 2u);
+            }
+        }
+    }
+}
+
 constexpr int kReadsPerBlock = kBlock / kWave;
 constexpr int kHugeBlock = 1024;            // threads per read on the huge-read path
 constexpr uint64_t kHugeRecords = 16384;    // reads with more records take that path
@@ -528,6 +556,18 @@ __global__ __launch_bounds__(kHugeBlock) void k_expand_huge(AlignArgs A, const u
 }
 
 }  // namespace
+
+hipError_t launch_random_gather(const uint64_t *src, uint64_t n_src, const uint64_t *idx,
+                                uint64_t n_idx, uint64_t *out, uint32_t *status, hipStream_t s)
+{
+    hipError_t e = fill_u32(status, 0, 1, s);
+    if (e != hipSuccess || n_idx == 0) return e;
+    uint64_t blocks = (n_idx + 4 * kBlock - 1) / (4 * kBlock);
+    if (blocks > 65536) blocks = 65536;
+    GD_LAUNCH(k_random_gather, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, n_src, idx, n_idx,
+              out, status);
+    return hipGetLastError();
+}
 
 hipError_t launch_lookup(const uint64_t *ikeys, uint64_t in, const uint64_t *q,
                          const uint64_t *n_q, uint64_t q_cap, uint32_t *lb, uint32_t *occ,

@@ -104,6 +104,15 @@ def test_host_rejects_bad_arguments_before_launch():
                          dummy, None) == E_INVAL
 
 
+def test_random_gather_host_checks():
+    from paper_2211_08157_amd.api import E_INVAL
+    L = _lib()
+    dummy = ctypes.c_void_p(0x3000)
+    assert L.godiet_random_gather(dummy, 10, dummy, 5, dummy, None, None) == E_INVAL
+    assert L.godiet_random_gather(None, 10, dummy, 5, dummy, dummy, None) == E_INVAL
+    assert L.godiet_random_gather(dummy, 10, dummy, 5, None, dummy, None) == E_INVAL
+
+
 def test_status_strings():
     L = _lib()
     for code in (0, -1, -2, -3, -4, -5, 7):

@@ -176,3 +176,19 @@ def test_rmi_stats_account_for_every_query(gpu, ref_index):
     lb, occ = gpu.lookup(m, present)
     elb, eocc = oracle.lookup(ek, ek[::7])
     assert np.array_equal(u32(lb).astype(np.uint64), elb)
+
+
+def test_random_gather_probe(gpu):
+    # the probe behind the lookups' random-request roofline: out[i] = src[idx[i]], with an
+    # out-of-range index reported in the status word (and 0 written)
+    import torch
+    src = torch.arange(7, 7 + 100_003, dtype=torch.int64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    for n in (0, 1, 999, 300_001):
+        idx = torch.randint(0, src.numel(), (n,), device="cuda", generator=g)
+        out, st = gpu.random_gather(src, idx)
+        assert torch.equal(out, src[idx]) and int(st.item()) == 0
+    idx = torch.tensor([0, 100_003, 5, 1 << 40], dtype=torch.int64, device="cuda")
+    out, st = gpu.random_gather(src, idx)
+    assert out.cpu().tolist() == [7, 0, 12, 0] and int(st.item()) == gpu.STATUS_RANGE
