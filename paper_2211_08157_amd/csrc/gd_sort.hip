@@ -106,9 +106,10 @@ __global__ __launch_bounds__(kBigBlock) void k_top_hist(const uint64_t *keys, co
         if (h[d]) atomicAdd(&hist[d], h[d]);
 }
 
-// Key -> digit, monotone in the key.  The kTop + 1 cumulative slice counts are the first
-// kTop in LDS and the total N in a register; a key's approximate rank is its slice's start plus the slice's count times the
-// key's position inside the slice (its next 32 bits), and the digit is rank * D / N.
+// Key -> digit, monotone in the key.  Of the kTop + 1 cumulative slice counts the first
+// kTop are in LDS and the total N in a register; a key's approximate rank is its slice's
+// start plus the slice's count times the key's position inside the slice (its next 32
+// bits), and the digit is rank * D / N.
 struct DigitMap {
     const uint32_t *C;                   // the first kTop CDF entries (in LDS)
     uint32_t total;                      // the last one, N
@@ -400,7 +401,8 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *sh)
 // partial lines double the bytes written.)
 constexpr int kCoarseBits = 8;
 constexpr int kCoarse = 1 << kCoarseBits;
-constexpr int kTile = 4 * kBigBlock;
+constexpr int kPerThread = 8;               // records per thread and step (158 KB of LDS)
+constexpr int kTile = kPerThread * kBigBlock;
 
 // One thread per coarse digit: per-chunk coarse counts -> each chunk's first slot of it.
 __global__ __launch_bounds__(kCoarse) void k_coarse_offsets(uint32_t *cmat, uint32_t nchunks,
@@ -415,13 +417,14 @@ __global__ __launch_bounds__(kCoarse) void k_coarse_offsets(uint32_t *cmat, uint
     }
 }
 
-// Stage up to kTile records (held four per thread in r, with group id gid[] and rank in
-// its group rk[]) grouped by group id in LDS, then write each group's run at run[group].
+// Stage up to kTile records (held kPerThread per thread in r, with group id gid[] and rank
+// in its group rk[]) grouped by group id in LDS, then write each group's run at run[group].
 // G groups (<= 256); cnt holds the tile's group counts on entry.
 template <int G>
-__device__ __forceinline__ void stage_and_write(const ulonglong2 (&r)[4], const uint32_t (&gid)[4],
-                                                const uint32_t (&rk)[4], int m, uint32_t *cnt,
-                                                uint32_t *lofs, uint32_t *run,
+__device__ __forceinline__ void stage_and_write(const ulonglong2 (&r)[kPerThread],
+                                                const uint32_t (&gid)[kPerThread],
+                                                const uint32_t (&rk)[kPerThread], int m,
+                                                uint32_t *cnt, uint32_t *lofs, uint32_t *run,
                                                 ulonglong2 *stage, uint8_t *sg, uint32_t *sh_scan,
                                                 ulonglong2 *out)
 {
@@ -430,7 +433,7 @@ __device__ __forceinline__ void stage_and_write(const ulonglong2 (&r)[4], const 
     if (t < G) lofs[t] = ex;
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < kPerThread; u++) {
         const int i = t + u * kBigBlock;
         if (i < m) {
             const uint32_t p = lofs[gid[u]] + rk[u];
@@ -440,7 +443,7 @@ __device__ __forceinline__ void stage_and_write(const ulonglong2 (&r)[4], const 
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < kPerThread; u++) {
         const int j = t + u * kBigBlock;
         if (j < m) {
             const uint32_t g = sg[j];
@@ -483,10 +486,10 @@ __global__ __launch_bounds__(kBigBlock) void k_coarse_scatter(const uint64_t *ke
     const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     for (uint64_t t0 = c0; t0 < c1; t0 += kTile) {
         const int m = (int)(c1 - t0 < (uint64_t)kTile ? c1 - t0 : (uint64_t)kTile);
-        ulonglong2 r[4];
-        uint32_t gid[4], rk[4];
+        ulonglong2 r[kPerThread];
+        uint32_t gid[kPerThread], rk[kPerThread];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < kPerThread; u++) {
             const int i = t + u * kBigBlock;
             if (i < m) {
                 const uint64_t key = keys[t0 + i];
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(kBigBlock) void k_coarse_scatter(const uint64_t *ke
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < kPerThread; u++)
             if (t + u * kBigBlock < m) rk[u] = atomicAdd(&cnt[gid[u]], 1u);
         __syncthreads();
         stage_and_write<kCoarse>(r, gid, rk, m, cnt, lofs, run, stage, sg, sh_scan, tmp);
@@ -524,10 +527,10 @@ __global__ __launch_bounds__(kBigBlock) void k_fine_scatter(const ulonglong2 *tm
     const uint64_t b0 = fofs[(size_t)g << sub_bits], b1 = fofs[(size_t)(g + 1) << sub_bits];
     for (uint64_t t0 = b0; t0 < b1; t0 += kTile) {
         const int m = (int)(b1 - t0 < (uint64_t)kTile ? b1 - t0 : (uint64_t)kTile);
-        ulonglong2 r[4];
-        uint32_t gid[4], rk[4];
+        ulonglong2 r[kPerThread];
+        uint32_t gid[kPerThread], rk[kPerThread];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < kPerThread; u++) {
             const int i = t + u * kBigBlock;
             if (i < m) {
                 r[u] = tmp[t0 + i];
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(kBigBlock) void k_fine_scatter(const ulonglong2 *tm
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < kPerThread; u++)
             if (t + u * kBigBlock < m) rk[u] = atomicAdd(&cnt[gid[u]], 1u);
         __syncthreads();
         stage_and_write<kMaxSub>(r, gid, rk, m, cnt, lofs, run, stage, sg, sh_scan, trec);
@@ -545,11 +548,12 @@ __global__ __launch_bounds__(kBigBlock) void k_fine_scatter(const ulonglong2 *tm
 // Digits mode: a coarse bucket is a run of whole digits holding more than kLo and at most
 // kCap records (three launches cover the sizes, with workgroups whose LDS and thread
 // count fit them).  Its records are binned in LDS by their key's offset from the
-// bucket's smallest key, scaled to NS bins (about two per record; monotone in the key),
+// bucket's smallest key, scaled to NS <= kBins bins (about two per record, or fewer when
+// kBins caps them so that more workgroups share a CU; monotone in the key),
 // the bins are scanned and filled from registers, and every record is then placed by its
 // rank inside its bin, as in k_bucket_sort.  A bucket holding a long bin (many equal
 // hashes) is bitonic-sorted; one beyond the largest capacity is listed for the fallback.
-template <typename V, int kCap, int kLo, int NT>
+template <typename V, int kCap, int kLo, int NT, int kBins = kCap>
 __global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec,
                                                           const uint64_t *fofs,
                                                           const uint32_t *cstart,
@@ -557,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec
                                                           uint32_t *overflow,
                                                           uint32_t *overflow_n, int last)
 {
-    constexpr int kSub = kCap;                  // bins
+    constexpr int kSub = kBins;                 // bins
     constexpr int kPer = kCap / NT;
     __shared__ uint64_t K[kCap];
     __shared__ V Vv[kCap];
@@ -824,6 +828,8 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
               (uint64_t)sp.ncoarse + 1);
     if (sp.digits) {
         // buckets by size: up to a quarter, a half and the whole of the largest capacity
+        // (the half-size launch with a quarter as many bins: 53 KB of LDS, three
+        // workgroups per CU, for the ~2.5K-record buckets of the two-level sort)
         constexpr int C = DCap<V>::value;
         const dim3 g((unsigned)sp.ncoarse);
         const ulonglong2 *tr = w.trec;
@@ -831,7 +837,7 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         const uint32_t *cs = w.cstart;
         GD_LAUNCH((k_digit_bucket_sort<V, C / 4, 0, kBlock>), g, dim3(kBlock), 0, s, tr, fo, cs,
                   keys, vals, w.overflow, w.overflow_n, 0);
-        GD_LAUNCH((k_digit_bucket_sort<V, C / 2, C / 4, 2 * kBlock>), g, dim3(2 * kBlock), 0, s,
+        GD_LAUNCH((k_digit_bucket_sort<V, C / 2, C / 4, 2 * kBlock, C / 8>), g, dim3(2 * kBlock), 0, s,
                   tr, fo, cs, keys, vals, w.overflow, w.overflow_n, 0);
         GD_LAUNCH((k_digit_bucket_sort<V, C, C / 2, kBigBlock>), g, dim3(kBigBlock), 0, s, tr, fo,
                   cs, keys, vals, w.overflow, w.overflow_n, 1);
