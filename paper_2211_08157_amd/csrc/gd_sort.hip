@@ -90,14 +90,17 @@ constexpr int kTop = 1 << kTopBits;
 // added globally).  The digit map only needs the key distribution's shape: any counts give
 // a monotone map (so a correct sort), a sample of the keys a balanced one.
 __global__ __launch_bounds__(kBigBlock) void k_top_hist(const uint64_t *keys, const uint64_t *n_ptr,
-                                                        uint64_t capacity, uint32_t stride,
-                                                        uint32_t *hist)
+                                                        uint64_t capacity, uint32_t *hist)
 {
     __shared__ uint32_t h[kTop];
     for (uint32_t d = threadIdx.x; d < (uint32_t)kTop; d += kBigBlock) h[d] = 0;
     __syncthreads();
     uint64_t n = *n_ptr;
     if (n > capacity) n = capacity;
+    // every stride-th key, stride (a power of two up to 64) keeping at least 256 sampled
+    // keys per slice on average: a strided sample touches only every (stride / 8)-th line
+    uint32_t stride = 1;
+    while (stride < 64 && n / (2ull * stride) >= (uint64_t)kTop * 256) stride <<= 1;
     for (uint64_t i = (blockIdx.x * (uint64_t)kBigBlock + threadIdx.x) * stride; i < n;
          i += (uint64_t)gridDim.x * kBigBlock * stride)
         atomicAdd(&h[keys[i] >> (64 - kTopBits)], 1u);
@@ -782,10 +785,7 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         const uint32_t ch = (uint32_t)sp.chunk;
         const unsigned dg = (D + kBlock - 1) / kBlock;
         if ((e = fill_u32(w.top, 0, kTop, s)) != hipSuccess) return e;
-        // one key in 8 once there are about 64 per slice (the sample still holds ~8 each)
-        const uint32_t stride = capacity >= ((uint64_t)kTop << 6) ? 8u : 1u;
-        GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, stride,
-                  w.top);
+        GD_LAUNCH(k_top_hist, dim3(256), dim3(kBigBlock), 0, s, keys, n_ptr, capacity, w.top);
         if ((e = exclusive_scan_u32(w.top, w.cdf, kTop, w.scan_tmp, s)) != hipSuccess) return e;
         // LDS sized to the digits: 80 KB at 2^14 digits, two workgroups per CU
         const size_t lds = ((size_t)D + kTop) * sizeof(uint32_t);
