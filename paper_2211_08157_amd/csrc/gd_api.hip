@@ -139,7 +139,8 @@ void plan_index_ws(Bump &b, const godiet_seqs *ref, const Pattern &P, int w, uin
     o->so.cmat = o->sp.two_level ? b.take<uint32_t>(o->sp.nchunks * 256) : nullptr;
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
-    o->so.overflow_n = b.take<uint32_t>(1);
+    o->so.blist = b.take<uint32_t>(o->sp.ncoarse);
+    o->so.overflow_n = b.take<uint32_t>(2);
 }
 
 struct VoteWs {
@@ -170,7 +171,8 @@ void plan_vote_ws(Bump &b, uint32_t n_reads, uint64_t capacity, VoteWs *o)
     o->so.cmat = o->sp.two_level ? b.take<uint32_t>(o->sp.nchunks * 256) : nullptr;
     o->so.cstart = b.take<uint32_t>(o->sp.ncoarse + 1);
     o->so.overflow = b.take<uint32_t>(o->sp.ncoarse);
-    o->so.overflow_n = b.take<uint32_t>(1);
+    o->so.blist = b.take<uint32_t>(o->sp.ncoarse);
+    o->so.overflow_n = b.take<uint32_t>(2);
 }
 
 struct SeedWs {

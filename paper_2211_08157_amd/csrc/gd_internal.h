@@ -153,7 +153,8 @@ struct SortWs {
     uint32_t *cmat;        // two-level: nchunks * 256 per-chunk coarse-digit counts
     uint32_t *cstart;      // ncoarse + 1: first fine bin of each coarse bucket
     uint32_t *overflow;    // ncoarse
-    uint32_t *overflow_n;  // 1
+    uint32_t *blist;       // ncoarse: buckets for the digits mode's largest bucket launch
+    uint32_t *overflow_n;  // 2: entries of overflow, then of blist
 };
 hipError_t launch_sort(const SortPlan &sp, const SortWs &w, uint64_t *keys, void *vals,
                        int val_bytes, const uint64_t *n_ptr, uint64_t capacity, hipStream_t s);

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint6
 __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
                                                        const RmiHeader *Hp, RmiLeaf *leaves)
 {
-    const RmiHeader &H = *Hp;      // read in place: per-lane segment indices would force a copy to scratch
+    const RmiHeader &H = *Hp;      // in place: per-lane segment indices would copy it to scratch
     const uint32_t L = 1u << H.log2_leaves;
     // A wave takes 63 new indices per group: lane t routes index s - 1 + t, so every lane
     // but the first finds its predecessor's leaf in the lane below (each key is routed
@@ -146,14 +146,15 @@ __global__ __launch_bounds__(kBlock) void k_rmi_ends(uint64_t n, uint32_t L, Rmi
     if (l < L) leaves[l].end = l + 1 < L ? leaves[l + 1].base : (uint32_t)n;
 }
 
-// Eight lanes per leaf (a group never straddles a wave): least-squares line through
-// ((key >> 32) - khi, position) in FP64, the lanes taking every eighth key so that a
-// group reads consecutive keys; the intercept's integer part moves into the leaf's base
-// position; then the largest under- and over-prediction over the leaf's keys with the
-// lookup's own prediction function (saturated at 65535: a larger miss only sends those
-// lookups to the binary-search fallback).  The butterfly sums add the same pairs in every
-// lane, so all eight lanes hold identical totals.
-constexpr int kFitLanes = 8;
+// Four lanes per leaf (a group never straddles a wave; leaves hold about 20 keys, so more
+// lanes would mostly idle): least-squares line through ((key >> 32) - khi, position) in
+// FP64, the lanes taking every fourth key so that a group reads consecutive keys; the
+// intercept's integer part moves into the leaf's base position; then the largest under-
+// and over-prediction over the leaf's keys with the lookup's own prediction function
+// (saturated at 65535: a larger miss only sends those lookups to the binary-search
+// fallback).  The butterfly sums add the same pairs in every lane, so all four lanes hold
+// identical totals.
+constexpr int kFitLanes = 4;
 
 __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64_t n,
                                                     const RmiHeader *Hp, RmiLeaf *leaves)
@@ -172,8 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_rmi_fit(const uint64_t *keys, uint64
     lf.err_lo = 0;
     lf.err_hi = 0;
     const uint64_t m = hi > lo ? hi - lo : 0;
-    // the group's first kHold * 8 keys stay in registers for the error pass; longer leaves
-    // read the rest twice
+    // the group's first kHold * kFitLanes keys stay in registers for the error pass;
+    // longer leaves read the rest twice
     constexpr int kHold = 8;
     unsigned long long held[kHold];
 #pragma unroll

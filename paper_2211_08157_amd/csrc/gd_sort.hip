@@ -407,13 +407,20 @@ constexpr int kCoarse = 1 << kCoarseBits;
 constexpr int kPerThread = 8;               // records per thread and step (158 KB of LDS)
 constexpr int kTile = kPerThread * kBigBlock;
 
-// One thread per coarse digit: per-chunk coarse counts -> each chunk's first slot of it.
+// One workgroup per coarse digit: per-chunk coarse counts -> each chunk's first slot of
+// it (each thread scans a run of consecutive chunks).
 __global__ __launch_bounds__(kCoarse) void k_coarse_offsets(uint32_t *cmat, uint32_t nchunks,
                                                             int sub_bits, const uint64_t *start)
 {
-    const uint32_t g = threadIdx.x;
-    uint32_t run = (uint32_t)start[(size_t)g << sub_bits];
-    for (uint32_t b = 0; b < nchunks; b++) {
+    __shared__ uint32_t sh_scan[kCoarse / kWave];
+    const uint32_t g = blockIdx.x, t = threadIdx.x;
+    const uint32_t per = (nchunks + kCoarse - 1) / kCoarse;
+    const uint32_t b0 = t * per < nchunks ? t * per : nchunks;
+    const uint32_t b1 = b0 + per < nchunks ? b0 + per : nchunks;
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; b++) sum += cmat[(size_t)b * kCoarse + g];
+    uint32_t run = (uint32_t)start[(size_t)g << sub_bits] + block_excl_sum<kCoarse>(sum, sh_scan);
+    for (uint32_t b = b0; b < b1; b++) {
         const uint32_t v = cmat[(size_t)b * kCoarse + g];
         cmat[(size_t)b * kCoarse + g] = run;
         run += v;
@@ -555,29 +562,26 @@ __global__ __launch_bounds__(kBigBlock) void k_fine_scatter(const ulonglong2 *tm
 // kBins caps them so that more workgroups share a CU; monotone in the key),
 // the bins are scanned and filled from registers, and every record is then placed by its
 // rank inside its bin, as in k_bucket_sort.  A bucket holding a long bin (many equal
-// hashes) is bitonic-sorted; one beyond the largest capacity is listed for the fallback.
-template <typename V, int kCap, int kLo, int NT, int kBins = kCap>
-__global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec,
-                                                          const uint64_t *fofs,
-                                                          const uint32_t *cstart,
-                                                          uint64_t *okeys, V *ovals,
-                                                          uint32_t *overflow,
-                                                          uint32_t *overflow_n, int last)
+// hashes) is bitonic-sorted.  A bucket larger than kCap is appended to the spill list if
+// one is given (the next size's list, or the fallback's).  Launched either over every
+// bucket (one workgroup each, those of other sizes exit at once) or, with a list, over the
+// listed buckets only (a small grid of workgroups taking entries in turn).
+template <typename V, int kCap, int kLo, int NT, int kBins>
+__device__ __forceinline__ void digit_bucket_one(uint32_t c, const ulonglong2 *trec,
+                                                 const uint64_t *fofs, const uint32_t *cstart,
+                                                 uint64_t *okeys, V *ovals, uint32_t *spill,
+                                                 uint32_t *spill_n, uint64_t *K, V *Vv,
+                                                 uint32_t *sub, uint32_t *sh_scan,
+                                                 uint64_t *sh_mm)
 {
     constexpr int kSub = kBins;                 // bins
     constexpr int kPer = kCap / NT;
-    __shared__ uint64_t K[kCap];
-    __shared__ V Vv[kCap];
-    __shared__ uint32_t sub[kSub + 1];
-    __shared__ uint32_t sh_scan[NT / kWave];
-    __shared__ uint64_t sh_mm[2 * (NT / kWave)];
-
-    const uint32_t d0 = cstart[blockIdx.x], d1 = cstart[blockIdx.x + 1];
+    const uint32_t d0 = cstart[c], d1 = cstart[c + 1];
     const uint64_t base = fofs[d0];
     const uint64_t n64 = fofs[d1] - base;
     if (n64 <= (uint64_t)kLo) return;                       // a smaller launch's bucket
     if (n64 > (uint64_t)kCap) {
-        if (last && threadIdx.x == 0) overflow[atomicAdd(overflow_n, 1u)] = blockIdx.x;
+        if (spill && threadIdx.x == 0) spill[atomicAdd(spill_n, 1u)] = c;
         return;
     }
     const int n = (int)n64;
@@ -682,6 +686,36 @@ __global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec
     }
 }
 
+// kList: the listed buckets (list, list_n) with any grid; otherwise bucket blockIdx.x.
+// (Two instantiations rather than one kernel with both paths, which would hold the
+// registers of both.)
+template <typename V, int kCap, int kLo, int NT, int kBins = kCap, bool kList = false>
+__global__ __launch_bounds__(NT) void k_digit_bucket_sort(const ulonglong2 *trec,
+                                                          const uint64_t *fofs,
+                                                          const uint32_t *cstart,
+                                                          uint64_t *okeys, V *ovals,
+                                                          const uint32_t *list,
+                                                          const uint32_t *list_n,
+                                                          uint32_t *spill, uint32_t *spill_n)
+{
+    __shared__ uint64_t K[kCap];
+    __shared__ V Vv[kCap];
+    __shared__ uint32_t sub[kBins + 1];
+    __shared__ uint32_t sh_scan[NT / kWave];
+    __shared__ uint64_t sh_mm[2 * (NT / kWave)];
+    if constexpr (!kList) {
+        digit_bucket_one<V, kCap, kLo, NT, kBins>(blockIdx.x, trec, fofs, cstart, okeys, ovals,
+                                                  spill, spill_n, K, Vv, sub, sh_scan, sh_mm);
+        return;
+    }
+    const uint32_t nl = *list_n;
+    for (uint32_t i = blockIdx.x; i < nl; i += gridDim.x) {     // workgroup-uniform
+        digit_bucket_one<V, kCap, kLo, NT, kBins>(list[i], trec, fofs, cstart, okeys, ovals,
+                                                  spill, spill_n, K, Vv, sub, sh_scan, sh_mm);
+        __syncthreads();                                        // LDS reused by the next one
+    }
+}
+
 // Fallback for coarse buckets larger than the LDS capacity: sort runs of kCap records in
 // LDS into the output, then merge pairs of runs by ranking (an element's output index is
 // its index in its own run plus the number of smaller elements in the other run),
@@ -779,7 +813,7 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
                      const uint64_t *n_ptr, uint64_t capacity, hipStream_t s)
 {
     hipError_t e;
-    if ((e = fill_u32(w.overflow_n, 0, 1, s)) != hipSuccess) return e;
+    if ((e = fill_u32(w.overflow_n, 0, 2, s)) != hipSuccess) return e;
     if (sp.digits) {
         const uint32_t D = (uint32_t)sp.nfine, nc = (uint32_t)sp.nchunks;
         const uint32_t ch = (uint32_t)sp.chunk;
@@ -797,7 +831,7 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
                   w.tot);
         if ((e = exclusive_scan_u32(w.tot, w.fofs, D, w.scan_tmp, s)) != hipSuccess) return e;
         if (sp.two_level) {
-            GD_LAUNCH(k_coarse_offsets, dim3(1), dim3(kCoarse), 0, s, w.cmat, nc, sb,
+            GD_LAUNCH(k_coarse_offsets, dim3(kCoarse), dim3(kCoarse), 0, s, w.cmat, nc, sb,
                       (const uint64_t *)w.fofs);
             GD_LAUNCH(k_coarse_scatter<V>, dim3(nc), dim3(kBigBlock), 0, s, keys, vals, n_ptr,
                       capacity, D, sb, ch, (const uint64_t *)w.cdf, (const uint32_t *)w.cmat,
@@ -835,12 +869,17 @@ hipError_t sort_impl(const SortPlan &sp, const SortWs &w, uint64_t *keys, V *val
         const ulonglong2 *tr = w.trec;
         const uint64_t *fo = w.fofs;
         const uint32_t *cs = w.cstart;
+        // the half-size launch lists the larger buckets for the largest launch, which takes
+        // them with a small grid (one workgroup per CU) instead of a workgroup per bucket
+        uint32_t *blist_n = w.overflow_n + 1;
         GD_LAUNCH((k_digit_bucket_sort<V, C / 4, 0, kBlock>), g, dim3(kBlock), 0, s, tr, fo, cs,
-                  keys, vals, w.overflow, w.overflow_n, 0);
-        GD_LAUNCH((k_digit_bucket_sort<V, C / 2, C / 4, 2 * kBlock, C / 8>), g, dim3(2 * kBlock), 0, s,
-                  tr, fo, cs, keys, vals, w.overflow, w.overflow_n, 0);
-        GD_LAUNCH((k_digit_bucket_sort<V, C, C / 2, kBigBlock>), g, dim3(kBigBlock), 0, s, tr, fo,
-                  cs, keys, vals, w.overflow, w.overflow_n, 1);
+                  keys, vals, nullptr, nullptr, nullptr, nullptr);
+        GD_LAUNCH((k_digit_bucket_sort<V, C / 2, C / 4, 2 * kBlock, C / 8>), g, dim3(2 * kBlock),
+                  0, s, tr, fo, cs, keys, vals, nullptr, nullptr, w.blist, blist_n);
+        const unsigned gbig = sp.ncoarse < 256 ? (unsigned)sp.ncoarse : 256u;
+        GD_LAUNCH((k_digit_bucket_sort<V, C, C / 2, kBigBlock, C, true>), dim3(gbig),
+                  dim3(kBigBlock), 0, s, tr, fo, cs, keys, vals, (const uint32_t *)w.blist,
+                  (const uint32_t *)blist_n, w.overflow, w.overflow_n);
     }
     else
         GD_LAUNCH(k_bucket_sort<V>, dim3((unsigned)sp.ncoarse), dim3(kBlock), 0, s,
