@@ -57,12 +57,12 @@ SORT_KERNELS = ("k_top_hist", "k_digit", "k_hist", "k_scatter", "k_bucket_sort",
 MEASURED_TRAFFIC = {
     ("k_lookup<2>", "uneven-1Gbp/10"): dict(
         summary="profiles/k_lookup_uneven-1Gbp_hbm_bytes.md",
-        src="paper_2211_08157_amd/csrc/gd_seed.hip", sha256_16="9a1f90b2215604c5",
-        bytes_per_step=37779.5e6),
+        src="paper_2211_08157_amd/csrc/gd_seed.hip", sha256_16="f85d4bd549d06727",
+        bytes_per_step=37780.4e6),
     ("k_sketch<11,0>", "uneven-1Gbp/10"): dict(
         summary="profiles/k_sketch_uneven-1Gbp_hbm_bytes.md",
         src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="ee047c9ea693f9f1",
-        bytes_per_step=3066.0e6),
+        bytes_per_step=3066.4e6),
 }
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
 SECTIONS = ("uneven", "lookups", "sketch1g", "illumina", "extras", "containment")
