@@ -104,6 +104,30 @@ def test_host_rejects_bad_arguments_before_launch():
                          dummy, None) == E_INVAL
 
 
+def test_index_workspace_size_covers_both_value_widths():
+    # the sort's partition depends on the value width (digits mode, two-level from 2^24
+    # records, or fine bins), and the workspace size must cover whichever the call uses.
+    # With the full size the host checks pass and the call reaches its first launch, which
+    # fails without a GPU (E_HIP): so this runs only where no GPU is visible.
+    import torch
+    from paper_2211_08157_amd.api import Params, OP_INDEX_BUILD, E_WORKSPACE, E_HIP
+    if torch.cuda.is_available():
+        pytest.skip("reaches a launch with dummy pointers; host-only check")
+    L = _lib()
+    s = _seqs(1, 1000)
+    p = Params(b"10", 21, 11)
+    dummy = ctypes.c_void_p(0x3000)
+    for cap in (1000, (1 << 24) + 5, 150_000_000):
+        size = L.godiet_workspace_size(OP_INDEX_BUILD, ctypes.byref(s), ctypes.byref(p), cap)
+        short = []
+        for vb in (32, 64):
+            assert L.godiet_index_build(ctypes.byref(s), ctypes.byref(p), dummy, dummy, vb, cap,
+                                        dummy, dummy, size, dummy, None) == E_HIP
+            short.append(L.godiet_index_build(ctypes.byref(s), ctypes.byref(p), dummy, dummy, vb,
+                                              cap, dummy, dummy, size - 1, dummy, None))
+        assert E_WORKSPACE in short
+
+
 def test_random_gather_host_checks():
     from paper_2211_08157_amd.api import E_INVAL
     L = _lib()
