@@ -22,19 +22,22 @@
 // (hash, val) pairs are unique, so the result does not depend on the order in which the
 // scatter's atomics land.
 //
-// Indexes of up to ~190M records with 32-bit values (~48M with 64-bit values) take a
+// Indexes of up to ~200M records with 32-bit values (~100M with 64-bit values) take a
 // cheaper partition ("digits" mode) whose digits are balanced by the data: a histogram of
 // the top 12 bits of a sample of the keys, scanned, maps a key to its approximate rank
 // (the cumulative count of its 12-bit slice plus its share of the slice, by the next 32
 // key bits, which is monotone in the key), and the digit is that rank scaled to
 // D <= 2^15 digits, so every digit holds about N / D records whatever the skew of the
-// hashes.  Digits are counted per chunk of records in LDS, turned into per-chunk digit
-// offsets by one thread per digit, and scattered with LDS atomics, so no record touches a
-// global atomic or a random global read.  Coarse buckets of whole digits (about 2,048
-// records, at most that plus one digit) are sorted in LDS: binned by their key's offset
-// from the bucket's smallest key, scaled to about two bins per record, and placed by rank
-// inside their bin (k_digit_bucket_sort, in three launches by bucket size, the largest
-// with up to 128 KB of LDS).
+// hashes.  Digits are counted per chunk of records in LDS.  Below 2^24 records they are
+// turned into per-chunk digit offsets by one thread per digit and scattered with LDS
+// atomics; from 2^24 records the records move in two coalesced passes (256 coarse digits,
+// then the fine digits inside each), staged in LDS so that every group of a step is
+// written as one run.  No record touches a global atomic or a random global read.  Coarse
+// buckets of whole digits (about 2,048 records, at most that plus one digit) are sorted
+// in LDS: binned by their key's offset from the bucket's smallest key, scaled to about
+// two bins per record, and placed by rank inside their bin (k_digit_bucket_sort, in three
+// launches by bucket size, the largest with up to 128 KB of LDS and over a device-built
+// list of its buckets).
 #include "gd_internal.h"
 
 namespace gd {
