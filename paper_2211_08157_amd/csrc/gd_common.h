@@ -194,7 +194,7 @@ __device__ __forceinline__ T wave_sum(T v)
 
 // Workgroup exclusive prefix sum over kBlock threads; returns the exclusive value and
 // writes the workgroup total to *total.  `sh` must hold kBlock / kWave elements.
-template <typename T>
+template <typename T, int NT = kBlock>
 __device__ __forceinline__ T block_excl_scan(T v, T *sh, T *total)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -204,7 +204,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T *sh, T *total)
     __syncthreads();
     T before = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; i++) {
+    for (int i = 0; i < NT / kWave; i++) {
         const T s = sh[i];
         if (i < wv) before += s;
         all += s;

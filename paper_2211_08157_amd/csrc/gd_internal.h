@@ -68,6 +68,7 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint64_t *out, size_t n, uint6
 enum ValMode : int { VAL_LOCAL32 = 0, VAL_GLOBAL32 = 1, VAL_SEQ64 = 2 };
 
 // Geometry of the sketch tiles for a given w.
+constexpr int kSkBlock = 512;   // threads per sketch tile, 16 positions each
 struct TileGeom {
     int H;   // halo k-mers on each side (multiple of 16, >= w - 1)
     int T;   // output k-mers per tile

@@ -3,8 +3,8 @@
 // Layout: a batch of sequences is first sparsified into one "patterned stream" (2-bit
 // packed, 16 bases per uint32 word, sequences back to back, boundaries pofs[]).  The
 // sketch kernel then tiles the patterned positions of the whole batch: a workgroup of
-// 256 threads owns T consecutive positions (k-mer starts) plus a halo of H positions on
-// each side, so that every window touching an owned position lies in its LDS.  A
+// kSkBlock = 512 threads, 16 positions each, owns T consecutive positions (k-mer starts)
+// plus a halo of H positions on each side, so that every window touching an owned position lies in its LDS.  A
 // position whose k-mer would cross the end of its sequence gets an "empty" hash, and a
 // window is valid only when its w k-mers lie in one sequence, so tiles may span any
 // number of sequences (reads) or cover part of one (a chromosome).
@@ -25,7 +25,7 @@ TileGeom tile_geom(int w)
     TileGeom g;
     g.H = ((w - 1 + 15) / 16) * 16;
     if (g.H == 0) g.H = 16;
-    g.T = kBlock * 16 - 2 * g.H;
+    g.T = kSkBlock * 16 - 2 * g.H;
     return g;
 }
 
@@ -197,7 +197,7 @@ __device__ __forceinline__ SeqCache seq_cache(const uint64_t *pofs, uint32_t n_s
     c.lo = lo;
     c.n = lo < n_seq ? hi - lo + 1 : 0;      // sequences lo..hi, boundaries lo..hi+1
     if (c.n + 1 > (uint32_t)kSeqCache) c.n = 0;
-    for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += kBlock) {
+    for (uint32_t i = threadIdx.x; c.n > 0 && i <= c.n; i += blockDim.x) {
         sh[i] = pofs[c.lo + i];
         if (osh) osh[i] = offs[c.lo + i];
     }
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_ascii(const uint8_t *text, uint
 
 // ---------------------------------------------------------------- sketch
 
-constexpr int kE = kBlock * 16;     // LDS positions per tile (T + 2H)
+constexpr int kE = kSkBlock * 16;   // LDS positions per tile (T + 2H)
 constexpr uint64_t kFlagA = 1ull << 62, kFlagP = 2ull << 62, kValMask = (1ull << 62) - 1;
 constexpr int kMaxRegW = 17;        // largest w handled by the register path
 
@@ -659,11 +659,11 @@ __device__ __forceinline__ uint32_t select_reg(const T (&v)[16], uint32_t selm, 
 #pragma unroll
     for (int u = 1; u < 16; u++) P[u] = min(P[u - 1], v[u]);
 #pragma unroll
-    for (int u = 0; u < W - 1; u++) ex[u * kBlock + t] = P[u];
+    for (int u = 0; u < W - 1; u++) ex[u * kSkBlock + t] = P[u];
     __syncthreads();
     T Pn[W > 1 ? W - 1 : 1];
 #pragma unroll
-    for (int u = 0; u < W - 1; u++) Pn[u] = t + 1 < kBlock ? ex[u * kBlock + t + 1] : kTop;
+    for (int u = 0; u < W - 1; u++) Pn[u] = t + 1 < kSkBlock ? ex[u * kSkBlock + t + 1] : kTop;
     __syncthreads();
     S[15] = v[15];
 #pragma unroll
@@ -703,11 +703,11 @@ __device__ __forceinline__ uint32_t select_reg(const T (&v)[16], uint32_t selm, 
 #pragma unroll
     for (int u = 14; u >= 0; u--) SM[u] = max(SM[u + 1], mw[u]);
 #pragma unroll
-    for (int u = 17 - W; u < 16; u++) ex[u * kBlock + t] = SM[u];
+    for (int u = 17 - W; u < 16; u++) ex[u * kSkBlock + t] = SM[u];
     __syncthreads();
     T Sp[W > 1 ? W - 1 : 1];
 #pragma unroll
-    for (int j = 0; j < W - 1; j++) Sp[j] = t > 0 ? ex[(17 - W + j) * kBlock + t - 1] : T(0);
+    for (int j = 0; j < W - 1; j++) Sp[j] = t > 0 ? ex[(17 - W + j) * kSkBlock + t - 1] : T(0);
     PM[0] = mw[0];
 #pragma unroll
     for (int u = 1; u < 16; u++) PM[u] = max(PM[u - 1], mw[u]);
@@ -1037,7 +1037,8 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
     // exclusive record offset of this thread, the tile's count, whether it is staged
     auto count = [&]() {
         uint32_t tot32;
-        excl = block_excl_scan<uint32_t>((uint32_t)__popc(sel), (uint32_t *)sh_scan, &tot32);
+        excl = block_excl_scan<uint32_t, kSkBlock>((uint32_t)__popc(sel), (uint32_t *)sh_scan,
+                                                   &tot32);
         total = tot32;
         staged = total * (uint64_t)(8 + vbytes) <= (uint64_t)kE * 8;     // workgroup-uniform
     };
@@ -1068,7 +1069,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
         if (staged) {
             compact();
             __syncthreads();
-            for (uint32_t i = t; i < (uint32_t)total; i += kBlock) {
+            for (uint32_t i = t; i < (uint32_t)total; i += kSkBlock) {
                 const uint64_t cur = ex[i];
                 const uint64_t prev = i > 0 ? ex[i - 1] : sh_misc[1];
                 const bool has = i > 0 || sh_misc[2] != 0;
@@ -1137,7 +1138,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 if (staged) {
                     sv64[idx] = v;
                 } else if (tile_base + idx < A.capacity) {
-                    A.keys[tile_base + idx] = ex[u * kBlock + t];
+                    A.keys[tile_base + idx] = ex[u * kSkBlock + t];
                     ((uint64_t *)A.vals)[tile_base + idx] = v;
                 }
             } else {
@@ -1147,7 +1148,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                 if (staged) {
                     sv32[idx] = v;
                 } else if (tile_base + idx < A.capacity) {
-                    A.keys[tile_base + idx] = ex[u * kBlock + t];
+                    A.keys[tile_base + idx] = ex[u * kSkBlock + t];
                     ((uint32_t *)A.vals)[tile_base + idx] = v;
                 }
             }
@@ -1209,7 +1210,7 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
     // finished before the scan's barriers.
     if (!staged) {
 #pragma unroll
-        for (int u = 0; u < 16; u++) ex[u * kBlock + t] = hv[u];
+        for (int u = 0; u < 16; u++) ex[u * kSkBlock + t] = hv[u];
     }
     __syncthreads();
     const uint64_t tile_base = sh_misc[0];
@@ -1235,12 +1236,12 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
                                ? total
                                : (tile_base < A.capacity ? A.capacity - tile_base : 0);
         if (A.val_mode == VAL_SEQ64) {
-            for (uint64_t i = t; i < n; i += kBlock) {
+            for (uint64_t i = t; i < n; i += kSkBlock) {
                 A.keys[tile_base + i] = ex[i];
                 ((uint64_t *)A.vals)[tile_base + i] = sv64[i];
             }
         } else {
-            for (uint64_t i = t; i < n; i += kBlock) {
+            for (uint64_t i = t; i < n; i += kSkBlock) {
                 A.keys[tile_base + i] = ex[i];
                 ((uint32_t *)A.vals)[tile_base + i] = sv32[i];
             }
@@ -1249,10 +1250,10 @@ __device__ __forceinline__ void sketch_tile(const SketchArgs &A, uint64_t tile, 
 }
 
 template <int W, int HK>
-__global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
+__global__ __launch_bounds__(kSkBlock) void k_sketch(SketchArgs A)
 {
     __shared__ uint64_t ex[kE];       // neighbour exchange / sliding-reduction work array
-    __shared__ uint64_t sh_scan[kBlock / kWave];
+    __shared__ uint64_t sh_scan[kSkBlock / kWave];
     __shared__ uint64_t sh_misc[3];   // tile base; key and flag of the record before the tile
     __shared__ uint32_t sh_tile;
     __shared__ uint64_t sh_pofs[kSeqCache];
@@ -1263,7 +1264,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch(SketchArgs A)
     // tiles are numbered in the order workgroups start, so every predecessor a tile looks
     // back on is already running
     if (threadIdx.x == 0) sh_tile = atomicAdd(A.tile_counter, 1u);
-    for (uint32_t i = threadIdx.x; i < A.P.x; i += kBlock) sh_ones[i] = A.P.ones[i];
+    for (uint32_t i = threadIdx.x; i < A.P.x; i += kSkBlock) sh_ones[i] = A.P.ones[i];
     __syncthreads();
     const uint64_t tile = sh_tile;
     if (tile >= n_tiles) return;
@@ -1385,21 +1386,21 @@ hipError_t launch_sketch(const Batch &b, const Pattern &P, const uint32_t *shift
     const size_t grid = tiles;
     if (hash == 0 && k == 32) {
         // splitmix64 of full 64-bit codes: the general selection path (k = 32 is rare)
-        GD_LAUNCH((k_sketch<0, 2>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
+        GD_LAUNCH((k_sketch<0, 2>), dim3((unsigned)grid), dim3(kSkBlock), 0, s, A);
         return hipGetLastError();
     }
     switch (w) {
 #define GD_W(n)                                                                             \
     case n:                                                                                 \
-        if (hash == 1) GD_LAUNCH((k_sketch<n, 1>), dim3((unsigned)grid), dim3(kBlock), 0, s, A); \
-        else GD_LAUNCH((k_sketch<n, 0>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);          \
+        if (hash == 1) GD_LAUNCH((k_sketch<n, 1>), dim3((unsigned)grid), dim3(kSkBlock), 0, s, A); \
+        else GD_LAUNCH((k_sketch<n, 0>), dim3((unsigned)grid), dim3(kSkBlock), 0, s, A);          \
         break;
         GD_W(2) GD_W(3) GD_W(4) GD_W(5) GD_W(6) GD_W(7) GD_W(8) GD_W(9) GD_W(10) GD_W(11)
         GD_W(12) GD_W(13) GD_W(14) GD_W(15) GD_W(16) GD_W(17)
 #undef GD_W
     default:
-        if (hash == 1) GD_LAUNCH((k_sketch<0, 1>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
-        else GD_LAUNCH((k_sketch<0, 0>), dim3((unsigned)grid), dim3(kBlock), 0, s, A);
+        if (hash == 1) GD_LAUNCH((k_sketch<0, 1>), dim3((unsigned)grid), dim3(kSkBlock), 0, s, A);
+        else GD_LAUNCH((k_sketch<0, 0>), dim3((unsigned)grid), dim3(kSkBlock), 0, s, A);
         break;
     }
     return hipGetLastError();

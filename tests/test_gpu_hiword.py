@@ -83,7 +83,7 @@ def place(length, spots, tie, step, seed):
 @pytest.mark.parametrize("pattern,w", [("1", 17), ("1", 17 - 1), ("10", 17)])
 def test_high_word_ties_match_oracle(gpu, tie, pattern, w):
     step = len(pattern)
-    T = 4096 - 2 * 16              # positions a tile owns when w <= 17
+    T = 512 * 16 - 2 * 16          # positions a tile owns when w <= 17 (512 lanes x 16)
     # patterned positions: inside tile 0, just before tile 1's owned range (the second
     # k-mer inside it), deep in tile 2, and as a sequence of its own
     spots_np = [100, T - 8, 2 * T + 1000]
