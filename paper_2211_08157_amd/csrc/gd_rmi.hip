@@ -10,8 +10,9 @@
 //                                  position (intercept folded in), FP32 slope, 16-bit
 //                                  error bounds
 //
-// Routing is monotone in the key (FP32 conversion, non-negative slopes, floor), so each
-// leaf owns a contiguous run of the sorted keys.  A leaf predicts
+// Routing is monotone in the key (FP32 conversion, non-negative slopes, floor, and an
+// MLP whose FP32 segments are made to agree in order at every knot), so each leaf owns
+// a contiguous run of the sorted keys.  A leaf predicts
 //     p = base + floor(slope * float((q >> 32) - khi))
 // and the answer is searched in [p - err_lo, p + err_hi + 1].  The window is accepted
 // only if keys[lo-1] < q <= keys[hi] (with the array ends as sentinels); otherwise the
@@ -25,6 +26,45 @@ namespace gd {
 namespace {
 
 // ---- training
+
+// Make the FP32 MLP root non-decreasing in x, so that routing is monotone in the key.
+// Each segment is monotone once its slope is non-negative (a fused multiply-add rounded
+// to nearest preserves order); at a knot the two segments' FP32 values may disagree, so
+// the first float above knot i must not evaluate below the knot itself: the intercept of
+// its segment is raised by the deficit (at least one float step) until it does not.
+// Knots are taken in ascending order, so a raise is seen by the next knot's check.
+// Returns false if some knot could not be fixed (the caller then uses the linear root,
+// monotone as it stands).
+__device__ bool mlp_make_monotone(RmiHeader &h)
+{
+    for (int j = 0; j <= kKnots; j++)
+        if (!(h.sb[j] >= 0.f)) h.sb[j] = 0.f;        // FP32 prefix sums of slopes >= 0
+    auto value = [&](float x) {                      // the root before scaling to leaves
+        const uint32_t j = root_segment(h, x);
+        return __builtin_fmaf(h.sb[j], x, h.sa[j]);
+    };
+    for (int i = 0; i < kKnots; i++) {
+        const float a = h.t[i];                      // knots are key * 2^-64: in [0, 1]
+        const float b = __int_as_float(__float_as_int(a) + 1);     // the next float up
+        if (!(a >= 0.f) || !(b > a)) return false;
+        const uint32_t jb = root_segment(h, b);
+        bool ok = false;
+        for (int it = 0; it < 64 && !ok; it++) {
+            const float va = value(a), vb = value(b);
+            ok = vb >= va;
+            if (ok) break;
+            // raise by the deficit; at least to the next float up
+            const float cur = h.sa[jb];
+            float up = (float)((double)cur + ((double)va - (double)vb));
+            if (!(up > cur))
+                up = cur == 0.f ? __int_as_float(1)
+                                : __int_as_float(__float_as_int(cur) + (cur > 0.f ? 1 : -1));
+            h.sa[jb] = up;
+        }
+        if (!ok || !(h.sa[jb] == h.sa[jb])) return false;
+    }
+    return true;
+}
 
 // One workgroup: root parameters from the sorted keys (knots at key quantiles; the
 // network interpolates the rank/n curve linearly between them).
@@ -66,40 +106,53 @@ __global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint6
         h.sb[0] = 0.f;
         for (int j = 1; j <= kKnots; j++) {
             h.sb[j] = __fadd_rn(h.sb[j - 1], h.c[j]);
-            h.sa[j] = __fsub_rn(h.sa[j - 1], __fmul_rn(h.c[j], h.t[j - 1]));
+            h.sa[j] = __builtin_fmaf(-h.c[j], h.t[j - 1], h.sa[j - 1]);
         }
+        if (kind == 1 && !mlp_make_monotone(h)) h.kind = 0;
     }
     *H = h;
 }
 
 // Leaf boundaries: leaf l starts at the first key routed to a leaf >= l (index n routes
-// past the last leaf), stored in its base field.  The FP32 root can step back by one leaf
-// between neighbouring keys, so a boundary may be claimed by several keys: the smallest
-// index wins (the fields start at all ones), which keeps the model independent of store
-// order.  k_rmi_ends then copies each leaf's end (the next leaf's start) into its own slope
-// field, so the fitting pass reads and rewrites only its own leaf.
+// past the last leaf), stored in its base field.  Routing is monotone in the key (the root
+// is made so in training), so the indices where the routed leaf steps up partition the
+// leaves: each leaf's start is written by exactly one lane, with a plain store (atomics
+// would go to memory, and every later load of the wave would wait for them), and every
+// leaf is written.  k_rmi_ends then copies each leaf's end (the next leaf's start) into
+// its own slope field, so the fitting pass reads and rewrites only its own leaf.
 __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
                                                        const RmiHeader *Hp, RmiLeaf *leaves)
 {
-    const RmiHeader &H = *Hp;      // in place: per-lane segment indices would copy it to scratch
-    const uint32_t L = 1u << H.log2_leaves;
+    // The header's fields are read into registers once: the leaves share the model's
+    // buffer, so a field read after a store to a leaf would be loaded again.  Lane i < 32
+    // holds knot i, lane j <= 32 segment j's intercept and slope.
+    const uint32_t kind = Hp->kind;
+    const uint32_t L = 1u << Hp->log2_leaves;
+    const float ra = Hp->a, rb = Hp->b;
+    const int lane = threadIdx.x & (kWave - 1);
+    const float knot = Hp->t[lane & (kKnots - 1)];
+    const int seg = lane <= kKnots ? lane : kKnots;
+    const float seg_a = Hp->sa[seg], seg_b = Hp->sb[seg];
+    const uint64_t gtid = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+    if (n == 0) {                         // no keys: index 0 routes past the end
+        for (uint64_t l = gtid; l < L; l += (uint64_t)gridDim.x * kBlock) leaves[l].base = 0;
+        return;
+    }
     // A wave takes 63 new indices per group: lane t routes index s - 1 + t, so every lane
     // but the first finds its predecessor's leaf in the lane below (each key is routed
     // about once instead of twice).  Indices run to n inclusive (index n routes past the
     // end, to L).  A wave loads the keys of kGroups consecutive groups before routing
-    // them, so that several loads are in flight.
+    // them, at clamped indices so that the loads need no branch and are all in flight.
     constexpr int kGroups = 4;
     constexpr uint64_t kStep = (uint64_t)(kWave - 1) * kGroups;
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t wave = (blockIdx.x * (uint64_t)kBlock + threadIdx.x) / kWave;
+    const uint64_t wave = gtid / kWave;
     const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
-    const float knot = H.t[lane & (kKnots - 1)];          // lane i < 32 holds knot i
     for (uint64_t s0 = wave * kStep; s0 <= n; s0 += waves * kStep) {   // wave-uniform
         uint64_t kvs[kGroups];
 #pragma unroll
         for (int g = 0; g < kGroups; g++) {
-            const uint64_t s = s0 + (uint64_t)g * (kWave - 1), i = s + lane - 1;
-            kvs[g] = !(lane == 0 && s == 0) && i < n ? keys[i] : 0;
+            const uint64_t i = s0 + (uint64_t)g * (kWave - 1) + lane - 1;   // wraps for s = 0
+            kvs[g] = keys[i < n ? i : n - 1];
         }
 #pragma unroll
         for (int g = 0; g < kGroups; g++) {
@@ -107,15 +160,14 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
             if (s > n) break;                            // wave-uniform
             const uint64_t i = s + lane - 1;             // s - 1 for lane 0 (wraps at s = 0)
             const bool key = !(lane == 0 && s == 0) && i < n;
-            const uint64_t kv = kvs[g];
+            const float x = key_x(kvs[g]);
             uint32_t cur = 0;
-            if (H.kind == 0) {
-                cur = route(H, kv);
+            if (kind == 0) {
+                cur = leaf_of(__builtin_fmaf(ra, x, rb), L);
             } else {
                 // the keys are sorted, so a wave's keys usually share the root's segment:
                 // it is then the number of knots below the first and the last key, which
                 // 32 lanes compare at once (route() gives the same leaves)
-                const float x = key_x(kv);
                 const uint64_t m = __ballot(key);
                 uint32_t j = 0;
                 if (m != 0) {
@@ -125,16 +177,24 @@ __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uin
                     j = (uint32_t)__popcll(__ballot(lane < kKnots && knot < x0));
                     const uint32_t j1 =
                         (uint32_t)__popcll(__ballot(lane < kKnots && knot < x1));
-                    if (j != j1) j = root_segment(H, x);  // wave-uniform test
+                    if (j != j1) {                       // wave-uniform test
+                        // per lane, as root_segment(), with knot t read from lane t
+                        j = 0;
+#pragma unroll
+                        for (int t = 0; t < kKnots; t++) {
+                            const float tk = __int_as_float(
+                                __builtin_amdgcn_readlane(__float_as_int(knot), t));
+                            j += tk < x ? 1u : 0u;
+                        }
+                    }
                 }
-                cur = leaf_of(root_on_segment(H, j, x), L);
+                cur = leaf_of(root_value(__shfl(seg_a, (int)j), __shfl(seg_b, (int)j), x, L), L);
             }
             if (!key) cur = (lane == 0 && s == 0) ? 0u : L;   // index n and past it: L
             const uint32_t prv = __shfl_up(cur, 1);
             if (lane == 0 || i > n) continue;
             const uint32_t from = i > 0 ? prv + 1 : 0;
-            for (uint32_t l = from; l <= cur && l < L; l++)
-                atomicMin(&leaves[l].base, (uint32_t)i);
+            for (uint32_t l = from; l <= cur && l < L; l++) leaves[l].base = (uint32_t)i;
         }
     }
 }
@@ -306,8 +366,6 @@ hipError_t launch_rmi_train(const uint64_t *keys, uint64_t n, int kind, uint32_t
     RmiLeaf *leaves = (RmiLeaf *)((char *)rmi + sizeof(RmiHeader));
     const uint32_t L = 1u << log2_leaves;
     GD_LAUNCH(k_rmi_root, dim3(1), dim3(kBlock), 0, s, keys, n, kind, log2_leaves, H);
-    hipError_t e = fill_u32((uint32_t *)leaves, ~0u, (size_t)L * (sizeof(RmiLeaf) / 4), s);
-    if (e != hipSuccess) return e;
     uint64_t blocks = (n + 1 + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     GD_LAUNCH(k_rmi_bounds, dim3((unsigned)blocks), dim3(kBlock), 0, s, keys, n,

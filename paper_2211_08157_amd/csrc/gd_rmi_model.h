@@ -11,7 +11,9 @@ constexpr int kKnots = 32;
 // The MLP root y = c[0] + sum_i c[i + 1] * relu(x - t[i]) is evaluated per segment: with
 // knots ascending and j of them below x, y = sa[j] + sb[j] * x, where sb[j] sums the first
 // j output weights and sa[j] = c[0] minus the same weights times their knots (prefix
-// sums in FP32, written once by the training; training and lookups route identically).
+// sums in FP32, written once by the training, which also makes the segments agree in
+// order at every knot; training and lookups evaluate sb[j] * x + sa[j] as one fused
+// multiply-add, so they route identically).
 struct RmiHeader {
     uint32_t magic, kind, log2_leaves, pad;
     uint64_t n_keys;
@@ -75,17 +77,25 @@ __device__ __forceinline__ uint32_t root_segment(const RmiHeader &H, float x)
     return j;
 }
 
+// Root value of x, in leaves, from its segment's intercept and slope: one fused
+// multiply-add (a single rounding, written out so that no compiler contraction choice can
+// make two callers differ), then the exact scaling by the power of two L.
+__device__ __forceinline__ float root_value(float sa, float sb, float x, uint32_t L)
+{
+    return __builtin_fmaf(sb, x, sa) * (float)L;
+}
+
 // Root value of x on segment j, in leaves.
 __device__ __forceinline__ float root_on_segment(const RmiHeader &H, uint32_t j, float x)
 {
-    return __fmul_rn(__fadd_rn(H.sa[j], __fmul_rn(H.sb[j], x)), (float)(1u << H.log2_leaves));
+    return root_value(H.sa[j], H.sb[j], x, 1u << H.log2_leaves);
 }
 
 __device__ __forceinline__ uint32_t route(const RmiHeader &H, uint64_t k)
 {
     const float x = key_x(k);
     const uint32_t L = 1u << H.log2_leaves;
-    const float y = H.kind == 0 ? __fadd_rn(__fmul_rn(H.a, x), H.b)
+    const float y = H.kind == 0 ? __builtin_fmaf(H.a, x, H.b)
                                 : root_on_segment(H, root_segment(H, x), x);
     return leaf_of(y, L);
 }

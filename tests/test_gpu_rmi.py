@@ -2,6 +2,8 @@
 binary search and to the oracle, for present keys, absent keys, the array ends, runs of
 equal keys, a corrupted model (errors zeroed, slopes scrambled) and a model trained on
 another index."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 import torch
@@ -65,6 +67,54 @@ def test_rmi_training_is_deterministic(gpu, ref_index, root):
     assert leaves.shape[0] == 1 << 18 and np.all(leaves[:, 1] <= ek.size)
     slope = leaves[:, 2].view(np.float32)
     assert np.all(np.isfinite(slope)) and np.all(slope >= 0)
+
+
+def round_f32(v):
+    """The float32 nearest to the rational v (ties to even), as a Python float."""
+    if v == 0:
+        return 0.0
+    sign, v = (-1 if v < 0 else 1), abs(v)
+    e = v.numerator.bit_length() - v.denominator.bit_length()
+    while v >= Fraction(2) ** (e + 1):
+        e += 1
+    while v < Fraction(2) ** e:
+        e -= 1
+    e = max(e, -126)                                  # subnormals share the least exponent
+    q = v / Fraction(2) ** (e - 23)
+    m, r = divmod(q.numerator, q.denominator)
+    if 2 * r > q.denominator or (2 * r == q.denominator and m % 2):
+        m += 1
+    return sign * m * 2.0 ** (e - 23)
+
+
+def mlp_value(blob, xs):
+    """The MLP root of a model blob before its scaling to leaves, evaluated as the kernels
+    do: segment j = number of knots below x, then sb[j] * x + sa[j] rounded once to
+    float32 (a fused multiply-add), computed exactly here."""
+    f = blob[:576].view(np.float32)
+    t, sa, sb = f[8:40], f[73:106], f[106:139]       # byte offsets 32, 292 and 424
+    j = np.sum(t[None, :] < xs[:, None], axis=1)
+    y = [round_f32(Fraction(float(sb[i])) * Fraction(float(x)) + Fraction(float(sa[i])))
+         for i, x in zip(j, xs)]
+    return np.array(y), t, sb
+
+
+@pytest.mark.parametrize("leaves", [18, 22])
+def test_rmi_mlp_root_is_monotone(gpu, ref_index, leaves):
+    # leaf starts are written by one lane each, which needs routing monotone in the key:
+    # the trained root never decreases, across every knot and between samples of [0, 1]
+    ref, offs, ek, ev, ix = ref_index
+    blob = gpu.rmi_train(ix, root="mlp", log2_leaves=leaves).rmi.cpu().numpy()
+    assert blob[4:8].view(np.uint32)[0] == 1            # the MLP root was kept
+    _, t, sb = mlp_value(blob, np.zeros(1, np.float32))
+    assert np.all(sb >= 0)
+    steps = np.arange(-4, 5, dtype=np.int32)
+    near = (t.view(np.int32)[:, None] + steps[None, :]).ravel().view(np.float32)
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([near[(near >= 0) & (near <= 1)], rng.random(20_000, np.float32),
+                         np.float32([0, 1])])
+    y, _, _ = mlp_value(blob, np.unique(xs))
+    assert np.all(np.diff(y) >= 0)
 
 
 def test_rmi_corrupted_model_falls_back(gpu, ref_index):
