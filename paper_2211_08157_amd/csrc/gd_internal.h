@@ -102,8 +102,16 @@ hipError_t launch_window_ranges(const uint64_t *pofs, uint32_t n_seq, size_t wor
 // Text to 2-bit codes and N bits (godiet_pack_ascii).
 hipError_t launch_pack_ascii(const char *text, uint64_t n, uint32_t *bases, uint16_t *nmask,
                              hipStream_t s);
+// A sparsify workgroup of kBlock threads writes kSpWords output words per thread (16 kept
+// bases each): its range of the patterned stream is kSpSpan positions.
+constexpr int kSpWords = 4;
+constexpr uint64_t kSpSpan = (uint64_t)kBlock * kSpWords * 16;
+inline size_t sparsify_blocks(size_t words)
+{
+    return (words + (size_t)kBlock * kSpWords - 1) / ((size_t)kBlock * kSpWords);
+}
 // Entries of the lohi scratch a sparsify of `words` output words needs.
-inline size_t sparsify_lohi(size_t words) { return 2 * ((words + 255) / 256) + 2; }
+inline size_t sparsify_lohi(size_t words) { return 2 * sparsify_blocks(words) + 2; }
 
 struct SketchOut {
     uint64_t *keys;

@@ -163,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_window_seqs(const uint64_t *pofs, ui
     window_range(pofs, n_seq, pofs[n_seq], i, stride, before, span, lohi);
 }
 
-// The ranges of the sparsify workgroups (4,096 positions each) and of the sketch tiles of
-// the same stream in one launch.
+// The ranges of the sparsify workgroups (kSpSpan positions each) and of the sketch tiles
+// of the same stream in one launch.
 __global__ __launch_bounds__(kBlock) void k_window_seqs2(const uint64_t *pofs, uint32_t n_seq,
                                                          uint64_t count_sp, uint32_t *lohi_sp,
                                                          uint64_t T, uint64_t H,
@@ -173,8 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_window_seqs2(const uint64_t *pofs, u
     const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
     const uint64_t np = pofs[n_seq];
     if (i < count_sp)
-        window_range(pofs, n_seq, np, i, (uint64_t)kBlock * 16, 0, (uint64_t)kBlock * 16 - 1,
-                     lohi_sp);
+        window_range(pofs, n_seq, np, i, kSpSpan, 0, kSpSpan - 1, lohi_sp);
     if (i < count_sk) window_range(pofs, n_seq, np, i, T, H, T + 2 * H + 48, lohi_sk);
 }
 
@@ -259,7 +258,17 @@ __device__ __forceinline__ uint32_t phase1(const Pattern &P, uint32_t a)
     return v >= P.p ? v - P.p : v;
 }
 
-// One thread per output word: gathers the 16 kept bases [16q, 16q+16) of the batch.
+// Input bases o, o + 2, .., o + 30 (every other base of the 32 from o) as one word, from
+// the three input words from o >> 4: one funnel shift and a bit unzip.
+__device__ __forceinline__ uint32_t unzip_run(uint32_t W0, uint32_t W1, uint32_t W2, uint64_t o)
+{
+    const int sh = 2 * (int)(o & 15);
+    const uint32_t lo = __builtin_amdgcn_alignbit(W1, W0, sh);
+    const uint32_t hi = __builtin_amdgcn_alignbit(W2, W1, sh);
+    return unzip_even(((uint64_t)hi << 32) | lo);
+}
+
+// The 16 kept bases [16q, 16q+16) of the batch as one word (q below the stream's words).
 // nbytes = ceil(n_bases / 4), the readable size of `bases`.  Three paths:
 //  * period 2 with one kept base, word inside one sequence: the 16 kept bases are every
 //    other base of a run of 32, one funnel shift and a bit unzip;
@@ -267,19 +276,10 @@ __device__ __forceinline__ uint32_t phase1(const Pattern &P, uint32_t a)
 //    segment of the word, one 64-base window of the input in registers, the kept phases
 //    walked as the set bits of the rotated pattern (no tables, no divisions per base);
 //  * otherwise one 2-bit load per base.
-__global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const uint64_t *offsets,
-                                                     uint32_t n_seq, Pattern P,
-                                                     const uint32_t *shift, uint32_t uniform,
-                                                     const uint64_t *pofs, uint32_t *psw,
-                                                     size_t words, uint64_t nbytes, int compact,
-                                                     double inv_x, const uint32_t *lohi)
+__device__ uint32_t sparsify_word(const SeqCache &C, const uint8_t *bases, const Pattern &P,
+                                  const uint32_t *shift, uint32_t uniform, uint64_t np,
+                                  size_t q, uint64_t nbytes, int compact, double inv_x)
 {
-    __shared__ uint64_t sh_pofs[kSeqCache];
-    __shared__ uint64_t sh_offs[kSeqCache];
-    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs, offsets, sh_offs);
-    const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
-    if (q >= words) return;
-    const uint64_t np = pofs[n_seq];
     const uint64_t j0 = (uint64_t)q * 16;
     uint32_t word = 0;
     if (j0 < np) {
@@ -293,16 +293,11 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
             const uint32_t *wd = (const uint32_t *)bases;
             auto run16 = [&](uint64_t o) -> uint32_t {
                 const uint64_t g = o >> 4;
-                const uint32_t W0 = wd[g], W1 = wd[g + 1], W2 = wd[g + 2];
-                const int sh = 2 * (int)(o & 15);
-                const uint32_t lo = __builtin_amdgcn_alignbit(W1, W0, sh);
-                const uint32_t hi = __builtin_amdgcn_alignbit(W2, W1, sh);
-                return unzip_even(((uint64_t)hi << 32) | lo);
+                return unzip_run(wd[g], wd[g + 1], wd[g + 2], o);
             };
             const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + phase1(P, a);   // x == 1
             if (j0 + 16 <= end && ((o0 >> 4) + 3) * 4 <= nbytes) {
-                psw[q] = run16(o0);
-                return;
+                return run16(o0);
             }
             // a word that ends inside the next non-empty sequence (most read boundaries):
             // the first n1 bases from this sequence, the rest from the start of the next;
@@ -318,8 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
                     ((o2 >> 4) + 3) * 4 <= nbytes) {
                     const int n1 = (int)(end - j0);           // 1..15
                     const uint32_t w1 = run16(o0), w2 = run16(o2);
-                    psw[q] = (w1 & ((1u << (2 * n1)) - 1u)) | (w2 << (2 * n1));
-                    return;
+                    return (w1 & ((1u << (2 * n1)) - 1u)) | (w2 << (2 * n1));
                 }
             }
         }
@@ -381,25 +375,82 @@ __global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const
             u += seg;
         }
     }
-    psw[q] = word;
+    return word;
 }
 
-// N bits of the kept bases: one thread per 16 patterned positions (the words of
-// k_sparsify, with the same workgroups and sequence ranges), writing 16 bits.  Each base
-// is located as in the per-base path above; N runs are rare, so nothing faster is needed.
-__global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
-                                                       const uint64_t *offsets, uint32_t n_seq,
-                                                       Pattern P, const uint32_t *shift,
-                                                       uint32_t uniform, const uint64_t *pofs,
-                                                       uint16_t *pnw, size_t words, double inv_x,
-                                                       const uint32_t *lohi, uint64_t nwords)
+
+// kSpWords output words per thread, kBlock apart (so that each round of stores is
+// coalesced), in one workgroup per kSpSpan patterned positions: the workgroup's sequence
+// range is loaded once for all of them.  Under a period-2 pattern the words that lie
+// inside one sequence (all but a few per read) first compute their input offsets, then
+// issue every input load at once, so one memory round trip serves all of a thread's
+// words; the others take sparsify_word.
+__global__ __launch_bounds__(kBlock) void k_sparsify(const uint8_t *bases, const uint64_t *offsets,
+                                                     uint32_t n_seq, Pattern P,
+                                                     const uint32_t *shift, uint32_t uniform,
+                                                     const uint64_t *pofs, uint32_t *psw,
+                                                     size_t words, uint64_t nbytes, int compact,
+                                                     double inv_x, const uint32_t *lohi)
 {
     __shared__ uint64_t sh_pofs[kSeqCache];
     __shared__ uint64_t sh_offs[kSeqCache];
     const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs, offsets, sh_offs);
-    const size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x;
-    if (q >= words) return;
+    const size_t q0 = blockIdx.x * (size_t)kBlock * kSpWords + threadIdx.x;
     const uint64_t np = pofs[n_seq];
+    if (P.p == 2 && P.x == 1) {
+        uint64_t o[kSpWords];
+        bool fast[kSpWords];
+#pragma unroll
+        for (int u = 0; u < kSpWords; u++) {
+            const size_t q = q0 + (size_t)u * kBlock;
+            const uint64_t j0 = (uint64_t)q * 16;
+            fast[u] = false;
+            o[u] = 0;
+            if (q < words && j0 < np) {
+                uint32_t s = C.find(j0);
+                uint64_t beg = C.at(s), end = C.at(s + 1);
+                while (j0 >= end) { s++; beg = end; end = C.at(s + 1); }
+                uint32_t a = seq_shift(shift, uniform, s);
+                if (a >= P.p) a = 0;
+                const uint64_t oo = C.orig(s) + (j0 - beg) * 2 + phase1(P, a);   // x == 1
+                fast[u] = j0 + 16 <= end && ((oo >> 4) + 3) * 4 <= nbytes;
+                o[u] = fast[u] ? oo : 0;
+            }
+        }
+        // every load in flight before the first use; a word off the fast path reads the
+        // input's first three words, which exist whenever some word is fast
+        uint32_t W[kSpWords][3];
+        const uint32_t *wd = (const uint32_t *)bases;
+        if (nbytes >= 12) {
+#pragma unroll
+            for (int u = 0; u < kSpWords; u++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) W[u][k] = wd[(o[u] >> 4) + k];
+        }
+#pragma unroll
+        for (int u = 0; u < kSpWords; u++) {
+            const size_t q = q0 + (size_t)u * kBlock;
+            if (q >= words) break;
+            psw[q] = fast[u] ? unzip_run(W[u][0], W[u][1], W[u][2], o[u])
+                             : sparsify_word(C, bases, P, shift, uniform, np, q, nbytes, compact,
+                                             inv_x);
+        }
+        return;
+    }
+    for (int u = 0; u < kSpWords; u++) {
+        const size_t q = q0 + (size_t)u * kBlock;
+        if (q >= words) break;
+        psw[q] = sparsify_word(C, bases, P, shift, uniform, np, q, nbytes, compact, inv_x);
+    }
+}
+
+// N bits of the kept bases: the 16 bits of output word q (the words of k_sparsify, with the
+// same workgroups and sequence ranges).  Each base is located as in the per-base path of
+// sparsify_word; N runs are rare, so nothing faster is needed.
+__device__ uint16_t sparsify_nword(const SeqCache &C, const uint32_t *nmask, const Pattern &P,
+                                   const uint32_t *shift, uint32_t uniform, uint64_t np,
+                                   size_t q, double inv_x, uint64_t nwords)
+{
     const uint64_t j0 = (uint64_t)q * 16;
     uint32_t bits = 0;
     if (j0 < np) {
@@ -424,8 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
             if (a >= P.p) a = 0;
             const uint64_t o0 = C.orig(s) + (j0 - beg) * 2 + phase1(P, a);
             if (j0 + 16 <= end) {
-                pnw[q] = (uint16_t)run16(o0);
-                return;
+                return (uint16_t)run16(o0);
             }
             if (j0 + 16 <= np) {
                 uint32_t s2 = s + 1;
@@ -437,8 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
                 if (j0 + 16 <= C.at(s2 + 1) && ((o0 + 30) >> 5) < nwords &&
                     ((o2 + 30) >> 5) < nwords) {
                     const int n1 = (int)(end - j0);           // 1..15
-                    pnw[q] = (uint16_t)((run16(o0) & ((1u << n1) - 1u)) | (run16(o2) << n1));
-                    return;
+                    return (uint16_t)((run16(o0) & ((1u << n1) - 1u)) | (run16(o2) << n1));
                 }
             }
         }
@@ -481,7 +530,27 @@ __global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
             u += seg;
         }
     }
-    pnw[q] = (uint16_t)bits;
+    return (uint16_t)bits;
+}
+
+
+__global__ __launch_bounds__(kBlock) void k_sparsify_n(const uint32_t *nmask,
+                                                       const uint64_t *offsets, uint32_t n_seq,
+                                                       Pattern P, const uint32_t *shift,
+                                                       uint32_t uniform, const uint64_t *pofs,
+                                                       uint16_t *pnw, size_t words, double inv_x,
+                                                       const uint32_t *lohi, uint64_t nwords)
+{
+    __shared__ uint64_t sh_pofs[kSeqCache];
+    __shared__ uint64_t sh_offs[kSeqCache];
+    const SeqCache C = seq_cache(pofs, n_seq, lohi, blockIdx.x, sh_pofs, offsets, sh_offs);
+    const size_t q0 = blockIdx.x * (size_t)kBlock * kSpWords + threadIdx.x;
+    const uint64_t np = pofs[n_seq];
+    for (int u = 0; u < kSpWords; u++) {
+        const size_t q = q0 + (size_t)u * kBlock;
+        if (q >= words) break;
+        pnw[q] = sparsify_nword(C, nmask, P, shift, uniform, np, q, inv_x, nwords);
+    }
 }
 
 // Code of one character (4 = N).
@@ -1295,7 +1364,7 @@ hipError_t launch_window_ranges(const uint64_t *pofs, uint32_t n_seq, size_t wor
                                 uint64_t np_bound, int w, uint32_t *lohi_sp, uint32_t *lohi_sk,
                                 hipStream_t s)
 {
-    const size_t blocks = (words + kBlock - 1) / kBlock;
+    const size_t blocks = sparsify_blocks(words);
     const TileGeom g = tile_geom(w);
     const size_t tiles = sketch_tiles_bound(np_bound, w);
     const size_t count = blocks > tiles ? blocks : tiles;
@@ -1310,12 +1379,11 @@ hipError_t launch_sparsify(const Batch &b, const Pattern &P, const uint32_t *shi
                            uint32_t *pnw, size_t words, uint32_t *lohi, bool ranges_ready,
                            hipStream_t s)
 {
-    const size_t blocks = (words + kBlock - 1) / kBlock;
+    const size_t blocks = sparsify_blocks(words);
     if (blocks == 0) return hipSuccess;
     if (!ranges_ready)
         GD_LAUNCH(k_window_seqs, dim3((unsigned)((blocks + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                  s, pofs, b.n_seq, (uint64_t)kBlock * 16, (uint64_t)0, (uint64_t)kBlock * 16 - 1,
-                  (uint64_t)blocks, lohi);
+                  s, pofs, b.n_seq, kSpSpan, (uint64_t)0, kSpSpan - 1, (uint64_t)blocks, lohi);
     // 16 consecutive kept bases lie in at most ceil(15/x) + 1 periods; with that span
     // <= 48 bases every base of a word's segment is inside a 64-base window that starts
     // at most 15 bases before the segment's first kept base
