@@ -58,11 +58,11 @@ MEASURED_TRAFFIC = {
     ("k_lookup<2>", "uneven-1Gbp/10"): dict(
         summary="profiles/k_lookup_uneven-1Gbp_hbm_bytes.md",
         src="paper_2211_08157_amd/csrc/gd_seed.hip", sha256_16="f85d4bd549d06727",
-        bytes_per_step=37771.4e6),
+        bytes_per_step=37771.8e6),
     ("k_sketch<11,0>", "uneven-1Gbp/10"): dict(
         summary="profiles/k_sketch_uneven-1Gbp_hbm_bytes.md",
-        src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="59ba477b1fb9a6f7",
-        bytes_per_step=2921.7e6),
+        src="paper_2211_08157_amd/csrc/gd_sketch.hip", sha256_16="dc3215cf367ec9ef",
+        bytes_per_step=2921.9e6),
 }
 METRIC = "reads/sec seeded (bit-exact anchors), learned-index vs binary search; sketch GB/s"
 SECTIONS = ("uneven", "lookups", "sketch1g", "illumina", "extras", "containment")
