@@ -39,18 +39,20 @@ __device__ bool mlp_make_monotone(RmiHeader &h)
 {
     for (int j = 0; j <= kKnots; j++)
         if (!(h.sb[j] >= 0.f)) h.sb[j] = 0.f;        // FP32 prefix sums of slopes >= 0
-    auto value = [&](float x) {                      // the root before scaling to leaves
-        const uint32_t j = root_segment(h, x);
-        return __builtin_fmaf(h.sb[j], x, h.sa[j]);
-    };
     for (int i = 0; i < kKnots; i++) {
         const float a = h.t[i];                      // knots are key * 2^-64: in [0, 1]
+        if (i + 1 < kKnots && h.t[i + 1] == a) continue;   // the last of equal knots checks
         const float b = __int_as_float(__float_as_int(a) + 1);     // the next float up
         if (!(a >= 0.f) || !(b > a)) return false;
-        const uint32_t jb = root_segment(h, b);
+        // the knots ascend, so a lies on segment #(t < a) (the first knot equal to a) and
+        // b, with no float between them, on segment #(t <= a) = i + 1
+        int ja = i;
+        while (ja > 0 && h.t[ja - 1] == a) ja--;
+        const int jb = i + 1;
         bool ok = false;
         for (int it = 0; it < 64 && !ok; it++) {
-            const float va = value(a), vb = value(b);
+            const float va = __builtin_fmaf(h.sb[ja], a, h.sa[ja]);
+            const float vb = __builtin_fmaf(h.sb[jb], b, h.sa[jb]);
             ok = vb >= va;
             if (ok) break;
             // raise by the deficit; at least to the next float up
