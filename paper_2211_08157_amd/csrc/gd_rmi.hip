@@ -118,10 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_rmi_root(const uint64_t *keys, uint6
 // Leaf boundaries: leaf l starts at the first key routed to a leaf >= l (index n routes
 // past the last leaf), stored in its base field.  Routing is monotone in the key (the root
 // is made so in training), so the indices where the routed leaf steps up partition the
-// leaves: each leaf's start is written by exactly one lane, with a plain store (atomics
-// would go to memory, and every later load of the wave would wait for them), and every
-// leaf is written.  k_rmi_ends then copies each leaf's end (the next leaf's start) into
-// its own slope field, so the fitting pass reads and rewrites only its own leaf.
+// leaves: each leaf's start is written by exactly one lane, with a plain store, and every
+// leaf is written (so no atomics, and no clearing of the leaves beforehand).  k_rmi_ends
+// then copies each leaf's end (the next leaf's start) into its own slope field, so the
+// fitting pass reads and rewrites only its own leaf.
 __global__ __launch_bounds__(kBlock) void k_rmi_bounds(const uint64_t *keys, uint64_t n,
                                                        const RmiHeader *Hp, RmiLeaf *leaves)
 {
