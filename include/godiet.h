@@ -347,6 +347,9 @@ godiet_status godiet_table_build(const godiet_index *index, void *table, size_t 
  * 0: linear, 1: 1->32->1 ReLU network with knots at key quantiles) routes the FP32 image
  * of a key to one of 2^log2_leaves linear leaves, each predicting the key's rank from its
  * integer offset to the leaf's first key and storing its largest under/over-prediction.
+ * Training makes the network's FP32 evaluation non-decreasing in the key (its segments
+ * are made to agree in order at every knot), so routing is monotone; should that fail,
+ * the model is built with the linear root instead and its header's root kind says 0.
  * A lookup searches only the predicted window after checking that it brackets the
  * answer, and falls back to binary search otherwise, so results equal binary search.
  * rmi: device buffer of godiet_rmi_size(log2_leaves) bytes, 64-byte aligned, written

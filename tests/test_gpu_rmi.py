@@ -56,9 +56,10 @@ def test_rmi_lookup_equals_binary_search(gpu, ref_index, root, leaves):
 
 @pytest.mark.parametrize("root", ["mlp", "linear"])
 def test_rmi_training_is_deterministic(gpu, ref_index, root):
-    # every leaf's boundaries are the first keys routed to it or past it, whatever order
-    # the claims land in: two trainings give the same bytes; every leaf's base position
-    # (its first key plus the fitted intercept) lies inside the keys
+    # every leaf's start is the first key routed to it or past it, written by the one lane
+    # where the (monotone) routing steps up to it: two trainings give the same bytes;
+    # every leaf's base position (its first key plus the fitted intercept) lies inside
+    # the keys
     ref, offs, ek, ev, ix = ref_index
     a = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
     b = gpu.rmi_train(ix, root=root, log2_leaves=18).rmi.cpu().numpy()
